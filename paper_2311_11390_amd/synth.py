@@ -1,0 +1,187 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module draws random numbers and nothing else: it holds none of the ALIF
+arithmetic, so the GPU path and the FP64 oracle can both be fed from it. All
+draws use numpy's PCG64 with an explicit seed and are returned as the exact
+float32 / uint8 arrays the GPU consumes (the oracle upcasts them).
+
+Workload shapes (see the configuration table in the design notes):
+
+* Bernoulli input spikes per step (the supplementary "Synthetic spike dataset"
+  draws a homogeneous Poisson train per sample; the workloads here fix the rate
+  per step or per channel instead).
+* Ornstein-Uhlenbeck injected current, exact discretisation
+  I[t+1] = mu + (I[t] - mu) e + sd sqrt(1 - e^2) xi,  e = exp(-DT/tau),
+  with I[0] drawn from the stationary law N(mu, sd^2).
+* Per-neuron time constants drawn uniformly, Normal(0, 1/sqrt(fan_in)) weights.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def bernoulli_spikes(g: np.random.Generator, shape, prob) -> np.ndarray:
+    """uint8 0/1 spikes; ``prob`` is a scalar or broadcasts against ``shape``."""
+    u = g.random(shape, dtype=np.float32)
+    return (u < np.asarray(prob, dtype=np.float32)).astype(np.uint8)
+
+
+def ou_current(g: np.random.Generator, B: int, T: int, N: int, dt_ms: float,
+               tau_ms: float = 5.0, mu: float = 0.8, sd: float = 0.5) -> np.ndarray:
+    """Ornstein-Uhlenbeck current [B][T][N] float32 (exact discretisation)."""
+    e = np.exp(-dt_ms / tau_ms)
+    s = sd * np.sqrt(1.0 - e * e)
+    out = np.empty((B, T, N), dtype=np.float32)
+    x = mu + sd * g.standard_normal((B, N))
+    out[:, 0, :] = x
+    chunk = 256
+    for t0 in range(1, T, chunk):
+        t1 = min(T, t0 + chunk)
+        xi = g.standard_normal((B, t1 - t0, N))
+        for k in range(t1 - t0):
+            x = mu + (x - mu) * e + s * xi[:, k, :]
+            out[:, t0 + k, :] = x
+    return out
+
+
+def normal_weights(g: np.random.Generator, n_out: int, n_in: int) -> np.ndarray:
+    """W ~ N(0, sd = 1/sqrt(n_in)), [n_out][n_in] float32."""
+    return (g.standard_normal((n_out, n_in)) / np.sqrt(n_in)).astype(np.float32)
+
+
+def uniform(g: np.random.Generator, lo: float, hi: float, n: int) -> np.ndarray:
+    return g.uniform(lo, hi, n).astype(np.float32)
+
+
+def const(v: float, n: int) -> np.ndarray:
+    return np.full(n, v, dtype=np.float32)
+
+
+@dataclass
+class LayerParams:
+    """Per-neuron ALIF parameters, float32 [N] each. ``d`` is the adaptation scalar
+    (the paper's d; the workload tables call it "beta")."""
+    tau_mem: np.ndarray
+    tau_adapt: np.ndarray
+    d: np.ndarray
+    theta0: np.ndarray
+    bias: np.ndarray | None = None
+
+
+def layer_params(g, N, tau_mem=(20.0, 20.0), tau_adapt=(200.0, 200.0), d=1.8, theta0=1.0,
+                 bias=None) -> LayerParams:
+    tm = uniform(g, *tau_mem, N) if tau_mem[0] != tau_mem[1] else const(tau_mem[0], N)
+    ta = uniform(g, *tau_adapt, N) if tau_adapt[0] != tau_adapt[1] else const(tau_adapt[0], N)
+    b = None if bias is None else uniform(g, bias[0], bias[1], N)
+    return LayerParams(tm, ta, const(d, N), const(theta0, N), b)
+
+
+# ---------------------------------------------------------------------------
+# The five workloads
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    B: int
+    T: int
+    dt: float
+    arp: float
+    sizes: list          # [n_in, n1, n2, ...]; n_in == 0 means injected current
+    inputs: dict = field(default_factory=dict)
+    layers: list = field(default_factory=list)
+    weights: list = field(default_factory=list)
+    extra: dict = field(default_factory=dict)
+
+
+def single_layer(seed=0, driven=False, B=1, T=1000) -> Workload:
+    """200 Bernoulli(0.02) channels -> 100 ALIF, DT 1 ms, ARP 2 ms, T=1000.
+
+    ``driven`` adds a bias b ~ U[1, 2] (Eq. 3's constant source) so that the layer
+    fires; without it this layer stays below threshold."""
+    g = rng(seed)
+    x = bernoulli_spikes(g, (B, T, 200), 0.02)
+    W = normal_weights(g, 100, 200)
+    lp = layer_params(g, 100, bias=(1.0, 2.0) if driven else None)
+    return Workload("single_layer_200x100" + ("_driven" if driven else ""), B, T, 1.0, 2.0,
+                    [200, 100], {"x": x}, [lp], [W])
+
+
+def shd_like_training(seed=0, driven=False, B=32, T=1000) -> Workload:
+    """700 Bernoulli channels (rate_j ~ U[0,50] Hz) -> 512 ALIF -> 20 leaky readout,
+    DT 1 ms, ARP 2 ms, per-neuron tau_m ~ U[10,30], tau_a ~ U[100,300], random labels."""
+    g = rng(seed)
+    dt = 1.0
+    rates_hz = g.uniform(0.0, 50.0, 700)
+    x = bernoulli_spikes(g, (B, T, 700), (rates_hz * dt * 1e-3).astype(np.float32))
+    W = normal_weights(g, 512, 700)
+    lp = layer_params(g, 512, tau_mem=(10.0, 30.0), tau_adapt=(100.0, 300.0),
+                      bias=(1.0, 2.0) if driven else None)
+    Wr = normal_weights(g, 20, 512)
+    labels = g.integers(0, 20, B)
+    return Workload("shd_like_700x512x20" + ("_driven" if driven else ""), B, T, dt, 2.0,
+                    [700, 512], {"x": x, "labels": labels}, [lp], [W],
+                    {"readout_W": Wr, "readout_tau": const(20.0, 20)})
+
+
+def fine_dt_fit(seed=0, B=64, N=256, T=20000, dt=0.05) -> Workload:
+    """N independent ALIF neurons driven by OU current (tau 5 ms, mean 0.8, sd 0.5),
+    DT 0.05 ms, ARP 2 ms (40-step blocks), per-neuron tau_m ~ U[10,30],
+    tau_a ~ U[100,300], d = 1.8, theta0 = 1."""
+    g = rng(seed)
+    I = ou_current(g, B, T, N, dt)
+    lp = layer_params(g, N, tau_mem=(10.0, 30.0), tau_adapt=(100.0, 300.0))
+    # perturbed parameters for the target trains of the fitting loss
+    tgt = LayerParams(
+        np.maximum(lp.tau_mem * (1 + 0.1 * g.standard_normal(N)), 1e-3).astype(np.float32),
+        np.maximum(lp.tau_adapt * (1 + 0.1 * g.standard_normal(N)), 1e-3).astype(np.float32),
+        np.maximum(lp.d * (1 + 0.1 * g.standard_normal(N)), 0.0).astype(np.float32),
+        np.maximum(lp.theta0 * (1 + 0.05 * g.standard_normal(N)), 1e-3).astype(np.float32))
+    return Workload(f"fine_dt_fit_B{B}_N{N}_T{T}_dt{dt}", B, T, dt, 2.0, [0, N], {"I": I},
+                    [lp], [], {"target_params": tgt, "sigma_steps": 2.0 / dt})
+
+
+def three_layer(seed=0, driven=False, B=128, T=2000) -> Workload:
+    """700 -> 1024 -> 1024 -> 20 ALIF, Bernoulli 10 Hz input at DT 0.5 ms, ARP 2 ms,
+    single-layer parameters, loss = total final-layer spike count."""
+    g = rng(seed)
+    dt = 0.5
+    x = bernoulli_spikes(g, (B, T, 700), 10.0 * dt * 1e-3)
+    sizes = [700, 1024, 1024, 20]
+    Ws = [normal_weights(g, sizes[i + 1], sizes[i]) for i in range(3)]
+    lps = [layer_params(g, sizes[i + 1], bias=(1.0, 2.0) if driven else None) for i in range(3)]
+    return Workload("three_layer_700x1024x1024x20" + ("_driven" if driven else ""), B, T, dt,
+                    2.0, sizes, {"x": x}, lps, Ws)
+
+
+@dataclass
+class Request:
+    """One serving request: a single ALIF layer of N neurons over T steps fed by
+    an OU current that the server draws on the device from ``seed``."""
+    rid: int
+    arrival_s: float
+    N: int
+    T: int
+    dt: float
+    arp: float
+    seed: int
+
+
+def request_stream(seed=0, n=2000, rate_hz=200.0, n_range=(64, 2048),
+                   t_range=(500, 50000), dts=(1.0, 0.1, 0.05)) -> list:
+    """Poisson arrivals at ``rate_hz``; N ~ U{n_range}, T ~ U{t_range}, DT from ``dts``."""
+    g = rng(seed)
+    gaps = g.exponential(1.0 / rate_hz, n)
+    t = np.cumsum(gaps) - gaps[0]
+    Ns = g.integers(n_range[0], n_range[1] + 1, n)
+    Ts = g.integers(t_range[0], t_range[1] + 1, n)
+    D = g.choice(np.asarray(dts), n)
+    seeds = g.integers(1, 2**62, n)
+    return [Request(i, float(t[i]), int(Ns[i]), int(Ts[i]), float(D[i]), 2.0, int(seeds[i]))
+            for i in range(n)]
