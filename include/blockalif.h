@@ -1,0 +1,317 @@
+/*
+ * libblockalif -- block-wise ALIF simulation and surrogate-gradient training on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the "Blocks" reformulation of the adaptive leaky
+ * integrate-and-fire (ALIF) network of Taylor, King & Harper, "Addressing the
+ * speed-accuracy simulation trade-off for adaptive spiking neurons" (NeurIPS 2023,
+ * arXiv 2311.11390): time is cut into blocks of T_R steps (T_R = ARP / DT, the
+ * absolute refractory period in steps), inside which a neuron fires at most once,
+ * so that each block is integrated in parallel over its T_R steps (Section 3,
+ * "Block", Eqs. 6-9, Props. 1-2) and only the block-boundary state is carried
+ * sequentially, T / T_R times (Section 3, "Blocks", Props. 3-5). The dynamics
+ * are exactly those of the standard ALIF model (Section 2, Eqs. 1-5):
+ *
+ *   S[t]  = 1[V[t] > th[t]]                                  (Eq. 1, strict)
+ *   V[t]  = (beta V[t-1] + (1 - beta) I[t]) (1 - S[t-1])     (Eq. 2)
+ *   I~[t] = b + W x[t]                                       (Eq. 3, feedforward)
+ *   I[t]  = I~[t] if the last spike is >= T_R steps back, else 0   (Eq. 4)
+ *   th[t] = theta0 + d a[t],  a[t] = p a[t-1] + S[t-1]       (Eq. 5)
+ *
+ * with beta = exp(-DT / tau_mem), p = exp(-DT / tau_adapt) (supplementary,
+ * "Weight initialisation"), V = a = 0 and no earlier spike at t = 0. The paper's
+ * baseline threshold 1 is generalised to a per-neuron theta0. NOTE: the parameter
+ * called `d` here is the paper's adaptation scalar d; some workload descriptions
+ * call it "beta", which is NOT the membrane decay beta above.
+ *
+ * Conventions shared by every entry point:
+ *  - Status: 0 = ALIF_OK, 1 = ALIF_PENDING, negative = error. After an error,
+ *    alif_last_error() returns a message (thread-local). No C++ exception ever
+ *    crosses this boundary.
+ *  - Memory: every pointer argument is caller-owned. Pointers documented as
+ *    "device" must be device memory of the current HIP device; "host" pointers
+ *    are ordinary host memory. The library keeps no pointer after a call returns,
+ *    except where a server request says otherwise.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream). alif_forward / alif_backward and the other compute calls only
+ *    enqueue work on that stream and never synchronise the device.
+ *  - Layout: every per-step tensor is row-major [B][T][N] (batch, step, neuron),
+ *    neuron innermost, so that 64 lanes of a wavefront read 64 consecutive
+ *    neurons of one step.
+ *  - T_R = round(arp_ms / dt_ms) must be a whole number of steps (within 1e-9
+ *    relative) and 2 <= T_R <= ALIF_MAX_TR. With T_R = 1 the block model is not
+ *    the standard model (the reset of Eq. 2 already silences the step after a
+ *    spike, which a one-step block cannot express), so it is rejected.
+ *  - T need not be a multiple of T_R: the last block is zero-padded (footnote to
+ *    Section 3, "Blocks") and padded steps are never written.
+ *  - Parameter VALUES live in device memory, so they are checked on the device:
+ *    a neuron with tau_mem <= 0, tau_adapt <= 0, theta0 <= 0, d < 0 or a NaN
+ *    parameter produces unspecified outputs and sets ALIF_STATUS_BAD_PARAM in the
+ *    device status word, read with alif_device_status(). (theta0 > 0 and d >= 0
+ *    keep the threshold positive, so a reset neuron at V = 0 cannot fire during
+ *    its refractory steps -- the premise of "at most one spike per block".)
+ */
+#ifndef BLOCKALIF_H
+#define BLOCKALIF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------- */
+#define ALIF_OK            0
+#define ALIF_PENDING       1
+#define ALIF_EINVAL       (-1)  /* bad size, pointer, enum or T_R */
+#define ALIF_ENOMEM       (-2)  /* host or device allocation failed */
+#define ALIF_EHIP         (-3)  /* a HIP runtime call failed (message has the HIP error) */
+#define ALIF_EBUDGET      (-4)  /* serving: request footprint exceeds the server budget */
+#define ALIF_ENOTFOUND    (-5)  /* serving: unknown ticket */
+#define ALIF_EUNSUPPORTED (-6)  /* valid request the build does not cover (e.g. T_R too large) */
+#define ALIF_ESHUTDOWN    (-7)  /* serving: server is shutting down */
+
+#define ALIF_MAX_TR 128          /* largest block length (steps) the kernels are built for */
+
+/* device status word bits (alif_device_status) */
+#define ALIF_STATUS_BAD_PARAM 1u
+
+/* ---- enums ----------------------------------------------------------------- */
+enum alif_input_kind {
+    ALIF_INPUT_CURRENT_F32 = 0, /* input is the current I~ itself, float [B][T][N] */
+    ALIF_INPUT_SPIKES_U8   = 1, /* input is presynaptic spikes x, uint8 0/1 [B][T][n_in] */
+    ALIF_INPUT_SPIKES_BF16 = 2, /* x as bfloat16 0/1 [B][T][n_in] (exact) */
+    ALIF_INPUT_SPIKES_F32  = 3  /* x as float 0/1 [B][T][n_in] */
+};
+enum alif_gemm_precision {
+    ALIF_GEMM_FP32 = 0,  /* I~ = b + W x with FP32 MFMA (v_mfma_f32_16x16x4_f32) */
+    ALIF_GEMM_BF16 = 1   /* W and x rounded to bfloat16, FP32 accumulation (MFMA) */
+};
+enum alif_spike_dtype { ALIF_SPIKES_U8 = 0, ALIF_SPIKES_BF16 = 1, ALIF_SPIKES_F32 = 2 };
+enum alif_algo {
+    ALIF_ALGO_BLOCKS          = 0, /* the block-wise method (default) */
+    ALIF_ALGO_SEQUENTIAL      = 1, /* baseline: one thread per (b, neuron), fused loop over t */
+    ALIF_ALGO_SEQUENTIAL_STEP = 2  /* baseline: one kernel launch per time step */
+};
+enum alif_surrogate { ALIF_SG_FAST_SIGMOID = 0 }; /* dS/du = (k|u| + 1)^-2, u = V - th */
+
+/* ---- problem descriptor ------------------------------------------------------ */
+typedef struct alif_desc {
+    int32_t batch;          /* B >= 0 */
+    int32_t n_in;           /* presynaptic channels (spike input); ignored for current input */
+    int32_t n_neurons;      /* N >= 0 */
+    int32_t T;              /* steps >= 0 */
+    double  dt_ms;          /* step size DT > 0 */
+    double  arp_ms;         /* absolute refractory period; T_R = round(arp_ms / dt_ms) */
+    int32_t input_kind;     /* enum alif_input_kind */
+    int32_t gemm_precision; /* enum alif_gemm_precision (spike input only) */
+    int32_t spike_dtype;    /* enum alif_spike_dtype of the spike output */
+    int32_t algo;           /* enum alif_algo */
+    int32_t surrogate;      /* enum alif_surrogate */
+    float   sg_slope;       /* surrogate slope k (supplementary uses 10) */
+} alif_desc;
+
+/* Per-neuron parameters, device float [N] each (Eqs. 2-5). bias may be NULL (= 0). */
+typedef struct alif_params {
+    const float *tau_mem_ms;   /* > 0;  beta = exp(-DT / tau_mem) */
+    const float *tau_adapt_ms; /* > 0;  p = exp(-DT / tau_adapt) */
+    const float *d;            /* >= 0; adaptation scalar: threshold jump per spike */
+    const float *theta0;       /* > 0;  baseline threshold */
+    const float *bias;         /* b of Eq. 3, or NULL */
+} alif_params;
+
+/*
+ * Complete simulation state at a block boundary (Props. 4-5: the membrane carried
+ * into the next block, the adaptation variable and where the last block's spike
+ * fell, which fixes the next block's refractory mask, Prop. 3). Device [B][N] each.
+ * Running T steps in one call equals running it in pieces whose lengths are
+ * multiples of T_R, passing `final` of one piece as `init` of the next.
+ */
+typedef struct alif_state {
+    double  *v;   /* membrane potential at the boundary; 0 if the last block spiked */
+    double  *a;   /* adaptation a at the boundary */
+    int32_t *ts;  /* 1..T_R: step of the last block's spike, 0: none */
+} alif_state;
+
+/* ---- sizes ----------------------------------------------------------------- */
+
+/* T_R for dt/arp, or a negative status if they do not give 2 <= T_R <= ALIF_MAX_TR. */
+int alif_refractory_steps(double dt_ms, double arp_ms);
+
+/* Bytes of the block-carry buffer alif_forward writes for alif_backward:
+ * 9 bytes per (b, block, neuron) plus alignment. */
+int alif_carry_bytes(const alif_desc *desc, size_t *bytes);
+
+/* Bytes of device scratch alif_backward needs (per-(b, neuron) FP64 partial sums). */
+int alif_backward_workspace_bytes(const alif_desc *desc, size_t *bytes);
+
+/* ---- compute ----------------------------------------------------------------- */
+
+/*
+ * Decay tables (supplementary "Weight initialisation": beta = exp(-DT/tau_mem),
+ * p = exp(-DT/tau_adapt); Props. 1 and 5 use their powers). Computes in FP64
+ * and rounds once to FP32: beta_pow[n][k] = beta_n^k, p_pow[n][k] = p_n^k for
+ * k = 0..T_R. Device outputs float [N][T_R + 1], either may be NULL. The
+ * forward and backward kernels build the same tables in their prologue; this
+ * entry point exposes them for checking.
+ */
+int alif_decay_tables(const alif_desc *desc, const alif_params *prm,
+                      float *beta_pow, float *p_pow, void *stream);
+
+/*
+ * Input current of Eq. 3 (feedforward part plus bias), the dense projection
+ * I~[b][t][:] = bias + W x[b][t][:], as an MFMA GEMM on gfx950.
+ *   input   device spikes [B][T][n_in] of desc->input_kind (0/1 values)
+ *   W       device float [N][n_in]; bias device float [N] or NULL
+ *   current device float [B][T][N] output
+ * FP32 precision uses FP32 MFMA; BF16 rounds W to bfloat16 (x is exact) and
+ * accumulates in FP32.
+ */
+int alif_input_current(const alif_desc *desc, const void *input, const float *W,
+                       const float *bias, float *current, void *stream);
+
+/*
+ * Forward pass of one ALIF layer over T steps (Eqs. 1-5 computed by Blocks,
+ * Props. 1-5; or, with desc->algo, by the sequential baselines).
+ *   input    device: current float [B][T][N] (ALIF_INPUT_CURRENT_F32; the bias is
+ *            still added) or spikes [B][T][n_in] (then W is required)
+ *   W        device float [N][n_in] or NULL for current input
+ *   current  device float [B][T][N] workspace receiving b + W x for spike input
+ *            (keep it for alif_backward); must be NULL for current input
+ *   init     initial state or NULL (= zeros, no earlier spike)
+ *   final    state after step T or NULL; requires T % T_R == 0
+ *   spikes   device [B][T][N] of desc->spike_dtype (required)
+ *   v, theta device float [B][T][N] membrane / threshold traces, or NULL
+ *   carries  device buffer of alif_carry_bytes() for alif_backward, or NULL
+ * Returns ALIF_OK after enqueueing; errors are reported before any work is queued.
+ */
+int alif_forward(const alif_desc *desc, const alif_params *prm,
+                 const void *input, const float *W, float *current,
+                 const alif_state *init, alif_state *final,
+                 void *spikes, float *v, float *theta,
+                 void *carries, void *stream);
+
+/*
+ * Surrogate-gradient backward pass of alif_forward under the paper's "detached"
+ * policy (supplementary "Detaching gradients"; fast-sigmoid surrogate,
+ * supplementary "Surrogate gradient"): spikes pass gradient to the loss and to
+ * downstream layers; their uses in reset, adaptation and refractory gate are
+ * constants. Each block is recomputed from the input and its saved carry, then
+ * the reverse recurrences run over blocks in reverse order.
+ *   desc, prm, input, W, current  exactly as given to alif_forward (current:
+ *            the workspace alif_forward filled, NULL for current input)
+ *   carries  the buffer alif_forward filled (it holds every block's carry-in,
+ *            including the init state's)
+ *   grad_spikes, grad_v, grad_theta  device float [B][T][N] upstream gradients,
+ *            each nullable (= 0)
+ *   grad_current  device float [B][T][N]: gradient w.r.t. I~ (the input current);
+ *            required when grad_W or grad_input (spike input) is requested,
+ *            otherwise nullable
+ *   grad_input    spike input only: device float [B][T][n_in] = grad_current W;
+ *            nullable. (For current input the gradient is grad_current.)
+ *   grad_W        device float [N][n_in] = sum_{b,t} grad_current^T x; nullable
+ *   grad_bias, grad_tau_mem, grad_tau_adapt, grad_d, grad_theta0
+ *            device float [N], summed over the batch; each nullable
+ *   workspace device scratch of alif_backward_workspace_bytes() bytes
+ */
+int alif_backward(const alif_desc *desc, const alif_params *prm,
+                  const void *input, const float *W, const float *current,
+                  const void *carries,
+                  const float *grad_spikes, const float *grad_v, const float *grad_theta,
+                  float *grad_current, float *grad_input, float *grad_W,
+                  float *grad_bias, float *grad_tau_mem, float *grad_tau_adapt,
+                  float *grad_d, float *grad_theta0,
+                  void *workspace, void *stream);
+
+/*
+ * Leaky non-spiking readout (supplementary "Readout neurons"): the membrane of
+ * Eq. 2 without spike, reset or refractory gate, driven by I_r = W_r S, with
+ * output o[b][c] = sum_t V_r[b][t][c].
+ *   spikes  device [B][T][n_hidden] of spike_dtype (0/1)
+ *   W_r     device float [C][n_hidden]; tau_r device float [C] (> 0)
+ *   o       device float [B][C] output
+ * Backward: given go [B][C] returns grad_spikes [B][T][n_hidden] (float),
+ * grad_W_r [C][n_hidden] and grad_tau_r [C] (each nullable). workspace is device
+ * memory of alif_readout_workspace_bytes() bytes; alif_readout_forward stores the
+ * readout current and membrane there and alif_readout_backward reads them, so
+ * the same workspace must be passed to both, unchanged in between.
+ */
+int alif_readout_workspace_bytes(int32_t B, int32_t T, int32_t n_hidden, int32_t C,
+                                 size_t *bytes);
+int alif_readout_forward(int32_t B, int32_t T, int32_t n_hidden, int32_t C, double dt_ms,
+                         int32_t spike_dtype, const void *spikes, const float *W_r,
+                         const float *tau_r, float *o, void *workspace, void *stream);
+int alif_readout_backward(int32_t B, int32_t T, int32_t n_hidden, int32_t C, double dt_ms,
+                          int32_t spike_dtype, const void *spikes, const float *W_r,
+                          const float *tau_r, const float *go, float *grad_spikes,
+                          float *grad_W_r, float *grad_tau_r, void *workspace, void *stream);
+
+/* Copies the device status word (ALIF_STATUS_* bits OR-ed by kernels on the
+ * current device since the last call) to *bits and clears it. Synchronises
+ * `stream`. */
+int alif_device_status(uint32_t *bits, void *stream);
+
+/* Message for the last error on this thread (empty string if none). */
+const char *alif_last_error(void);
+
+/* ---- serving: continuous batching of independent simulations ---------------- */
+
+typedef struct alif_server alif_server;
+
+enum alif_request_input {
+    ALIF_REQ_HOST_CURRENT = 0, /* host float [T][N] current, caller-owned until done */
+    ALIF_REQ_OU           = 1  /* Ornstein-Uhlenbeck current drawn on the device */
+};
+
+/*
+ * One single-layer simulation request (forward only, batch 1). Parameters are
+ * host float [N] arrays copied at submit. The OU current is
+ *   I[0] = mu + sd z_0,  I[t+1] = mu + (I[t] - mu) e + sd sqrt(1 - e^2) z_{t+1},
+ *   e = exp(-DT / ou_tau_ms),
+ * where z_t for neuron n is the standard normal produced by Box-Muller from
+ * Philox4x32-10 (Salmon et al., SC 2011) with key = seed and counter
+ * (t, n, 0, 0): z = sqrt(-2 ln u1) cos(2 pi u2), u1 = (w0 + 1) / 2^32,
+ * u2 = w1 / 2^32 for the first two output words w0, w1 (evaluated in FP64,
+ * rounded once to float at the end of each step's update).
+ */
+typedef struct alif_request {
+    int32_t n_neurons;
+    int32_t T;
+    double  dt_ms;
+    double  arp_ms;
+    const float *tau_mem_ms, *tau_adapt_ms, *d, *theta0, *bias; /* host [N]; bias nullable */
+    int32_t input;             /* enum alif_request_input */
+    const float *host_current; /* ALIF_REQ_HOST_CURRENT: host [T][N] */
+    float ou_tau_ms, ou_mean, ou_sd;
+    uint64_t seed;
+    uint8_t *host_spikes;      /* host [T][N] output, caller-owned; written before done */
+} alif_request;
+
+typedef struct alif_result {
+    int32_t status;            /* ALIF_OK, or the request's error */
+    int32_t reserved;
+    int64_t n_spikes;
+    double  t_submit_s, t_admit_s, t_done_s; /* server clock (CLOCK_MONOTONIC), seconds */
+} alif_result;
+
+/*
+ * hbm_budget_bytes: device memory the server may hold for admitted requests;
+ * max_slots: requests simultaneously resident; device: HIP device ordinal.
+ * The server owns a scheduler thread and its own streams on `device`.
+ */
+int alif_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t device,
+                       alif_server **out);
+/* Device bytes a request holds while resident (its admission footprint). */
+int alif_request_footprint(const alif_request *req, size_t *bytes);
+/* Validates and enqueues; returns at once. ALIF_EBUDGET if it can never fit. */
+int alif_submit(alif_server *srv, const alif_request *req, uint64_t *ticket);
+/* ALIF_PENDING until the request is done; then fills *res and forgets the ticket. */
+int alif_poll(alif_server *srv, uint64_t ticket, alif_result *res);
+/* Blocks until every submitted request is done, then stops the scheduler. */
+int alif_server_destroy(alif_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BLOCKALIF_H */

@@ -1,0 +1,420 @@
+// C-ABI of libblockalif: argument validation, buffer layouts, kernel dispatch.
+// Every entry point catches its own failures and reports them as a status code
+// plus a thread-local message; nothing throws across the boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <mutex>
+#include <string>
+
+#include "../../include/blockalif.h"
+#include "alif_gemm.h"
+#include "alif_kernels.h"
+
+using namespace alif;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+int hip_fail(hipError_t e, const char *what) {
+    return fail(ALIF_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// one status word per device, allocated on first use
+std::mutex g_status_mu;
+unsigned *g_status[64] = {nullptr};
+
+int status_word(unsigned **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(ALIF_EINVAL, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_status_mu);
+    if (!g_status[dev]) {
+        unsigned *p = nullptr;
+        e = hipMalloc(&p, 256);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(status)");
+        e = hipMemset(p, 0, 256);
+        if (e != hipSuccess) return hip_fail(e, "hipMemset(status)");
+        g_status[dev] = p;
+    }
+    *out = g_status[dev];
+    return ALIF_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int tr_of(double dt, double arp) {
+    if (!(dt > 0.0) || !(arp > 0.0) || !std::isfinite(dt) || !std::isfinite(arp)) return -1;
+    const double r = arp / dt;
+    const double n = std::floor(r + 0.5);
+    if (n < 1.0 || std::fabs(r - n) > 1e-9 * n) return -1;
+    if (n > 1e9) return -1;
+    return (int)n;
+}
+
+struct Prob {
+    int B, T, N, n_in, TR, NB;
+    bool spikes_in;
+};
+
+int check_desc(const alif_desc *d, Prob *p) {
+    if (!d) return fail(ALIF_EINVAL, "desc is NULL");
+    if (d->batch < 0 || d->n_neurons < 0 || d->T < 0)
+        return fail(ALIF_EINVAL, "negative size (batch=%d n_neurons=%d T=%d)", d->batch, d->n_neurons, d->T);
+    const int TR = tr_of(d->dt_ms, d->arp_ms);
+    if (TR < 0)
+        return fail(ALIF_EINVAL, "arp_ms/dt_ms = %g/%g is not a whole number of steps", d->arp_ms, d->dt_ms);
+    if (TR < 2)
+        return fail(ALIF_EINVAL, "T_R = %d: blocks need T_R >= 2 (Eq. 2's reset already blanks the step after a spike)", TR);
+    if (TR > ALIF_MAX_TR) return fail(ALIF_EUNSUPPORTED, "T_R = %d exceeds ALIF_MAX_TR = %d", TR, ALIF_MAX_TR);
+    if (d->input_kind < ALIF_INPUT_CURRENT_F32 || d->input_kind > ALIF_INPUT_SPIKES_F32)
+        return fail(ALIF_EINVAL, "unknown input_kind %d", d->input_kind);
+    if (d->spike_dtype < ALIF_SPIKES_U8 || d->spike_dtype > ALIF_SPIKES_F32)
+        return fail(ALIF_EINVAL, "unknown spike_dtype %d", d->spike_dtype);
+    if (d->algo < ALIF_ALGO_BLOCKS || d->algo > ALIF_ALGO_SEQUENTIAL_STEP)
+        return fail(ALIF_EINVAL, "unknown algo %d", d->algo);
+    if (d->surrogate != ALIF_SG_FAST_SIGMOID) return fail(ALIF_EINVAL, "unknown surrogate %d", d->surrogate);
+    if (!(d->sg_slope >= 0.0f) || !std::isfinite(d->sg_slope)) return fail(ALIF_EINVAL, "bad sg_slope");
+    const bool sp = d->input_kind != ALIF_INPUT_CURRENT_F32;
+    if (sp) {
+        if (d->n_in <= 0) return fail(ALIF_EINVAL, "spike input needs n_in > 0 (got %d)", d->n_in);
+        if (d->gemm_precision != ALIF_GEMM_FP32 && d->gemm_precision != ALIF_GEMM_BF16)
+            return fail(ALIF_EINVAL, "unknown gemm_precision %d", d->gemm_precision);
+    }
+    const size_t TN = (size_t)d->T * (size_t)d->n_neurons;
+    if (TN * 4 >= ((size_t)1 << 31))
+        return fail(ALIF_EUNSUPPORTED, "T * n_neurons = %zu: one batch row must stay below 2 GiB of float", TN);
+    if (sp && (size_t)d->T * (size_t)d->n_in * 4 >= ((size_t)1 << 31))
+        return fail(ALIF_EUNSUPPORTED, "T * n_in too large");
+    p->B = d->batch;
+    p->T = d->T;
+    p->N = d->n_neurons;
+    p->n_in = sp ? d->n_in : 0;
+    p->TR = TR;
+    p->NB = (d->T + TR - 1) / TR;
+    p->spikes_in = sp;
+    if ((size_t)p->NB * (size_t)p->N * 8 >= ((size_t)1 << 31))
+        return fail(ALIF_EUNSUPPORTED, "T / T_R * n_neurons too large");
+    return ALIF_OK;
+}
+
+int check_params(const alif_params *prm) {
+    if (!prm) return fail(ALIF_EINVAL, "params is NULL");
+    if (!prm->tau_mem_ms || !prm->tau_adapt_ms || !prm->d || !prm->theta0)
+        return fail(ALIF_EINVAL, "tau_mem_ms, tau_adapt_ms, d and theta0 are required");
+    return ALIF_OK;
+}
+
+size_t carry_bytes(const alif_desc *d, const Prob &p) {
+    const size_t cn = (size_t)p.B * p.NB * p.N;
+    if (d->algo == ALIF_ALGO_BLOCKS) return align256(cn * 4) * 2 + align256(cn);
+    if (d->algo == ALIF_ALGO_SEQUENTIAL) return align256(cn * 8) * 2 + align256(cn * 4);
+    const size_t bn = (size_t)p.B * p.N;  // per-step launch: state only
+    return align256(bn * 8) * 2 + align256(bn * 4);
+}
+
+CarryView carry_view(void *base, const Prob &p) {
+    const size_t cn = (size_t)p.B * p.NB * p.N;
+    char *c = (char *)base;
+    CarryView v;
+    v.v = (float *)c;
+    v.a = (float *)(c + align256(cn * 4));
+    v.ts = (uint8_t *)(c + 2 * align256(cn * 4));
+    return v;
+}
+SeqCarryView seq_carry_view(void *base, size_t cn) {
+    char *c = (char *)base;
+    SeqCarryView v;
+    v.v = (double *)c;
+    v.a = (double *)(c + align256(cn * 8));
+    v.c = (int32_t *)(c + 2 * align256(cn * 8));
+    return v;
+}
+
+}  // namespace
+
+namespace alif {
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace alif
+
+extern "C" {
+
+const char *alif_last_error(void) { return g_err.c_str(); }
+
+int alif_refractory_steps(double dt_ms, double arp_ms) {
+    const int TR = tr_of(dt_ms, arp_ms);
+    if (TR < 0) return fail(ALIF_EINVAL, "arp/dt is not a whole number of steps");
+    if (TR < 2) return fail(ALIF_EINVAL, "T_R must be >= 2");
+    if (TR > ALIF_MAX_TR) return fail(ALIF_EUNSUPPORTED, "T_R > ALIF_MAX_TR");
+    return TR;
+}
+
+int alif_carry_bytes(const alif_desc *desc, size_t *bytes) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    if (!bytes) return fail(ALIF_EINVAL, "bytes is NULL");
+    *bytes = carry_bytes(desc, p);
+    return ALIF_OK;
+}
+
+int alif_backward_workspace_bytes(const alif_desc *desc, size_t *bytes) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    if (!bytes) return fail(ALIF_EINVAL, "bytes is NULL");
+    *bytes = align256((size_t)5 * p.B * p.N * sizeof(double)) +
+             (p.spikes_in ? gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.n_in) : 0);
+    return ALIF_OK;
+}
+
+int alif_decay_tables(const alif_desc *desc, const alif_params *prm, float *beta_pow, float *p_pow,
+                      void *stream) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    if (!prm || !prm->tau_mem_ms || !prm->tau_adapt_ms) return fail(ALIF_EINVAL, "tau pointers required");
+    hipError_t e = launch_decay_tables(p.N, p.TR, desc->dt_ms, prm->tau_mem_ms, prm->tau_adapt_ms,
+                                       beta_pow, p_pow, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "decay tables launch");
+    return ALIF_OK;
+}
+
+int alif_input_current(const alif_desc *desc, const void *input, const float *W, const float *bias,
+                       float *current, void *stream) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    if (!p.spikes_in) return fail(ALIF_EINVAL, "alif_input_current needs a spike input_kind");
+    if (!input || !W || !current) return fail(ALIF_EINVAL, "input, W and current are required");
+    GemmIn in;
+    in.kind = desc->input_kind;
+    in.ptr = input;
+    hipError_t e = gemm_input_current((size_t)p.B * p.T, p.N, p.n_in, in, W, bias, current,
+                                      desc->gemm_precision == ALIF_GEMM_BF16, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "input-current GEMM");
+    return ALIF_OK;
+}
+
+int alif_forward(const alif_desc *desc, const alif_params *prm, const void *input, const float *W,
+                 float *current, const alif_state *init, alif_state *final, void *spikes, float *v,
+                 float *theta, void *carries, void *stream) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    if ((rc = check_params(prm))) return rc;
+    if (!input && p.B * (size_t)p.T * p.N > 0) return fail(ALIF_EINVAL, "input is NULL");
+    if (!spikes && p.B * (size_t)p.T * p.N > 0) return fail(ALIF_EINVAL, "spikes output is NULL");
+    if (p.spikes_in) {
+        if (!W || !current) return fail(ALIF_EINVAL, "spike input needs W and the current workspace");
+    } else if (current) {
+        return fail(ALIF_EINVAL, "current workspace must be NULL for current input");
+    }
+    if (init && (!init->v || !init->a || !init->ts)) return fail(ALIF_EINVAL, "init state has NULL arrays");
+    if (final) {
+        if (!final->v || !final->a || !final->ts) return fail(ALIF_EINVAL, "final state has NULL arrays");
+        if (p.T % p.TR != 0) return fail(ALIF_EINVAL, "final state needs T %% T_R == 0 (T=%d, T_R=%d)", p.T, p.TR);
+    }
+    if (desc->algo == ALIF_ALGO_SEQUENTIAL_STEP && !carries)
+        return fail(ALIF_EINVAL, "the per-step baseline keeps its state in the carries buffer");
+    unsigned *status = nullptr;
+    if ((rc = status_word(&status))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+
+    const float *I = (const float *)input;
+    const float *bias_k = prm->bias;
+    if (p.spikes_in) {
+        GemmIn in;
+        in.kind = desc->input_kind;
+        in.ptr = input;
+        hipError_t e = gemm_input_current((size_t)p.B * p.T, p.N, p.n_in, in, W, prm->bias, current,
+                                          desc->gemm_precision == ALIF_GEMM_BF16, st);
+        if (e != hipSuccess) return hip_fail(e, "input-current GEMM");
+        I = current;
+        bias_k = nullptr;
+    }
+    if (p.B == 0 || p.N == 0 || p.T == 0) return ALIF_OK;
+
+    if (desc->algo == ALIF_ALGO_BLOCKS) {
+        FwdArgs a{};
+        a.B = p.B; a.T = p.T; a.N = p.N; a.TR = p.TR; a.NB = p.NB;
+        a.n_groups = (p.N + block_neurons_per_wg(block_config(p.TR).seg) - 1) /
+                     block_neurons_per_wg(block_config(p.TR).seg);
+        a.dt = desc->dt_ms;
+        a.I = I;
+        a.bias_k = bias_k;
+        a.tau_m = prm->tau_mem_ms; a.tau_a = prm->tau_adapt_ms; a.d = prm->d; a.theta0 = prm->theta0;
+        if (init) { a.init_v = init->v; a.init_a = init->a; a.init_ts = init->ts; }
+        if (final) { a.fin_v = final->v; a.fin_a = final->a; a.fin_ts = final->ts; }
+        a.spikes = spikes;
+        a.spike_dtype = desc->spike_dtype;
+        a.V = v;
+        a.TH = theta;
+        if (carries) a.ck = carry_view(carries, p);
+        a.status = status;
+        hipError_t e = launch_blocks_fwd(a, st);
+        if (e != hipSuccess) return hip_fail(e, "block forward launch");
+        return ALIF_OK;
+    }
+    SeqArgs a{};
+    a.B = p.B; a.T = p.T; a.N = p.N; a.TR = p.TR; a.NB = p.NB;
+    a.dt = desc->dt_ms;
+    a.slope = desc->sg_slope;
+    a.I = I;
+    a.bias_k = bias_k;
+    a.tau_m = prm->tau_mem_ms; a.tau_a = prm->tau_adapt_ms; a.d = prm->d; a.theta0 = prm->theta0;
+    if (init) { a.init_v = init->v; a.init_a = init->a; a.init_ts = init->ts; }
+    if (final) { a.fin_v = final->v; a.fin_a = final->a; a.fin_ts = final->ts; }
+    a.spikes = spikes;
+    a.spike_dtype = desc->spike_dtype;
+    a.V = v;
+    a.TH = theta;
+    a.status = status;
+    hipError_t e;
+    if (desc->algo == ALIF_ALGO_SEQUENTIAL) {
+        if (carries) a.ck = seq_carry_view(carries, (size_t)p.B * p.NB * p.N);
+        e = launch_seq_fwd(a, st);
+    } else {
+        SeqCarryView sv = seq_carry_view(carries, (size_t)p.B * p.N);
+        a.st_v = sv.v;
+        a.st_a = sv.a;
+        a.st_c = sv.c;
+        e = launch_seq_step_fwd(a, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "sequential forward launch");
+    return ALIF_OK;
+}
+
+int alif_backward(const alif_desc *desc, const alif_params *prm, const void *input, const float *W,
+                  const float *current, const void *carries, const float *grad_spikes,
+                  const float *grad_v, const float *grad_theta, float *grad_current,
+                  float *grad_input, float *grad_W, float *grad_bias, float *grad_tau_mem,
+                  float *grad_tau_adapt, float *grad_d, float *grad_theta0, void *workspace,
+                  void *stream) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    if ((rc = check_params(prm))) return rc;
+    if (desc->algo == ALIF_ALGO_SEQUENTIAL_STEP)
+        return fail(ALIF_EUNSUPPORTED, "the per-step-launch baseline is forward only");
+    if (desc->algo == ALIF_ALGO_SEQUENTIAL && p.TR > seq_bwd_max_tr())
+        return fail(ALIF_EUNSUPPORTED, "sequential backward supports T_R <= %d", seq_bwd_max_tr());
+    const size_t work = (size_t)p.B * p.T * p.N;
+    if (work == 0) {
+        // nothing to differentiate: parameter gradients are zero
+        hipStream_t st = (hipStream_t)stream;
+        float *outs[5] = {grad_bias, grad_tau_mem, grad_tau_adapt, grad_d, grad_theta0};
+        for (float *o : outs)
+            if (o && p.N > 0) {
+                hipError_t e = hipMemsetAsync(o, 0, (size_t)p.N * 4, st);
+                if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+            }
+        if (grad_W && p.spikes_in && p.N > 0) {
+            hipError_t e = hipMemsetAsync(grad_W, 0, (size_t)p.N * p.n_in * 4, st);
+            if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+        }
+        return ALIF_OK;
+    }
+    if (!input || !carries || !workspace) return fail(ALIF_EINVAL, "input, carries and workspace are required");
+    if (p.spikes_in) {
+        if (!current || !W) return fail(ALIF_EINVAL, "spike input: pass W and the current workspace alif_forward filled");
+        if ((grad_W || grad_input) && !grad_current)
+            return fail(ALIF_EINVAL, "grad_W / grad_input need the grad_current buffer");
+    } else {
+        if (grad_input || grad_W) return fail(ALIF_EINVAL, "current input: its gradient is grad_current");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const float *I = p.spikes_in ? current : (const float *)input;
+    const float *bias_k = p.spikes_in ? nullptr : prm->bias;
+    double *part = (double *)workspace;
+
+    hipError_t e;
+    if (desc->algo == ALIF_ALGO_BLOCKS) {
+        BwdArgs a{};
+        a.B = p.B; a.T = p.T; a.N = p.N; a.TR = p.TR; a.NB = p.NB;
+        const int nwg = block_neurons_per_wg(block_config(p.TR).seg);
+        a.n_groups = (p.N + nwg - 1) / nwg;
+        a.dt = desc->dt_ms;
+        a.slope = desc->sg_slope;
+        a.I = I;
+        a.bias_k = bias_k;
+        a.tau_m = prm->tau_mem_ms; a.tau_a = prm->tau_adapt_ms; a.d = prm->d; a.theta0 = prm->theta0;
+        a.ck = carry_view(const_cast<void *>(carries), p);
+        a.gS = grad_spikes; a.gV = grad_v; a.gTH = grad_theta;
+        a.gI = grad_current;
+        a.part = part;
+        e = launch_blocks_bwd(a, st);
+        if (e != hipSuccess) return hip_fail(e, "block backward launch");
+    } else {
+        SeqArgs a{};
+        a.B = p.B; a.T = p.T; a.N = p.N; a.TR = p.TR; a.NB = p.NB;
+        a.dt = desc->dt_ms;
+        a.slope = desc->sg_slope;
+        a.I = I;
+        a.bias_k = bias_k;
+        a.tau_m = prm->tau_mem_ms; a.tau_a = prm->tau_adapt_ms; a.d = prm->d; a.theta0 = prm->theta0;
+        a.ck = seq_carry_view(const_cast<void *>(carries), (size_t)p.B * p.NB * p.N);
+        a.gS = grad_spikes; a.gV = grad_v; a.gTH = grad_theta;
+        a.gI = grad_current;
+        a.part = part;
+        e = launch_seq_bwd(a, st);
+        if (e != hipSuccess) return hip_fail(e, "sequential backward launch");
+    }
+    FinalizeArgs f{};
+    f.B = p.B; f.N = p.N; f.dt = desc->dt_ms;
+    f.tau_m = prm->tau_mem_ms; f.tau_a = prm->tau_adapt_ms;
+    f.part = part;
+    f.g_tau_m = grad_tau_mem; f.g_tau_a = grad_tau_adapt; f.g_d = grad_d; f.g_theta0 = grad_theta0;
+    f.g_bias = grad_bias;
+    e = launch_finalize(f, st);
+    if (e != hipSuccess) return hip_fail(e, "gradient finalize launch");
+
+    if (p.spikes_in) {
+        GemmIn in;
+        in.kind = desc->input_kind;
+        in.ptr = input;
+        void *gws = (char *)workspace + align256((size_t)5 * p.B * p.N * sizeof(double));
+        if (grad_W) {
+            e = gemm_weight_grad((size_t)p.B * p.T, p.N, p.n_in, grad_current, in, grad_W,
+                                 desc->gemm_precision == ALIF_GEMM_BF16, gws, st);
+            if (e != hipSuccess) return hip_fail(e, "weight-gradient GEMM");
+        }
+        if (grad_input) {
+            e = gemm_input_grad((size_t)p.B * p.T, p.N, p.n_in, grad_current, W, grad_input,
+                                desc->gemm_precision == ALIF_GEMM_BF16, st);
+            if (e != hipSuccess) return hip_fail(e, "input-gradient GEMM");
+        }
+    }
+    return ALIF_OK;
+}
+
+int alif_device_status(uint32_t *bits, void *stream) {
+    if (!bits) return fail(ALIF_EINVAL, "bits is NULL");
+    unsigned *s = nullptr;
+    int rc = status_word(&s);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned h = 0;
+    hipError_t e = hipMemcpyAsync(&h, s, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemsetAsync(s, 0, sizeof(unsigned), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reading the device status word");
+    *bits = h;
+    return ALIF_OK;
+}
+
+}  // extern "C"

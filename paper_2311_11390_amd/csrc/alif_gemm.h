@@ -1,0 +1,47 @@
+// MFMA GEMMs for the dense projections around an ALIF layer (paper Eq. 3):
+// input current I~ = b + W x (forward), weight gradient dW = gI^T x and input
+// gradient dx = gI W (backward). FP32 MFMA or BF16 MFMA with FP32 accumulation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace alif {
+
+struct GemmIn {
+    int kind;         // ALIF_INPUT_SPIKES_U8 / _BF16 / _F32 (enum alif_input_kind)
+    const void *ptr;  // [M][K] row-major
+};
+
+// out[M][N] = bias[N] + x[M][K] . W[N][K]^T
+hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, const float *bias,
+                              float *out, bool bf16, hipStream_t st);
+// gW[N][K] = sum_m gI[m][n] x[m][k]   (split over m, reduced in a fixed order)
+hipError_t gemm_weight_grad(size_t M, int N, int K, const float *gI, GemmIn x, float *gW, bool bf16,
+                            void *ws, hipStream_t st);
+// gx[M][K] = gI[M][N] . W[N][K]
+hipError_t gemm_input_grad(size_t M, int N, int K, const float *gI, const float *W, float *gx,
+                           bool bf16, hipStream_t st);
+// scratch bytes gemm_weight_grad needs for its split partial sums
+size_t gemm_workspace_bytes(size_t M, int N, int K);
+
+// general C[M][N] = sum_k A(m, k) B(n, k) (+ bias[n]) for tests and readout
+struct GemmArgs {
+    long long M;
+    int N, K;
+    const void *A;
+    int a_dt;          // 0 float, 1 uint8, 2 bf16
+    long long lda;
+    int a_kc;          // 1: A(m, k) = A[m * lda + k]; 0: A(m, k) = A[k * lda + m]
+    const void *B;
+    int b_dt;
+    long long ldb;
+    int b_kc;          // 1: B(n, k) = B[n * ldb + k]; 0: B(n, k) = B[k * ldb + n]
+    float *C;
+    long long ldc;
+    const float *bias;
+    int splits;        // split of K over blockIdx.z; > 1 writes partials to C_part
+    float *C_part;     // [splits][M][N]
+};
+hipError_t gemm_launch(const GemmArgs &g, bool bf16, hipStream_t st);
+
+}  // namespace alif

@@ -1,0 +1,109 @@
+// Internal launcher interface between the C-ABI layer and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace alif {
+
+// Records a message for alif_last_error() and returns `code`.
+int set_error(int code, const char *msg);
+
+// Block-carry checkpoint layout written by the block forward for the backward:
+// three arrays [B][NB][N]: v0 (float), a0 (float), ts (uint8), 256-byte aligned.
+struct CarryView {
+    float *v;
+    float *a;
+    uint8_t *ts;
+};
+// Sequential-baseline checkpoint: [B][NB][N] of v (double), a (double), c (int32 =
+// steps since the last spike, capped at T_R).
+struct SeqCarryView {
+    double *v;
+    double *a;
+    int32_t *c;
+};
+
+struct FwdArgs {
+    int B, T, N, TR, NB, n_groups;
+    double dt;
+    const float *I;       // [B][T][N] current (without bias if bias_k != nullptr)
+    const float *bias_k;  // added in-kernel, nullable
+    const float *tau_m, *tau_a, *d, *theta0;
+    const double *init_v, *init_a;
+    const int32_t *init_ts;
+    double *fin_v, *fin_a;
+    int32_t *fin_ts;
+    void *spikes;
+    int spike_dtype;
+    float *V, *TH;
+    CarryView ck;
+    unsigned *status;
+};
+
+struct BwdArgs {
+    int B, T, N, TR, NB, n_groups;
+    double dt;
+    float slope;
+    const float *I;
+    const float *bias_k;
+    const float *tau_m, *tau_a, *d, *theta0;
+    CarryView ck;
+    const float *gS, *gV, *gTH;
+    float *gI;
+    double *part;  // [5][B][N]
+};
+
+struct SeqArgs {
+    int B, T, N, TR, NB;
+    double dt;
+    float slope;
+    const float *I;
+    const float *bias_k;
+    const float *tau_m, *tau_a, *d, *theta0;
+    const double *init_v, *init_a;
+    const int32_t *init_ts;
+    double *fin_v, *fin_a;
+    int32_t *fin_ts;
+    void *spikes;
+    int spike_dtype;
+    float *V, *TH;
+    SeqCarryView ck;
+    const float *gS, *gV, *gTH;
+    float *gI;
+    double *part;
+    unsigned *status;
+    // per-step-launch baseline state [B][N]
+    double *st_v, *st_a;
+    int32_t *st_c;
+    int step;
+};
+
+struct FinalizeArgs {
+    int B, N;
+    double dt;
+    const float *tau_m, *tau_a;
+    const double *part;  // [5][B][N]
+    float *g_tau_m, *g_tau_a, *g_d, *g_theta0, *g_bias;
+};
+
+// (SEG, L) segmentation of a block of T_R steps over lanes; same for fwd and bwd.
+struct BlockConfig {
+    int seg, len;
+};
+BlockConfig block_config(int TR);
+int block_neurons_per_wg(int seg);
+size_t block_smem_bytes(int seg, int TR);
+
+hipError_t launch_blocks_fwd(const FwdArgs &a, hipStream_t st);
+hipError_t launch_blocks_bwd(const BwdArgs &a, hipStream_t st);
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st);
+hipError_t launch_decay_tables(int N, int TR, double dt, const float *tau_m, const float *tau_a,
+                               float *beta_pow, float *p_pow, hipStream_t st);
+
+hipError_t launch_seq_fwd(const SeqArgs &a, hipStream_t st);
+hipError_t launch_seq_step_fwd(SeqArgs a, hipStream_t st);
+hipError_t launch_seq_bwd(const SeqArgs &a, hipStream_t st);
+int seq_bwd_max_tr();
+
+}  // namespace alif

@@ -1,0 +1,94 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function the
+public header declares, the ctypes struct layouts match the C compiler's, and
+host-side validation rejects bad descriptors before touching the device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2311_11390_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "blockalif.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z_0-9]*\s*\*?\s*(alif_[a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    lib = L.load()
+    names = _declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.exported_symbols())
+
+
+def test_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "blockalif.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(alif_desc), sizeof(alif_params), sizeof(alif_state),
+         sizeof(alif_request), sizeof(alif_result));
+  printf("%zu %zu %zu %zu\\n", offsetof(alif_desc, dt_ms), offsetof(alif_desc, sg_slope),
+         offsetof(alif_request, seed), offsetof(alif_request, host_spikes));
+  return 0;
+}""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    c = [int(x) for x in out]
+    py = [ctypes.sizeof(L.AlifDesc), ctypes.sizeof(L.AlifParams), ctypes.sizeof(L.AlifState),
+          ctypes.sizeof(L.AlifRequest), ctypes.sizeof(L.AlifResult),
+          L.AlifDesc.dt_ms.offset, L.AlifDesc.sg_slope.offset, L.AlifRequest.seed.offset,
+          L.AlifRequest.host_spikes.offset]
+    assert c == py
+
+
+def test_refractory_steps_rules():
+    lib = L.load()
+    assert lib.alif_refractory_steps(0.05, 2.0) == 40
+    assert lib.alif_refractory_steps(1.0, 2.0) == 2
+    assert lib.alif_refractory_steps(1.0, 1.0) == L.ALIF_EINVAL       # T_R = 1
+    assert b"T_R" in lib.alif_last_error()
+    assert lib.alif_refractory_steps(0.3, 2.0) == L.ALIF_EINVAL       # not whole
+    assert lib.alif_refractory_steps(0.01, 2.0) == L.ALIF_EUNSUPPORTED  # 200 > 128
+
+
+def _desc(**kw):
+    d = dict(batch=2, n_in=0, n_neurons=8, T=100, dt_ms=0.5, arp_ms=2.0, input_kind=0,
+             gemm_precision=0, spike_dtype=0, algo=0, surrogate=0, sg_slope=10.0)
+    d.update(kw)
+    return L.AlifDesc(**d)
+
+
+def test_sizes_and_validation_host_side():
+    lib = L.load()
+    n = ctypes.c_size_t()
+    assert lib.alif_carry_bytes(ctypes.byref(_desc()), ctypes.byref(n)) == 0
+    nb = 25
+    assert n.value >= 2 * 8 * nb * 4 * 2 + 2 * 8 * nb
+    assert lib.alif_carry_bytes(ctypes.byref(_desc(batch=-1)), ctypes.byref(n)) == L.ALIF_EINVAL
+    assert lib.alif_carry_bytes(ctypes.byref(_desc(input_kind=7)), ctypes.byref(n)) == L.ALIF_EINVAL
+    assert lib.alif_carry_bytes(ctypes.byref(_desc(input_kind=1, n_in=0)), ctypes.byref(n)) == L.ALIF_EINVAL
+    assert lib.alif_carry_bytes(ctypes.byref(_desc(algo=9)), ctypes.byref(n)) == L.ALIF_EINVAL
+    assert lib.alif_carry_bytes(ctypes.byref(_desc(T=2 ** 28, n_neurons=16)), ctypes.byref(n)) == L.ALIF_EUNSUPPORTED
+    assert lib.alif_carry_bytes(None, ctypes.byref(n)) == L.ALIF_EINVAL
+    assert lib.alif_backward_workspace_bytes(ctypes.byref(_desc()), ctypes.byref(n)) == 0
+    assert n.value >= 5 * 2 * 8 * 8
+    # forward rejects a bad descriptor before any device call
+    p = L.AlifParams(None, None, None, None, None)
+    assert lib.alif_forward(ctypes.byref(_desc(dt_ms=1.0, arp_ms=1.0)), ctypes.byref(p), None, None, None,
+                            None, None, None, None, None, None, None) == L.ALIF_EINVAL
+    assert lib.alif_forward(ctypes.byref(_desc()), ctypes.byref(p), None, None, None,
+                            None, None, None, None, None, None, None) == L.ALIF_EINVAL
+    assert b"required" in lib.alif_last_error()

@@ -1,0 +1,80 @@
+"""GPU backward parity: surrogate-gradient backward (block-wise and sequential)
+against the oracle's sequential adjoint, run on the teacher-forced oracle
+forward so that both sides differentiate the same spike train."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import driven_current, gpu_forward, log, np_, random_params
+from parity import check_forward, check_grad
+from paper_2311_11390_amd.synth import rng
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(TR, dt, algo, seed, B=2, N=67, T=None, gv=True, bias=True):
+    import torch
+
+    from paper_2311_11390_amd import alif
+    T = T or max(300, 9 * TR + TR // 3 + 1)
+    I = driven_current(seed, B, T, N)
+    prm = random_params(seed, N, tm=(2.0, 30.0), bias=(-0.3, 0.3) if bias else None)
+    g = rng(seed + 7)
+    gS = g.standard_normal((B, T, N)).astype(np.float32)
+    gV = g.standard_normal((B, T, N)).astype(np.float32) if gv else None
+    gT = g.standard_normal((B, T, N)).astype(np.float32) if gv else None
+    log(f"[bwd] algo={algo} T_R={TR} dt={dt} B={B} N={N} T={T} gv={gv}")
+    f, It, P = gpu_forward(I, prm, dt, 2.0, algo=algo, traces=False, save=True)
+    tt = lambda a: None if a is None else torch.as_tensor(a, device="cuda").contiguous()
+    out = alif.backward(f, It, P, grad_spikes=tt(gS), grad_v=tt(gV), grad_theta=tt(gT), want_grad_current=True)
+    torch.cuda.synchronize()
+    rep = check_forward(np_(f["spikes"]), I, prm, dt, 2.0)
+    orc = rep["oracle"]
+    ob = oracle.alif_backward(orc, dt, 10.0, gS=gS, gV=gV, gTH=gT)
+    res = {}
+    res["gI"] = check_grad("grad_current", np_(out["grad_current"]), ob["gI"])
+    res["tau_mem"] = check_grad("grad_tau_mem", np_(out["grad_tau_mem"]), ob["g_tau_m"])
+    res["tau_adapt"] = check_grad("grad_tau_adapt", np_(out["grad_tau_adapt"]), ob["g_tau_a"])
+    res["d"] = check_grad("grad_d", np_(out["grad_d"]), ob["g_d"])
+    res["theta0"] = check_grad("grad_theta0", np_(out["grad_theta0"]), ob["g_theta0"])
+    res["bias"] = check_grad("grad_bias", np_(out["grad_bias"]), ob["gI"].sum(axis=(0, 1)))
+    log("    " + " ".join(f"{k}:{v['rel_l2']:.1e}" for k, v in res.items()) + f" excused={rep['excused']}")
+    return res
+
+
+@pytest.mark.parametrize("TR,dt", [(2, 1.0), (3, 2.0 / 3.0), (4, 0.5), (5, 0.4), (8, 0.25), (11, 2.0 / 11),
+                                   (16, 0.125), (20, 0.1), (23, 2.0 / 23), (31, 2.0 / 31), (40, 0.05),
+                                   (47, 2.0 / 47), (64, 2.0 / 64), (80, 0.025), (128, 2.0 / 128)])
+def test_blocks_backward_matches_oracle(TR, dt):
+    _run(TR, dt, 0, 500 + TR)
+
+
+@pytest.mark.parametrize("TR,dt", [(2, 1.0), (40, 0.05)])
+def test_blocks_backward_spike_grad_only(TR, dt):
+    _run(TR, dt, 0, 600 + TR, gv=False, bias=False)
+
+
+@pytest.mark.parametrize("TR,dt", [(2, 1.0), (4, 0.5), (20, 0.1), (40, 0.05)])
+def test_sequential_backward_matches_oracle(TR, dt):
+    _run(TR, dt, 1, 700 + TR)
+
+
+def test_fine_dt_backward_ou_workload_small():
+    """OU-driven, DT = 0.05 ms, spike-only loss gradient (the fitting workload)."""
+    import torch
+
+    from paper_2311_11390_amd import alif
+    from paper_2311_11390_amd.synth import fine_dt_fit
+    w = fine_dt_fit(seed=5, B=3, N=80, T=8000)
+    lp = w.layers[0]
+    g = rng(55)
+    gS = g.standard_normal(w.inputs["I"].shape).astype(np.float32)
+    log("[bwd] fine-DT OU B=3 N=80 T=8000")
+    f, It, P = gpu_forward(w.inputs["I"], lp, w.dt, w.arp, traces=False, save=True)
+    out = alif.backward(f, It, P, grad_spikes=torch.as_tensor(gS, device="cuda"))
+    torch.cuda.synchronize()
+    rep = check_forward(np_(f["spikes"]), w.inputs["I"], lp, w.dt, w.arp)
+    ob = oracle.alif_backward(rep["oracle"], w.dt, 10.0, gS=gS, want_gI=False)
+    for k, ko in [("grad_tau_mem", "g_tau_m"), ("grad_tau_adapt", "g_tau_a"), ("grad_d", "g_d"),
+                  ("grad_theta0", "g_theta0")]:
+        check_grad(k, np_(out[k]), ob[ko])

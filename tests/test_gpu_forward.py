@@ -1,0 +1,162 @@
+"""GPU forward parity: block-wise kernels (and the sequential baselines) against
+the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from gpu_helpers import driven_current, gpu_forward, log, np_, random_params
+from parity import check_forward, coincidence
+
+pytestmark = pytest.mark.gpu
+
+# (T_R, DT) pairs covering every (segments, steps-per-segment) kernel variant
+TR_CASES = [(2, 1.0), (3, 2.0 / 3.0), (4, 0.5), (5, 0.4), (8, 0.25), (11, 2.0 / 11), (16, 0.125),
+            (20, 0.1), (23, 2.0 / 23), (31, 2.0 / 31), (40, 0.05), (47, 2.0 / 47), (64, 2.0 / 64),
+            (80, 0.025), (128, 2.0 / 128)]
+
+
+@pytest.mark.parametrize("TR,dt", TR_CASES)
+def test_blocks_forward_matches_oracle(TR, dt):
+    B, N = 2, 67                                   # ragged neuron count
+    T = 7 * TR + TR // 2 + 1                       # ragged final block
+    T = max(T, 300)
+    log(f"[fwd] T_R={TR} dt={dt} B={B} N={N} T={T}")
+    I = driven_current(TR, B, T, N)
+    prm = random_params(TR, N, tm=(2.0, 30.0))
+    f, _, _ = gpu_forward(I, prm, dt, 2.0)
+    rep = check_forward(np_(f["spikes"]), I, prm, dt, 2.0, np_(f["v"]), np_(f["theta"]))
+    log(f"    spikes={rep['n_spikes']} excused={rep['excused']} dV={rep['max_dV']:.2e} dTH={rep['max_dTH']:.2e}")
+    assert rep["n_spikes"] > 0
+
+
+@pytest.mark.parametrize("TR,dt", [(2, 1.0), (4, 0.5), (20, 0.1), (40, 0.05)])
+def test_sequential_forward_matches_oracle(TR, dt):
+    B, N, T = 2, 70, 1234
+    log(f"[seq fwd] T_R={TR}")
+    I = driven_current(100 + TR, B, T, N)
+    prm = random_params(100 + TR, N, tm=(2.0, 30.0))
+    f, _, _ = gpu_forward(I, prm, dt, 2.0, algo=1)
+    rep = check_forward(np_(f["spikes"]), I, prm, dt, 2.0, np_(f["v"]), np_(f["theta"]))
+    assert rep["n_spikes"] > 0
+
+
+def test_per_step_launch_forward_matches_oracle():
+    B, N, T = 2, 33, 400
+    log("[step fwd]")
+    I = driven_current(7, B, T, N)
+    prm = random_params(7, N, tm=(2.0, 30.0))
+    f, _, _ = gpu_forward(I, prm, 0.5, 2.0, algo=2)
+    check_forward(np_(f["spikes"]), I, prm, 0.5, 2.0, np_(f["v"]), np_(f["theta"]))
+
+
+def test_fine_dt_ou_workload_small():
+    """OU-driven neurons at DT = 0.05 ms (40-step blocks), reduced size."""
+    from paper_2311_11390_amd.synth import fine_dt_fit
+    w = fine_dt_fit(seed=3, B=4, N=96, T=6000)
+    log("[fwd] fine-DT OU workload B=4 N=96 T=6000")
+    f, _, _ = gpu_forward(w.inputs["I"], w.layers[0], w.dt, w.arp)
+    rep = check_forward(np_(f["spikes"]), w.inputs["I"], w.layers[0], w.dt, w.arp, np_(f["v"]), np_(f["theta"]))
+    log(f"    spikes={rep['n_spikes']} excused={rep['excused']} dV={rep['max_dV']:.2e}")
+    assert rep["n_spikes"] > 0
+
+
+def test_bias_and_spike_dtypes():
+    import torch
+    B, N, T, dt = 2, 130, 500, 0.25
+    I = driven_current(11, B, T, N, lo=-1.0, hi=1.0)
+    prm = random_params(11, N, tm=(2.0, 30.0), bias=(0.8, 2.0))
+    log("[fwd] bias + spike dtypes")
+    outs = []
+    for sd in (0, 1, 2):
+        f, _, _ = gpu_forward(I, prm, dt, 2.0, spike_dtype=sd)
+        outs.append(np_(f["spikes"]).astype(np.float32))
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
+    rep = check_forward(outs[0], I, prm, dt, 2.0, np_(f["v"]), np_(f["theta"]))
+    assert rep["n_spikes"] > 0
+
+
+@pytest.mark.parametrize("algo", [0, 1])
+def test_chunked_run_equals_one_shot(algo):
+    """The (V0, a, t_s) boundary state is complete: two calls equal one call."""
+    import torch
+    from paper_2311_11390_amd import alif
+    B, N, TR, dt = 3, 50, 8, 0.25
+    T1, T2 = 37 * TR, 23 * TR
+    I = driven_current(21, B, T1 + T2, N)
+    prm = random_params(21, N, tm=(2.0, 30.0))
+    log(f"[fwd] chunked algo={algo}")
+    full, _, _ = gpu_forward(I, prm, dt, 2.0, algo=algo)
+    a, _, _ = gpu_forward(np.ascontiguousarray(I[:, :T1]), prm, dt, 2.0, algo=algo, want_final=True)
+    b, _, _ = gpu_forward(np.ascontiguousarray(I[:, T1:]), prm, dt, 2.0, algo=algo, init=a["final"])
+    np.testing.assert_array_equal(np_(full["spikes"][:, :T1]), np_(a["spikes"]))
+    np.testing.assert_array_equal(np_(full["spikes"][:, T1:]), np_(b["spikes"]))
+    np.testing.assert_array_equal(np_(full["v"][:, T1:]), np_(b["v"]))
+
+
+def test_empty_and_tiny_shapes():
+    import torch
+    from paper_2311_11390_amd import alif
+    prm = random_params(5, 3)
+    log("[fwd] empty / tiny")
+    for (B, T, N) in [(0, 10, 3), (2, 0, 3), (2, 10, 0)]:
+        p = random_params(5, max(N, 1))
+        I = np.zeros((B, T, N), np.float32)
+        if N == 0:
+            continue
+        f, _, _ = gpu_forward(I, p, 0.5, 2.0)
+        assert tuple(f["spikes"].shape) == (B, T, N)
+    # T shorter than one block
+    I = driven_current(6, 2, 3, 3, lo=2.0, hi=5.0)
+    f, _, _ = gpu_forward(I, prm, 0.05, 2.0)
+    check_forward(np_(f["spikes"]), I, prm, 0.05, 2.0, np_(f["v"]), np_(f["theta"]))
+
+
+def test_bad_parameters_flagged_on_device():
+    from paper_2311_11390_amd import alif
+    N = 10
+    prm = random_params(8, N)
+    prm.theta0[3] = -1.0
+    I = driven_current(8, 1, 50, N)
+    alif.device_status()   # clear
+    gpu_forward(I, prm, 0.5, 2.0)
+    assert alif.device_status() & 1
+    prm.theta0[3] = 1.0
+    gpu_forward(I, prm, 0.5, 2.0)
+    assert alif.device_status() == 0
+
+
+def test_invalid_descriptors_rejected():
+    import torch
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif
+    prm = random_params(9, 4)
+    I = torch.zeros(1, 10, 4, device="cuda")
+    P = alif.Params.from_numpy(prm)
+    with pytest.raises(L.AlifError) as e:
+        alif.forward(I, P, 1.0, 1.0)           # T_R = 1
+    assert e.value.code == L.ALIF_EINVAL
+    with pytest.raises(L.AlifError):
+        alif.forward(I, P, 0.3, 2.0)           # not a whole number of steps
+    with pytest.raises(L.AlifError) as e:
+        alif.forward(I, P, 0.01, 2.0)          # T_R = 200 > ALIF_MAX_TR
+    assert e.value.code == L.ALIF_EUNSUPPORTED
+
+
+def test_repeat_runs_bitwise_identical():
+    B, N, T = 4, 256, 4000
+    I = driven_current(31, B, T, N)
+    prm = random_params(31, N)
+    log("[fwd] determinism")
+    a, _, _ = gpu_forward(I, prm, 0.05, 2.0)
+    b, _, _ = gpu_forward(I, prm, 0.05, 2.0)
+    np.testing.assert_array_equal(np_(a["spikes"]), np_(b["spikes"]))
+    np.testing.assert_array_equal(np_(a["v"]), np_(b["v"]))
+
+
+def test_blocks_vs_sequential_coincidence():
+    B, N, T = 2, 64, 3000
+    I = driven_current(41, B, T, N)
+    prm = random_params(41, N)
+    a, _, _ = gpu_forward(I, prm, 0.05, 2.0, algo=0)
+    b, _, _ = gpu_forward(I, prm, 0.05, 2.0, algo=1)
+    assert coincidence(np_(a["spikes"]), np_(b["spikes"])) > 0.99
