@@ -1,0 +1,639 @@
+// Block-wise ALIF kernels for gfx950: forward (integrate + first crossing +
+// persistent block-boundary carry) and surrogate-gradient backward.
+//
+// Method (paper Section 3): time is cut into blocks of T_R steps. Inside a block a
+// neuron fires at most once, so with the reset ignored the membrane is a linear
+// filter of the (refractory-masked) input (Prop. 1, Eq. 6):
+//   V~[t] = beta^t V0 + (1 - beta) sum_{j<=t} beta^(t-j) Im[j],   t = 1..T_R,
+// the threshold inside the block is theta0 + d p^(t-1) a1 (Prop. 5, written with
+// a1 = a[1] of the block so that no 1/p appears), and the block's only real
+// spike is the first crossing V~[t] > theta[t] (Eqs. 7-9, Prop. 2: phi marks the
+// first faulty spike; here it is found directly as a min-reduce). Across blocks
+// only (V0, a, t_s) are carried (Props. 3-5): the next block's first t_s - 1
+// steps are masked, V0 = 0 after a spike, and a follows Eq. 5.
+//
+// GPU mapping. The T_R steps of a block are split into SEG segments of L
+// steps. A wavefront owns one segment of 64 consecutive neurons (lane = neuron),
+// so every load and store instruction of the hot loop moves one contiguous
+// 64-neuron row of a [T][N] tensor (256 bytes of float, 64 bytes of uint8
+// spikes). A workgroup holds the SEG segment-waves of NG neuron groups; the
+// segments of a block are stitched together in LDS: each wave publishes its
+// segment's partial sum, then every wave combines the partial sums in order
+// (Horner) to get the membrane at its segment start and at the block end; the
+// block's spike step is the minimum of the segment candidates. Each wave is
+// persistent over all T / T_R blocks; the carry (V0 and a in FP64) is kept,
+// identically, by every wave of a neuron, and input loads run DEPTH blocks
+// ahead. The loop body has no data-dependent branches around memory
+// operations; blocks that follow a spike take a wave-uniform branch to the
+// masked / reset arithmetic.
+//
+// Precision. Inputs and per-step arithmetic are FP32. Decay powers beta^k, p^k
+// are evaluated in FP64 (exp(-k DT / tau)) and rounded once. The block-boundary
+// carry is FP64: the no-spike membrane is V0 <- beta^T_R V0 + U[T_R] and the
+// adaptation a <- p^T_R a + (spike term), so rounding does not accumulate over
+// the T / T_R boundaries.
+#pragma once
+#include "alif_common.h"
+#include "alif_kernels.h"
+
+namespace alif {
+
+#define ALIF_NO_SPIKE 0x7fff  // "no crossing" marker for the per-block spike step
+
+// workgroup geometry: NG groups of 64 neurons x SEG segment-waves
+template <int SEG>
+struct Geo {
+    static constexpr int NG = SEG >= 4 ? 1 : 4 / SEG;
+    static constexpr int WAVES = NG * SEG;
+    static constexpr int THREADS = 64 * WAVES;
+    static constexpr int NWG = 64 * NG;  // neurons per workgroup
+};
+
+// row length of the padded FP32 p^e table (e in [-T_R, T_R + L))
+__host__ __device__ constexpr int ptab_row(int TR, int L) { return 2 * TR + L; }
+
+// LDS layout: pd [NWG][TR] f64 | pfp [NWG][RL] f32 | exchange 6 x [SEG][NWG] f32
+template <int SEG, int L>
+size_t smem_bytes(int TR) {
+    constexpr int NWG = Geo<SEG>::NWG;
+    const size_t ex = SEG > 1 ? (size_t)6 * SEG * NWG * sizeof(float) : 0;
+    return (size_t)NWG * TR * sizeof(double) + (size_t)NWG * ptab_row(TR, L) * sizeof(float) + ex;
+}
+
+// Per-lane constants of the block recurrence. EVEN (T_R == SEG * L) means no
+// segment has padding, so the per-step padding arrays collapse to scalars.
+template <int SEG, int L, bool EVEN>
+struct Lane {
+    static constexpr int LP = EVEN ? 1 : L;
+    int w, nl, n, t0, len;
+    bool valid;
+    float beta, omb, pf, th0, dd, ob;  // ob = (1 - beta) * bias
+    double betaT, pT, pTm1;            // beta^T_R, p^T_R, p^(T_R - 1) in FP64
+    float bsL;                         // beta^t0: decay of V0 to this segment's start
+    float bL, bPart, pL, pPart;        // beta / p over a full segment and over the partial one
+    int sfull;                         // segments before sfull are full, sfull is partial, later empty
+    float bk[L];                       // beta^(k + 1)
+    float pk[L];                       // p^(k + 1)
+    float pt[L];                       // p^(t_k - 1),  t_k = t0 + k + 1
+    float ptm1;                        // p^(t0 - 1)
+    uint32_t off0;                     // byte offset of (t0, n) in a [T][N] float row block, or OOB
+    uint32_t stepN4;                   // N * 4
+    float bdec_[LP], pdec_[LP], obk_[LP], thk_[LP], PB_[LP], PP_[LP];
+    uint32_t off_[LP];
+
+    __device__ __forceinline__ float bdec(int k) const { return EVEN ? beta : bdec_[k]; }
+    __device__ __forceinline__ float pdec(int k) const { return EVEN ? pf : pdec_[k]; }
+    __device__ __forceinline__ float obk(int k) const { return EVEN ? ob : obk_[k]; }
+    __device__ __forceinline__ float thk(int k) const { return EVEN ? th0 : thk_[k]; }
+    // beta^(valid steps in [k, L)), p^(same)
+    __device__ __forceinline__ float PB(int k) const { return EVEN ? bk[L - 1 - k] : PB_[k]; }
+    __device__ __forceinline__ float PP(int k) const { return EVEN ? pk[L - 1 - k] : PP_[k]; }
+    __device__ __forceinline__ bool kvalid(int k) const { return EVEN ? true : k < len; }
+    // decay across segment s (full or last)
+    __device__ __forceinline__ float bseg(int s) const { return (EVEN || s < sfull) ? bL : (s == sfull ? bPart : 1.0f); }
+    __device__ __forceinline__ float pseg(int s) const { return (EVEN || s < sfull) ? pL : (s == sfull ? pPart : 1.0f); }
+    __device__ __forceinline__ uint32_t off(int k, uint32_t bo) const {
+        return EVEN ? off0 + (bo + (uint32_t)k * stepN4) : off_[k] + bo;
+    }
+};
+
+template <int SEG, int L, bool EVEN>
+__device__ __forceinline__ void lane_setup(Lane<SEG, L, EVEN> &c, int N, int TR, double dt, int n0,
+                                           const float *tau_m, const float *tau_a, const float *d,
+                                           const float *theta0, const float *bias) {
+    constexpr int NG = Geo<SEG>::NG;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    c.w = wave / NG;
+    c.nl = (wave % NG) * 64 + lane;
+    c.n = n0 + c.nl;
+    c.valid = c.n < N;
+    const int nc = c.valid ? c.n : N - 1;
+    const float tm = tau_m[nc], ta = tau_a[nc];
+    c.dd = d[nc];
+    c.th0 = theta0[nc];
+    const float b = bias ? bias[nc] : 0.0f;
+    const double lb = -dt / (double)tm, lp = -dt / (double)ta;
+    c.beta = (float)exp(lb);
+    c.omb = (float)(-expm1(lb));
+    c.ob = (float)(-expm1(lb) * (double)b);
+    c.pf = (float)exp(lp);
+    c.betaT = exp(lb * TR);
+    c.pT = exp(lp * TR);
+    c.pTm1 = exp(lp * (TR - 1));
+    c.t0 = c.w * L;
+    c.len = max(0, min(L, TR - c.t0));
+    c.bsL = (float)exp(lb * (double)c.t0);
+    c.sfull = TR / L;
+    const int part = TR - c.sfull * L;
+    c.bL = (float)exp(lb * (double)L);
+    c.pL = (float)exp(lp * (double)L);
+    c.bPart = (float)exp(lb * (double)part);
+    c.pPart = (float)exp(lp * (double)part);
+    c.stepN4 = (uint32_t)N * 4u;
+    c.off0 = c.valid ? (uint32_t)(c.t0 * N + c.n) * 4u : ALIF_OOB;
+#pragma unroll
+    for (int k = 0; k < L; k++) {
+        c.bk[k] = (float)exp(lb * (double)(k + 1));
+        c.pk[k] = (float)exp(lp * (double)(k + 1));
+        c.pt[k] = (float)exp(lp * (double)(c.t0 + k));
+    }
+    if constexpr (!EVEN) {
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            const bool v = k < c.len;
+            c.bdec_[k] = v ? c.beta : 1.0f;
+            c.pdec_[k] = v ? c.pf : 1.0f;
+            c.obk_[k] = v ? c.ob : 0.0f;
+            c.thk_[k] = v ? c.th0 : __int_as_float(0x7f800000);
+            const int nv = max(0, c.len - k);
+            c.PB_[k] = (float)exp(lb * (double)nv);
+            c.PP_[k] = (float)exp(lp * (double)nv);
+            c.off_[k] = (c.valid && v) ? (uint32_t)((c.t0 + k) * N + c.n) * 4u : ALIF_OOB;
+        }
+    }
+    c.ptm1 = (float)exp(lp * (double)max(0, c.t0 - 1));
+}
+
+// Tables for data-dependent exponents: pd[j][k] = p^k (FP64, k < T_R) for the
+// carry; pfp[j][T_R + e] = p^e (FP32, e >= 0; 0 for e < 0) for post-spike values.
+template <int SEG, int L>
+__device__ __forceinline__ void build_p_tables(double *pd, float *pfp, int n0, int N, int TR,
+                                               double dt, const float *tau_a) {
+    constexpr int NWG = Geo<SEG>::NWG;
+    const int RL = ptab_row(TR, L);
+    for (int idx = threadIdx.x; idx < NWG * TR; idx += blockDim.x) {
+        const int jj = idx / TR, k = idx - jj * TR;
+        pd[idx] = exp(-dt / (double)tau_a[min(n0 + jj, N - 1)] * (double)k);
+    }
+    for (int idx = threadIdx.x; idx < NWG * RL; idx += blockDim.x) {
+        const int jj = idx / RL, e = idx - jj * RL - TR;
+        pfp[idx] = e < 0 ? 0.0f : (float)exp(-dt / (double)tau_a[min(n0 + jj, N - 1)] * (double)e);
+    }
+    __syncthreads();
+}
+
+template <int SEG>
+struct Exch {  // LDS exchange arrays, each [SEG][NWG]
+    float *X;
+    int *C;
+    float *M, *R, *RA, *VL;
+};
+
+template <int SEG>
+__device__ __forceinline__ Exch<SEG> exch_at(unsigned char *base) {
+    constexpr int SZ = SEG * Geo<SEG>::NWG;
+    float *f = reinterpret_cast<float *>(base);
+    return Exch<SEG>{f, reinterpret_cast<int *>(f + SZ), f + 2 * SZ, f + 3 * SZ, f + 4 * SZ, f + 5 * SZ};
+}
+
+// The per-block integration shared by forward and backward (identical
+// arithmetic, so the backward recovers exactly the forward's spike steps).
+//   x[k]  input current at t_k, a1 = a[1] of the block, cv = V0 (float),
+//   mpre  = masked leading steps (t_s of the previous block - 1).
+// Returns the block's spike step t_s (ALIF_NO_SPIKE if none), the no-reset
+// membrane vt[k], the threshold th[k] (valid up to t_s), and U[T_R] (input part
+// of the membrane at the block end). Contains two workgroup barriers if SEG > 1.
+template <int SEG, int L, bool EVEN>
+__device__ __forceinline__ int block_integrate(const Lane<SEG, L, EVEN> &c, const Exch<SEG> &ex,
+                                               const float (&x)[L], float cv, float a1, int mpre,
+                                               float (&vt)[L], float (&th)[L], float &uTR) {
+    constexpr int NWG = Geo<SEG>::NWG;
+    float uu[L];
+    float u = 0.0f;
+    if (__any(mpre > 0)) {                 // after a spike: mask the refractory steps (Prop. 3)
+        const int kmin = mpre - c.t0;
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            const float in = k >= kmin ? fmaf(c.omb, x[k], c.obk(k)) : 0.0f;
+            u = fmaf(c.bdec(k), u, in);
+            uu[k] = u;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            u = fmaf(c.bdec(k), u, fmaf(c.omb, x[k], c.obk(k)));   // Prop. 1, local part
+            uu[k] = u;
+        }
+    }
+    float E = 0.0f;  // U at this segment's start
+    if constexpr (SEG > 1) {
+        ex.X[c.w * NWG + c.nl] = uu[L - 1];
+        __syncthreads();
+        float U = 0.0f;
+#pragma unroll
+        for (int s = 0; s < SEG; s++) {
+            const float xs = ex.X[s * NWG + c.nl];
+            E = (s == c.w) ? U : E;
+            U = fmaf(c.bseg(s), U, xs);
+        }
+        uTR = U;
+    } else {
+        uTR = uu[L - 1];
+    }
+    const float C = fmaf(c.bsL, cv, E);                              // V~ at the segment start
+    const float da1 = c.dd * a1;
+    int cand = ALIF_NO_SPIKE;
+#pragma unroll
+    for (int k = L - 1; k >= 0; k--) {
+        vt[k] = fmaf(c.bk[k], C, uu[k]);                             // V~[t_k]
+        th[k] = fmaf(c.pt[k], da1, c.thk(k));                        // Prop. 5
+        cand = vt[k] > th[k] ? c.t0 + k + 1 : cand;                  // Eq. 7, strict
+    }
+    if constexpr (SEG > 1) {                                         // Eqs. 8-9 / Prop. 2
+        ex.C[c.w * NWG + c.nl] = cand;
+        __syncthreads();
+        int ts = ALIF_NO_SPIKE;
+#pragma unroll
+        for (int s = 0; s < SEG; s++) ts = min(ts, ex.C[s * NWG + c.nl]);
+        return ts;
+    } else {
+        return cand;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+template <int SEG, int L, bool EVEN, int DEPTH, bool TRACES, int SDT>
+__global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_fwd(FwdArgs a) {
+    constexpr int NWG = Geo<SEG>::NWG;
+    constexpr uint32_t SB = SDT == 0 ? 1u : (SDT == 1 ? 2u : 4u);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int TR = a.TR, N = a.N, T = a.T, RL = ptab_row(TR, L);
+    double *pd_tab = reinterpret_cast<double *>(smem);
+    float *pf_tab = reinterpret_cast<float *>(smem + (size_t)NWG * TR * sizeof(double));
+    const Exch<SEG> ex = exch_at<SEG>(reinterpret_cast<unsigned char *>(pf_tab + (size_t)NWG * RL));
+
+    const int work = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = work / a.n_groups, g = work - b * a.n_groups;
+    const int n0 = g * NWG;
+    build_p_tables<SEG, L>(pd_tab, pf_tab, n0, N, TR, a.dt, a.tau_a);
+    Lane<SEG, L, EVEN> c;
+    lane_setup(c, N, TR, a.dt, n0, a.tau_m, a.tau_a, a.d, a.theta0, a.bias_k);
+    if (c.valid && c.w == 0 && !params_ok(a.tau_m[c.n], a.tau_a[c.n], c.dd, c.th0))
+        atomicOr(a.status, 1u);
+    const int pdrow = c.nl * TR;
+    const int pfrow = c.nl * RL + TR + c.t0;
+
+    const size_t TN = (size_t)T * N;
+    const rsrc_t rI = make_rsrc(a.I + b * TN, (uint32_t)(TN * 4));
+    const rsrc_t rS = make_rsrc((const char *)a.spikes + b * TN * SB, (uint32_t)(TN * SB));
+    const rsrc_t rV = make_rsrc(a.V ? a.V + b * TN : nullptr, a.V ? (uint32_t)(TN * 4) : 0u);
+    const rsrc_t rT = make_rsrc(a.TH ? a.TH + b * TN : nullptr, a.TH ? (uint32_t)(TN * 4) : 0u);
+    const size_t CN = (size_t)a.NB * N;
+    const bool ck = a.ck.v != nullptr;
+    const rsrc_t rCv = make_rsrc(ck ? a.ck.v + b * CN : nullptr, ck ? (uint32_t)(CN * 4) : 0u);
+    const rsrc_t rCa = make_rsrc(ck ? a.ck.a + b * CN : nullptr, ck ? (uint32_t)(CN * 4) : 0u);
+    const rsrc_t rCt = make_rsrc(ck ? a.ck.ts + b * CN : nullptr, ck ? (uint32_t)CN : 0u);
+    // checkpoint offsets (bytes); only the segment-0 wave stores
+    const uint32_t ck4 = (c.valid && c.w == 0) ? (uint32_t)c.n * 4u : ALIF_OOB;
+    const uint32_t ck1 = (c.valid && c.w == 0) ? (uint32_t)c.n : ALIF_OOB;
+
+    // carry-in of block 0
+    double v0d = 0.0, a0d = 0.0;
+    int cts = 0;
+    if (a.init_v && c.valid) {
+        const size_t i = (size_t)b * N + c.n;
+        v0d = a.init_v[i];
+        a0d = a.init_a[i];
+        cts = a.init_ts[i];
+        if (cts < 0 || cts > TR) { if (c.w == 0) atomicOr(a.status, 1u); cts = 0; }
+    }
+
+    const uint32_t blk4 = (uint32_t)(TR * N) * 4u;    // bytes per block in a float [T][N] row
+    float buf[DEPTH][L];
+#pragma unroll
+    for (int i = 0; i < DEPTH; i++)
+#pragma unroll
+        for (int k = 0; k < L; k++) buf[i][k] = ld_f32(rI, c.off(k, (uint32_t)min((size_t)i * blk4, TN * 4)));
+
+    for (int nb0 = 0; nb0 < a.NB; nb0 += DEPTH) {
+#pragma unroll
+        for (int i = 0; i < DEPTH; i++) {
+            const int nb = nb0 + i;
+            if (nb >= a.NB) break;             // uniform over the workgroup
+            float x[L];
+#pragma unroll
+            for (int k = 0; k < L; k++) x[k] = buf[i][k];
+            // prefetch block nb + DEPTH (beyond the end of the row: out of range -> 0)
+            const uint32_t nxt = (uint32_t)min((size_t)(nb + DEPTH) * blk4, TN * 4);
+#pragma unroll
+            for (int k = 0; k < L; k++) buf[i][k] = ld_f32(rI, c.off(k, nxt));
+
+            const float cv = (float)v0d, ca = (float)a0d;
+            const int mpre = cts > 0 ? cts - 1 : 0;
+            const float a1 = fmaf(c.pf, ca, cts == TR ? 1.0f : 0.0f);
+            {   // carry-in of this block, for the backward pass
+                const uint32_t e = (uint32_t)(nb * N);
+                st_f32(rCv, ck4 + e * 4u, cv);
+                st_f32(rCa, ck4 + e * 4u, ca);
+                st_u8(rCt, ck1 + e, (uint8_t)cts);
+            }
+            float vt[L], th[L], uTR;
+            const int ts = block_integrate<SEG, L, EVEN>(c, ex, x, cv, a1, mpre, vt, th, uTR);
+            const bool spk = ts <= TR;
+
+            // outputs: spikes and corrected traces (reset after t_s, Eqs. 2 and 5)
+            const uint32_t bo = (uint32_t)nb * blk4;
+#pragma unroll
+            for (int k = 0; k < L; k++) {
+                const int t = c.t0 + k + 1;
+                const uint32_t o4 = c.off(k, bo);
+                const bool sk = t == ts;
+                if constexpr (SDT == 0) st_u8(rS, o4 >> 2 | (o4 & ALIF_OOB), sk ? 1 : 0);
+                else if constexpr (SDT == 1) st_u16(rS, o4 >> 1 | (o4 & ALIF_OOB), sk ? (uint16_t)0x3F80 : (uint16_t)0);
+                else st_f32(rS, o4, sk ? 1.0f : 0.0f);
+                if constexpr (TRACES) {
+                    const bool after = t > ts;
+                    st_f32(rV, o4, after ? 0.0f : vt[k]);
+                    const float pa = pf_tab[pfrow - min(ts, TR) + k];
+                    st_f32(rT, o4, after ? fmaf(c.dd, pa, th[k]) : th[k]);
+                }
+            }
+            // carry to the next block (Props. 4-5), FP64
+            const double e1 = cts == TR ? c.pTm1 : 0.0;
+            const double e2 = pd_tab[pdrow + max(0, TR - 1 - min(ts, TR))];
+            const double extra = e1 + ((spk && ts < TR) ? e2 : 0.0);
+            v0d = spk ? 0.0 : fma(c.betaT, v0d, (double)uTR);
+            a0d = fma(c.pT, a0d, extra);
+            cts = spk ? ts : 0;
+        }
+    }
+    if (a.fin_v && c.valid && c.w == 0) {
+        const size_t i = (size_t)b * N + c.n;
+        a.fin_v[i] = v0d;
+        a.fin_a[i] = a0d;
+        a.fin_ts[i] = cts;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+// Reverse adjoint of the detached-policy recurrence (the oracle's sequential
+// surrogate gradient), one block at a time from the last to the first:
+//   lamV[t]  = gV[t] + gS[t] s'(u) + beta (1 - S[t]) lamV[t+1]
+//   lamTh[t] = gTh[t] - gS[t] s'(u),   lamA[t] = d lamTh[t] + p lamA[t+1]
+//   gI[t] = (1 - beta) gate[t] lamV[t];  dbeta += (1 - S[t-1]) (V[t-1] - gate I[t]) lamV[t]
+//   dp += a[t-1] lamA[t];  dd += a[t] lamTh[t];  dtheta0 += lamTh[t]
+// Each block's V, theta, a and spike are recomputed from its saved carry with
+// the forward's arithmetic. Within a block each segment-wave runs the two
+// reverse recurrences over its L steps from zero, publishes the resulting
+// affine map (lam_start = R + M lam_in) in LDS, and every wave composes the
+// maps from the block end (Horner) to get its own incoming lambda and the
+// block's lambda at step 1 (the carry to the previous block).
+template <int SEG, int L, bool EVEN, int DEPTH, bool GVT, bool GI>
+__global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
+    constexpr int NWG = Geo<SEG>::NWG;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int TR = a.TR, N = a.N, T = a.T, RL = ptab_row(TR, L);
+    double *pd_tab = reinterpret_cast<double *>(smem);
+    float *pf_tab = reinterpret_cast<float *>(smem + (size_t)NWG * TR * sizeof(double));
+    const Exch<SEG> ex = exch_at<SEG>(reinterpret_cast<unsigned char *>(pf_tab + (size_t)NWG * RL));
+
+    const int work = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = work / a.n_groups, g = work - b * a.n_groups;
+    const int n0 = g * NWG;
+    build_p_tables<SEG, L>(pd_tab, pf_tab, n0, N, TR, a.dt, a.tau_a);
+    Lane<SEG, L, EVEN> c;
+    lane_setup(c, N, TR, a.dt, n0, a.tau_m, a.tau_a, a.d, a.theta0, a.bias_k);
+    const int pfrow = c.nl * RL + TR + c.t0;
+    const float bias = (a.bias_k && c.valid) ? a.bias_k[c.n] : 0.0f;
+
+    const size_t TN = (size_t)T * N;
+    const rsrc_t rI = make_rsrc(a.I + b * TN, (uint32_t)(TN * 4));
+    const rsrc_t rGS = make_rsrc(a.gS ? a.gS + b * TN : nullptr, a.gS ? (uint32_t)(TN * 4) : 0u);
+    const rsrc_t rGV = make_rsrc(a.gV ? a.gV + b * TN : nullptr, a.gV ? (uint32_t)(TN * 4) : 0u);
+    const rsrc_t rGT = make_rsrc(a.gTH ? a.gTH + b * TN : nullptr, a.gTH ? (uint32_t)(TN * 4) : 0u);
+    const rsrc_t rGI = make_rsrc(a.gI ? a.gI + b * TN : nullptr, a.gI ? (uint32_t)(TN * 4) : 0u);
+    const size_t CN = (size_t)a.NB * N;
+    const rsrc_t rCv = make_rsrc(a.ck.v + b * CN, (uint32_t)(CN * 4));
+    const rsrc_t rCa = make_rsrc(a.ck.a + b * CN, (uint32_t)(CN * 4));
+    const rsrc_t rCt = make_rsrc(a.ck.ts + b * CN, (uint32_t)CN);
+    const uint32_t ck4 = c.valid ? (uint32_t)c.n * 4u : ALIF_OOB;
+    const uint32_t ck1 = c.valid ? (uint32_t)c.n : ALIF_OOB;
+    const uint32_t blk4 = (uint32_t)(TR * N) * 4u;
+    const uint32_t TN4 = (uint32_t)(TN * 4);
+
+    struct Slot {
+        float x[L], gs[L], gv[L], gt[L];
+        float cv, ca;
+        int cts;
+    };
+    Slot buf[DEPTH];
+    auto load_block = [&](Slot &dst, int nb) {   // nb < 0: everything out of range
+        const uint32_t bo = nb >= 0 ? (uint32_t)nb * blk4 : TN4;
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            const uint32_t o = c.off(k, bo);
+            dst.x[k] = ld_f32(rI, o);
+            dst.gs[k] = ld_f32(rGS, o);
+            if constexpr (GVT) {
+                dst.gv[k] = ld_f32(rGV, o);
+                dst.gt[k] = ld_f32(rGT, o);
+            }
+        }
+        const uint32_t e = nb >= 0 ? (uint32_t)(nb * N) : (uint32_t)CN;
+        dst.cv = ld_f32(rCv, ck4 + e * 4u);
+        dst.ca = ld_f32(rCa, ck4 + e * 4u);
+        dst.cts = ld_u8(rCt, ck1 + e);
+    };
+#pragma unroll
+    for (int i = 0; i < DEPTH; i++) load_block(buf[i], a.NB - 1 - i);
+
+    float lamV_c = 0.0f, lamA_c = 0.0f;  // lambda_V, lambda_a at step 1 of the next block
+    double acc_b = 0.0, acc_p = 0.0, acc_d = 0.0, acc_th = 0.0, acc_bias = 0.0;
+
+    for (int r0 = 0; r0 < a.NB; r0 += DEPTH) {
+#pragma unroll
+        for (int i = 0; i < DEPTH; i++) {
+            const int nb = a.NB - 1 - (r0 + i);
+            if (nb < 0) break;                 // uniform over the workgroup
+            Slot cur = buf[i];
+            load_block(buf[i], nb - DEPTH);
+            const int cts = min(cur.cts, TR);
+            const float cv = cur.cv, ca = cur.ca;
+            const int mpre = cts > 0 ? cts - 1 : 0;
+            const float a1 = fmaf(c.pf, ca, cts == TR ? 1.0f : 0.0f);
+            float vt[L], th[L], uTR;
+            const int ts = block_integrate<SEG, L, EVEN>(c, ex, cur.x, cv, a1, mpre, vt, th, uTR);
+            const int tsc = min(ts, TR);
+
+            // corrected forward quantities and the local reverse recurrences (from zero)
+            float Vk[L], ak[L], lt[L], rV[L], PVk[L], rA[L];
+            bool gate[L];
+            float rv = 0.0f, pv = 1.0f, ra = 0.0f;
+#pragma unroll
+            for (int k = L - 1; k >= 0; k--) {
+                const int t = c.t0 + k + 1;
+                const bool after = t > ts;
+                const float pa = pf_tab[pfrow - tsc + k];   // p^(t - 1 - t_s)
+                Vk[k] = after ? 0.0f : vt[k];
+                ak[k] = after ? fmaf(c.pt[k], a1, pa) : c.pt[k] * a1;
+                const float thk = after ? fmaf(c.dd, pa, th[k]) : th[k];
+                gate[k] = (t > mpre) && !after;
+                const float sg = fast_sigmoid_grad(Vk[k] - thk, a.slope);
+                const float gsk = cur.gs[k] * sg;
+                const float gvk = GVT ? cur.gv[k] : 0.0f, gtk = GVT ? cur.gt[k] : 0.0f;
+                lt[k] = gtk - gsk;
+                const float fV = t == ts ? 0.0f : c.bdec(k);
+                rv = fmaf(fV, rv, gvk + gsk);
+                pv = pv * fV;
+                ra = fmaf(c.pdec(k), ra, c.dd * lt[k]);
+                rV[k] = rv;
+                PVk[k] = pv;
+                rA[k] = ra;
+            }
+            // incoming lambdas at this segment's end, and the block's lambdas at step 1
+            float lVin, lAin, Vprev0, nlV, nlA;
+            if constexpr (SEG > 1) {
+                ex.M[c.w * NWG + c.nl] = pv;
+                ex.R[c.w * NWG + c.nl] = rv;
+                ex.RA[c.w * NWG + c.nl] = ra;
+                ex.VL[c.w * NWG + c.nl] = Vk[L - 1];
+                __syncthreads();
+                float lv = lamV_c, la = lamA_c;
+                lVin = lv;
+                lAin = la;
+#pragma unroll
+                for (int s = SEG - 1; s >= 0; s--) {
+                    lVin = (s == c.w) ? lv : lVin;
+                    lAin = (s == c.w) ? la : lAin;
+                    lv = fmaf(ex.M[s * NWG + c.nl], lv, ex.R[s * NWG + c.nl]);
+                    la = fmaf(c.pseg(s), la, ex.RA[s * NWG + c.nl]);
+                }
+                nlV = lv;
+                nlA = la;
+                Vprev0 = c.w > 0 ? ex.VL[(c.w - 1) * NWG + c.nl] : cv;
+            } else {
+                lVin = lamV_c;
+                lAin = lamA_c;
+                nlV = fmaf(pv, lamV_c, rv);
+                nlA = fmaf(c.pseg(0), lamA_c, ra);
+                Vprev0 = cv;
+            }
+            float lV[L], lA[L];
+#pragma unroll
+            for (int k = 0; k < L; k++) {
+                lV[k] = c.kvalid(k) ? fmaf(PVk[k], lVin, rV[k]) : 0.0f;
+                lA[k] = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
+            }
+
+            // gradient contributions of this lane's steps
+            const float pa0 = pf_tab[pfrow - tsc - 1];     // p^(t0 - 1 - t_s)
+            const float aprev0 = c.w == 0 ? ca : (c.t0 > ts ? fmaf(c.ptm1, a1, pa0) : c.ptm1 * a1);
+            float pb = 0.0f, pp = 0.0f, pdd = 0.0f, pth = 0.0f, pbias = 0.0f;
+            const uint32_t bo = (uint32_t)nb * blk4;
+#pragma unroll
+            for (int k = 0; k < L; k++) {
+                const int t = c.t0 + k + 1;
+                const bool sprev = (t == 1) ? (cts == TR) : (t - 1 == ts);
+                const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
+                const float aprev = (k == 0) ? aprev0 : ak[k > 0 ? k - 1 : 0];
+                const float gIk = gate[k] ? c.omb * lV[k] : 0.0f;
+                const float im = gate[k] ? cur.x[k] + bias : 0.0f;
+                pb = fmaf(sprev ? 0.0f : Vprev - im, lV[k], pb);
+                pp = fmaf(aprev, lA[k], pp);
+                pdd = fmaf(ak[k], lt[k], pdd);
+                pth += lt[k];
+                pbias += gIk;
+                if constexpr (GI) st_f32(rGI, c.off(k, bo), gIk);
+            }
+            acc_b += (double)pb;
+            acc_p += (double)pp;
+            acc_d += (double)pdd;
+            acc_th += (double)pth;
+            acc_bias += (double)pbias;
+            lamV_c = nlV;
+            lamA_c = nlA;
+        }
+    }
+    // per-(b, n) sums over this neuron's segment-waves, in a fixed order
+    if constexpr (SEG > 1) {
+        double *red = reinterpret_cast<double *>(ex.X);   // reuse the exchange area
+        __syncthreads();
+        const int q = c.w * NWG + c.nl;
+        double vals[5] = {acc_b, acc_p, acc_d, acc_th, acc_bias};
+#pragma unroll
+        for (int j = 0; j < 5; j++) {
+            red[q] = vals[j];
+            __syncthreads();
+            if (c.w == 0) {
+                double s = 0.0;
+                for (int w = 0; w < SEG; w++) s += red[w * NWG + c.nl];
+                vals[j] = s;
+            }
+            __syncthreads();
+        }
+        acc_b = vals[0]; acc_p = vals[1]; acc_d = vals[2]; acc_th = vals[3]; acc_bias = vals[4];
+    }
+    if (c.valid && c.w == 0) {
+        const size_t BN = (size_t)a.B * N, i = (size_t)b * N + c.n;
+        a.part[i] = acc_b;
+        a.part[BN + i] = acc_p;
+        a.part[2 * BN + i] = acc_d;
+        a.part[3 * BN + i] = acc_th;
+        a.part[4 * BN + i] = acc_bias;
+    }
+}
+
+#define ALIF_FWD_DEPTH 4
+#define ALIF_BWD_DEPTH 2
+
+template <int SEG, int L>
+hipError_t blocks_fwd_launch(const FwdArgs &a, hipStream_t st) {
+    const int grid = a.B * a.n_groups;
+    if (grid == 0) return hipSuccess;
+    const size_t sm = smem_bytes<SEG, L>(a.TR);
+    constexpr int TH = Geo<SEG>::THREADS;
+    const bool tr = a.V || a.TH;
+#define ALIF_LF(TRC, SD)                                                                          \
+    do {                                                                                          \
+        if (a.TR == SEG * L)                                                                      \
+            hipLaunchKernelGGL((k_blocks_fwd<SEG, L, true, ALIF_FWD_DEPTH, TRC, SD>), dim3(grid), \
+                               dim3(TH), sm, st, a);                                              \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_blocks_fwd<SEG, L, false, ALIF_FWD_DEPTH, TRC, SD>), dim3(grid),\
+                               dim3(TH), sm, st, a);                                              \
+    } while (0)
+    if (tr) {
+        if (a.spike_dtype == 0) ALIF_LF(true, 0);
+        else if (a.spike_dtype == 1) ALIF_LF(true, 1);
+        else ALIF_LF(true, 2);
+    } else {
+        if (a.spike_dtype == 0) ALIF_LF(false, 0);
+        else if (a.spike_dtype == 1) ALIF_LF(false, 1);
+        else ALIF_LF(false, 2);
+    }
+#undef ALIF_LF
+    return hipGetLastError();
+}
+
+template <int SEG, int L>
+hipError_t blocks_bwd_launch(const BwdArgs &a, hipStream_t st) {
+    const int grid = a.B * a.n_groups;
+    if (grid == 0) return hipSuccess;
+    const size_t sm = smem_bytes<SEG, L>(a.TR);
+    constexpr int TH = Geo<SEG>::THREADS;
+    const bool gvt = a.gV || a.gTH, gi = a.gI != nullptr;
+#define ALIF_LB(G1, G2)                                                                           \
+    do {                                                                                          \
+        if (a.TR == SEG * L)                                                                      \
+            hipLaunchKernelGGL((k_blocks_bwd<SEG, L, true, ALIF_BWD_DEPTH, G1, G2>), dim3(grid),  \
+                               dim3(TH), sm, st, a);                                              \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_blocks_bwd<SEG, L, false, ALIF_BWD_DEPTH, G1, G2>), dim3(grid), \
+                               dim3(TH), sm, st, a);                                              \
+    } while (0)
+    if (gvt) { if (gi) ALIF_LB(true, true); else ALIF_LB(true, false); }
+    else { if (gi) ALIF_LB(false, true); else ALIF_LB(false, false); }
+#undef ALIF_LB
+    return hipGetLastError();
+}
+
+#define ALIF_INSTANTIATE(SEG, L)                                                        \
+    template hipError_t blocks_fwd_launch<SEG, L>(const FwdArgs &, hipStream_t);       \
+    template hipError_t blocks_bwd_launch<SEG, L>(const BwdArgs &, hipStream_t);       \
+    template size_t smem_bytes<SEG, L>(int);
+
+}  // namespace alif
