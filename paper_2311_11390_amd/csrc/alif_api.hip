@@ -118,16 +118,21 @@ int check_params(const alif_params *prm) {
     return ALIF_OK;
 }
 
+// Block path: the carry-in of every block plus the final carry, [B][NB + 1][N]
+// (the backward reads block n's spike step from the carry-in of block n + 1).
 size_t carry_bytes(const alif_desc *d, const Prob &p) {
+    if (d->algo == ALIF_ALGO_BLOCKS) {
+        const size_t cn = (size_t)p.B * (p.NB + 1) * p.N;
+        return align256(cn * 4) * 2 + align256(cn);
+    }
     const size_t cn = (size_t)p.B * p.NB * p.N;
-    if (d->algo == ALIF_ALGO_BLOCKS) return align256(cn * 4) * 2 + align256(cn);
     if (d->algo == ALIF_ALGO_SEQUENTIAL) return align256(cn * 8) * 2 + align256(cn * 4);
     const size_t bn = (size_t)p.B * p.N;  // per-step launch: state only
     return align256(bn * 8) * 2 + align256(bn * 4);
 }
 
 CarryView carry_view(void *base, const Prob &p) {
-    const size_t cn = (size_t)p.B * p.NB * p.N;
+    const size_t cn = (size_t)p.B * (p.NB + 1) * p.N;
     char *c = (char *)base;
     CarryView v;
     v.v = (float *)c;

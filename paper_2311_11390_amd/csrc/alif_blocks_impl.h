@@ -251,6 +251,53 @@ __device__ __forceinline__ int block_integrate(const Lane<SEG, L, EVEN> &c, cons
     }
 }
 
+// The backward's recompute of a block whose spike step is already known (from
+// the carry-in of the next block): the same no-reset membrane and threshold as
+// block_integrate, with the same arithmetic, but no crossing search. One
+// workgroup barrier if SEG > 1.
+template <int SEG, int L, bool EVEN>
+__device__ __forceinline__ void block_membrane(const Lane<SEG, L, EVEN> &c, const Exch<SEG> &ex,
+                                               const float (&x)[L], float cv, float a1, int mpre,
+                                               float (&vt)[L], float (&th)[L]) {
+    constexpr int NWG = Geo<SEG>::NWG;
+    float uu[L];
+    float u = 0.0f;
+    if (__any(mpre > 0)) {
+        const int kmin = mpre - c.t0;
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            const float in = k >= kmin ? fmaf(c.omb, x[k], c.obk(k)) : 0.0f;
+            u = fmaf(c.bdec(k), u, in);
+            uu[k] = u;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            u = fmaf(c.bdec(k), u, fmaf(c.omb, x[k], c.obk(k)));
+            uu[k] = u;
+        }
+    }
+    float E = 0.0f;
+    if constexpr (SEG > 1) {
+        ex.X[c.w * NWG + c.nl] = uu[L - 1];
+        __syncthreads();
+        float U = 0.0f;
+#pragma unroll
+        for (int s = 0; s < SEG; s++) {
+            const float xs = ex.X[s * NWG + c.nl];
+            E = (s == c.w) ? U : E;
+            U = fmaf(c.bseg(s), U, xs);
+        }
+    }
+    const float C = fmaf(c.bsL, cv, E);
+    const float da1 = c.dd * a1;
+#pragma unroll
+    for (int k = L - 1; k >= 0; k--) {
+        vt[k] = fmaf(c.bk[k], C, uu[k]);
+        th[k] = fmaf(c.pt[k], da1, c.thk(k));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
@@ -280,7 +327,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_fwd(FwdArgs a) {
     const rsrc_t rS = make_rsrc((const char *)a.spikes + b * TN * SB, (uint32_t)(TN * SB));
     const rsrc_t rV = make_rsrc(a.V ? a.V + b * TN : nullptr, a.V ? (uint32_t)(TN * 4) : 0u);
     const rsrc_t rT = make_rsrc(a.TH ? a.TH + b * TN : nullptr, a.TH ? (uint32_t)(TN * 4) : 0u);
-    const size_t CN = (size_t)a.NB * N;
+    const size_t CN = (size_t)(a.NB + 1) * N;   // carry-in of every block, then the final carry
     const bool ck = a.ck.v != nullptr;
     const rsrc_t rCv = make_rsrc(ck ? a.ck.v + b * CN : nullptr, ck ? (uint32_t)(CN * 4) : 0u);
     const rsrc_t rCa = make_rsrc(ck ? a.ck.a + b * CN : nullptr, ck ? (uint32_t)(CN * 4) : 0u);
@@ -359,6 +406,12 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_fwd(FwdArgs a) {
             cts = spk ? ts : 0;
         }
     }
+    {   // the final carry, after the carry-in of the last block
+        const uint32_t e = (uint32_t)(a.NB * N);
+        st_f32(rCv, ck4 + e * 4u, (float)v0d);
+        st_f32(rCa, ck4 + e * 4u, (float)a0d);
+        st_u8(rCt, ck1 + e, (uint8_t)cts);
+    }
     if (a.fin_v && c.valid && c.w == 0) {
         const size_t i = (size_t)b * N + c.n;
         a.fin_v[i] = v0d;
@@ -406,7 +459,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     const rsrc_t rGV = make_rsrc(a.gV ? a.gV + b * TN : nullptr, a.gV ? (uint32_t)(TN * 4) : 0u);
     const rsrc_t rGT = make_rsrc(a.gTH ? a.gTH + b * TN : nullptr, a.gTH ? (uint32_t)(TN * 4) : 0u);
     const rsrc_t rGI = make_rsrc(a.gI ? a.gI + b * TN : nullptr, a.gI ? (uint32_t)(TN * 4) : 0u);
-    const size_t CN = (size_t)a.NB * N;
+    const size_t CN = (size_t)(a.NB + 1) * N;   // carry-in of every block, then the final carry
     const rsrc_t rCv = make_rsrc(a.ck.v + b * CN, (uint32_t)(CN * 4));
     const rsrc_t rCa = make_rsrc(a.ck.a + b * CN, (uint32_t)(CN * 4));
     const rsrc_t rCt = make_rsrc(a.ck.ts + b * CN, (uint32_t)CN);
@@ -418,7 +471,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     struct Slot {
         float x[L], gs[L], gv[L], gt[L];
         float cv, ca;
-        int cts;
+        int cts, tsn;   // spike step of the previous block (carry-in) and of this block
     };
     Slot buf[DEPTH];
     auto load_block = [&](Slot &dst, int nb) {   // nb < 0: everything out of range
@@ -437,6 +490,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
         dst.cv = ld_f32(rCv, ck4 + e * 4u);
         dst.ca = ld_f32(rCa, ck4 + e * 4u);
         dst.cts = ld_u8(rCt, ck1 + e);
+        dst.tsn = ld_u8(rCt, ck1 + (nb >= 0 ? e + (uint32_t)N : (uint32_t)CN));
     };
 #pragma unroll
     for (int i = 0; i < DEPTH; i++) load_block(buf[i], a.NB - 1 - i);
@@ -452,37 +506,61 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
             Slot cur = buf[i];
             load_block(buf[i], nb - DEPTH);
             const int cts = min(cur.cts, TR);
+            // the block's spike step, as the forward decided it (carry-in of block nb + 1)
+            const int ts = cur.tsn > 0 ? min(cur.tsn, TR) : ALIF_NO_SPIKE;
             const float cv = cur.cv, ca = cur.ca;
             const int mpre = cts > 0 ? cts - 1 : 0;
             const float a1 = fmaf(c.pf, ca, cts == TR ? 1.0f : 0.0f);
-            float vt[L], th[L], uTR;
-            const int ts = block_integrate<SEG, L, EVEN>(c, ex, cur.x, cv, a1, mpre, vt, th, uTR);
+            float vt[L], th[L];
+            block_membrane<SEG, L, EVEN>(c, ex, cur.x, cv, a1, mpre, vt, th);
             const int tsc = min(ts, TR);
+            // quiet block: no spike in this block and none at the end of the previous
+            // one anywhere in the wave -> no reset, no mask, no post-spike terms
+            const bool quiet = !__any(ts <= TR || mpre > 0);
 
             // corrected forward quantities and the local reverse recurrences (from zero)
             float Vk[L], ak[L], lt[L], rV[L], PVk[L], rA[L];
             bool gate[L];
             float rv = 0.0f, pv = 1.0f, ra = 0.0f;
+            if (quiet) {
 #pragma unroll
-            for (int k = L - 1; k >= 0; k--) {
-                const int t = c.t0 + k + 1;
-                const bool after = t > ts;
-                const float pa = pf_tab[pfrow - tsc + k];   // p^(t - 1 - t_s)
-                Vk[k] = after ? 0.0f : vt[k];
-                ak[k] = after ? fmaf(c.pt[k], a1, pa) : c.pt[k] * a1;
-                const float thk = after ? fmaf(c.dd, pa, th[k]) : th[k];
-                gate[k] = (t > mpre) && !after;
-                const float sg = fast_sigmoid_grad(Vk[k] - thk, a.slope);
-                const float gsk = cur.gs[k] * sg;
-                const float gvk = GVT ? cur.gv[k] : 0.0f, gtk = GVT ? cur.gt[k] : 0.0f;
-                lt[k] = gtk - gsk;
-                const float fV = t == ts ? 0.0f : c.bdec(k);
-                rv = fmaf(fV, rv, gvk + gsk);
-                pv = pv * fV;
-                ra = fmaf(c.pdec(k), ra, c.dd * lt[k]);
-                rV[k] = rv;
-                PVk[k] = pv;
-                rA[k] = ra;
+                for (int k = L - 1; k >= 0; k--) {
+                    Vk[k] = vt[k];
+                    ak[k] = c.pt[k] * a1;
+                    gate[k] = true;
+                    const float sg = fast_sigmoid_grad(vt[k] - th[k], a.slope);
+                    const float gsk = cur.gs[k] * sg;
+                    const float gvk = GVT ? cur.gv[k] : 0.0f, gtk = GVT ? cur.gt[k] : 0.0f;
+                    lt[k] = gtk - gsk;
+                    rv = fmaf(c.bdec(k), rv, gvk + gsk);
+                    ra = fmaf(c.pdec(k), ra, c.dd * lt[k]);
+                    rV[k] = rv;
+                    PVk[k] = c.PB(k);
+                    rA[k] = ra;
+                }
+                pv = c.PB(0);
+            } else {
+#pragma unroll
+                for (int k = L - 1; k >= 0; k--) {
+                    const int t = c.t0 + k + 1;
+                    const bool after = t > ts;
+                    const float pa = pf_tab[pfrow - tsc + k];   // p^(t - 1 - t_s)
+                    Vk[k] = after ? 0.0f : vt[k];
+                    ak[k] = after ? fmaf(c.pt[k], a1, pa) : c.pt[k] * a1;
+                    const float thk = after ? fmaf(c.dd, pa, th[k]) : th[k];
+                    gate[k] = (t > mpre) && !after;
+                    const float sg = fast_sigmoid_grad(Vk[k] - thk, a.slope);
+                    const float gsk = cur.gs[k] * sg;
+                    const float gvk = GVT ? cur.gv[k] : 0.0f, gtk = GVT ? cur.gt[k] : 0.0f;
+                    lt[k] = gtk - gsk;
+                    const float fV = t == ts ? 0.0f : c.bdec(k);
+                    rv = fmaf(fV, rv, gvk + gsk);
+                    pv = pv * fV;
+                    ra = fmaf(c.pdec(k), ra, c.dd * lt[k]);
+                    rV[k] = rv;
+                    PVk[k] = pv;
+                    rA[k] = ra;
+                }
             }
             // incoming lambdas at this segment's end, and the block's lambdas at step 1
             float lVin, lAin, Vprev0, nlV, nlA;
@@ -512,32 +590,46 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
                 nlA = fmaf(c.pseg(0), lamA_c, ra);
                 Vprev0 = cv;
             }
-            float lV[L], lA[L];
-#pragma unroll
-            for (int k = 0; k < L; k++) {
-                lV[k] = c.kvalid(k) ? fmaf(PVk[k], lVin, rV[k]) : 0.0f;
-                lA[k] = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
-            }
 
             // gradient contributions of this lane's steps
-            const float pa0 = pf_tab[pfrow - tsc - 1];     // p^(t0 - 1 - t_s)
-            const float aprev0 = c.w == 0 ? ca : (c.t0 > ts ? fmaf(c.ptm1, a1, pa0) : c.ptm1 * a1);
             float pb = 0.0f, pp = 0.0f, pdd = 0.0f, pth = 0.0f, pbias = 0.0f;
             const uint32_t bo = (uint32_t)nb * blk4;
+            if (quiet) {
+                const float aprev0 = c.w == 0 ? ca : c.ptm1 * a1;
 #pragma unroll
-            for (int k = 0; k < L; k++) {
-                const int t = c.t0 + k + 1;
-                const bool sprev = (t == 1) ? (cts == TR) : (t - 1 == ts);
-                const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
-                const float aprev = (k == 0) ? aprev0 : ak[k > 0 ? k - 1 : 0];
-                const float gIk = gate[k] ? c.omb * lV[k] : 0.0f;
-                const float im = gate[k] ? cur.x[k] + bias : 0.0f;
-                pb = fmaf(sprev ? 0.0f : Vprev - im, lV[k], pb);
-                pp = fmaf(aprev, lA[k], pp);
-                pdd = fmaf(ak[k], lt[k], pdd);
-                pth += lt[k];
-                pbias += gIk;
-                if constexpr (GI) st_f32(rGI, c.off(k, bo), gIk);
+                for (int k = 0; k < L; k++) {
+                    const float lV = c.kvalid(k) ? fmaf(PVk[k], lVin, rV[k]) : 0.0f;
+                    const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
+                    const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
+                    const float aprev = (k == 0) ? aprev0 : ak[k > 0 ? k - 1 : 0];
+                    const float gIk = c.omb * lV;
+                    pb = fmaf(Vprev - (cur.x[k] + bias), lV, pb);
+                    pp = fmaf(aprev, lA, pp);
+                    pdd = fmaf(ak[k], lt[k], pdd);
+                    pth += lt[k];
+                    pbias += gIk;
+                    if constexpr (GI) st_f32(rGI, c.off(k, bo), gIk);
+                }
+            } else {
+                const float pa0 = pf_tab[pfrow - tsc - 1];     // p^(t0 - 1 - t_s)
+                const float aprev0 = c.w == 0 ? ca : (c.t0 > ts ? fmaf(c.ptm1, a1, pa0) : c.ptm1 * a1);
+#pragma unroll
+                for (int k = 0; k < L; k++) {
+                    const float lV = c.kvalid(k) ? fmaf(PVk[k], lVin, rV[k]) : 0.0f;
+                    const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
+                    const int t = c.t0 + k + 1;
+                    const bool sprev = (t == 1) ? (cts == TR) : (t - 1 == ts);
+                    const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
+                    const float aprev = (k == 0) ? aprev0 : ak[k > 0 ? k - 1 : 0];
+                    const float gIk = gate[k] ? c.omb * lV : 0.0f;
+                    const float im = gate[k] ? cur.x[k] + bias : 0.0f;
+                    pb = fmaf(sprev ? 0.0f : Vprev - im, lV, pb);
+                    pp = fmaf(aprev, lA, pp);
+                    pdd = fmaf(ak[k], lt[k], pdd);
+                    pth += lt[k];
+                    pbias += gIk;
+                    if constexpr (GI) st_f32(rGI, c.off(k, bo), gIk);
+                }
             }
             acc_b += (double)pb;
             acc_p += (double)pp;
