@@ -139,8 +139,12 @@ typedef struct alif_state {
 /* T_R for dt/arp, or a negative status if they do not give 2 <= T_R <= ALIF_MAX_TR. */
 int alif_refractory_steps(double dt_ms, double arp_ms);
 
-/* Bytes of the block-carry buffer alif_forward writes for alif_backward:
- * 9 bytes per (b, block, neuron) plus alignment. */
+/* Bytes of the block-carry buffer alif_forward writes for alif_backward.
+ * ALIF_ALGO_BLOCKS: the carry-in (V0 float, a float, previous spike step u8)
+ * of every block plus the final carry, 9 bytes per (b, block + 1, neuron);
+ * ALIF_ALGO_SEQUENTIAL: FP64 state checkpoints every T_R steps, 20 bytes per
+ * (b, block, neuron); ALIF_ALGO_PER_STEP: the state of one step. Each part is
+ * 256-byte aligned. */
 int alif_carry_bytes(const alif_desc *desc, size_t *bytes);
 
 /* Bytes of device scratch alif_backward needs (per-(b, neuron) FP64 partial sums). */
@@ -255,6 +259,26 @@ int alif_device_status(uint32_t *bits, void *stream);
 /* Message for the last error on this thread (empty string if none). */
 const char *alif_last_error(void);
 
+/* ---- Ornstein-Uhlenbeck input current --------------------------------------- */
+
+/*
+ * Writes the device float [T][N] current I[t] = mean + X[t] of independent OU
+ * processes, discretised exactly with e = exp(-dt_ms / tau_ms):
+ *   X[0] = sd z_0,  X[t] = e X[t-1] + sd sqrt(1 - e^2) z_t,
+ * evaluated in FP64 and rounded once to float. z_t of neuron n is a standard
+ * normal from Philox4x32-10 (Salmon et al., SC 2011; key = seed, low word
+ * first; counter (t / 4, n, 0, 0)) through Box-Muller in FP64: with output
+ * words (w0, w1, w2, w3), u1 = (w_2j + 1) / 2^32, u2 = w_2j+1 / 2^32 and
+ * r = sqrt(-2 ln u1), step 4q + 2j takes r cos(2 pi u2) and step 4q + 2j + 1
+ * takes r sin(2 pi u2). The same (seed, n, t) always gives the same value,
+ * independent of T and N. workspace: device, alif_ou_workspace_bytes(T, N)
+ * bytes. Needs tau_ms > 0, sd >= 0, dt_ms > 0.
+ */
+int alif_ou_workspace_bytes(int32_t T, int32_t n_neurons, size_t *bytes);
+int alif_ou_current(int32_t T, int32_t n_neurons, double dt_ms, float tau_ms, float mean, float sd,
+                    uint64_t seed, float *current, void *workspace, size_t workspace_bytes,
+                    void *stream);
+
 /* ---- serving: continuous batching of independent simulations ---------------- */
 
 typedef struct alif_server alif_server;
@@ -266,14 +290,10 @@ enum alif_request_input {
 
 /*
  * One single-layer simulation request (forward only, batch 1). Parameters are
- * host float [N] arrays copied at submit. The OU current is
- *   I[0] = mu + sd z_0,  I[t+1] = mu + (I[t] - mu) e + sd sqrt(1 - e^2) z_{t+1},
- *   e = exp(-DT / ou_tau_ms),
- * where z_t for neuron n is the standard normal produced by Box-Muller from
- * Philox4x32-10 (Salmon et al., SC 2011) with key = seed and counter
- * (t, n, 0, 0): z = sqrt(-2 ln u1) cos(2 pi u2), u1 = (w0 + 1) / 2^32,
- * u2 = w1 / 2^32 for the first two output words w0, w1 (evaluated in FP64,
- * rounded once to float at the end of each step's update).
+ * host float [N] arrays copied at submit. ALIF_REQ_OU draws the current on the
+ * device exactly as alif_ou_current does (with the request's dt_ms, ou_tau_ms,
+ * ou_mean, ou_sd and seed). host_current (if used) and host_spikes must stay
+ * valid until alif_poll has returned the request's result.
  */
 typedef struct alif_request {
     int32_t n_neurons;
@@ -296,9 +316,15 @@ typedef struct alif_result {
 } alif_result;
 
 /*
- * hbm_budget_bytes: device memory the server may hold for admitted requests;
- * max_slots: requests simultaneously resident; device: HIP device ordinal.
- * The server owns a scheduler thread and its own streams on `device`.
+ * Continuous batching: a scheduler thread admits queued requests in arrival
+ * order whenever one of max_slots slots is free and the request's footprint
+ * fits in what is left of hbm_budget_bytes, and runs each on its slot's own
+ * stream on `device` (default priority), so that requests that arrive while
+ * others run overlap on the GPU. A request's result does not depend on what
+ * else is resident. 1 <= max_slots <= 64. Device memory for a request is taken
+ * from HIP's stream-ordered allocator at admission and returned on completion;
+ * each slot also keeps pinned host staging, grown to the largest request it
+ * has served.
  */
 int alif_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t device,
                        alif_server **out);

@@ -79,6 +79,9 @@ _SIGNATURES = {
                                       _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "alif_device_status": (c_int, [POINTER(c_uint32), _P]),
     "alif_last_error": (ctypes.c_char_p, []),
+    "alif_ou_workspace_bytes": (c_int, [c_int32, c_int32, POINTER(c_size_t)]),
+    "alif_ou_current": (c_int, [c_int32, c_int32, c_double, c_float, c_float, c_float, c_uint64,
+                                _P, _P, c_size_t, _P]),
     "alif_server_create": (c_int, [c_size_t, c_int32, c_int32, POINTER(c_void_p)]),
     "alif_request_footprint": (c_int, [POINTER(AlifRequest), POINTER(c_size_t)]),
     "alif_submit": (c_int, [c_void_p, POINTER(AlifRequest), POINTER(c_uint64)]),

@@ -288,3 +288,19 @@ class Readout(torch.autograd.Function):
         s, W_r, tau_r = ctx.saved_tensors
         gS, gW, gt = readout_backward(s, W_r.contiguous(), tau_r.contiguous(), ctx.dt, go.float(), ctx.ws)
         return (gS.to(s.dtype) if ctx.needs_input_grad[0] else None, gW, gt, None)
+
+
+def ou_current(T: int, N: int, dt: float, tau: float, mean: float, sd: float, seed: int,
+               device="cuda", out: torch.Tensor | None = None) -> torch.Tensor:
+    """float32 [T][N] Ornstein-Uhlenbeck current drawn on the device by the library
+    (Philox4x32-10 + Box-Muller, FP64 recurrence; the definition is in the header)."""
+    lib = L.load()
+    ws_b = ctypes.c_size_t()
+    L.check(lib.alif_ou_workspace_bytes(T, N, ctypes.byref(ws_b)))
+    if out is None:
+        out = torch.empty((T, N), dtype=torch.float32, device=device)
+    assert out.shape == (T, N) and out.dtype == torch.float32 and out.is_contiguous()
+    ws = torch.empty(max(ws_b.value, 1), dtype=torch.uint8, device=out.device)
+    L.check(lib.alif_ou_current(T, N, dt, tau, mean, sd, seed, _p(out), _p(ws), ws_b.value,
+                                _stream(out.device)))
+    return out

@@ -185,3 +185,14 @@ def request_stream(seed=0, n=2000, rate_hz=200.0, n_range=(64, 2048),
     seeds = g.integers(1, 2**62, n)
     return [Request(i, float(t[i]), int(Ns[i]), int(Ts[i]), float(D[i]), 2.0, int(seeds[i]))
             for i in range(n)]
+
+
+# OU current of a serving request (the same process as the fine-DT workload)
+REQUEST_OU = dict(tau=5.0, mean=0.8, sd=0.5)
+
+
+def request_params(req: Request) -> LayerParams:
+    """Per-neuron parameters of a serving request, drawn from its seed:
+    tau_m ~ U[10, 30] ms, tau_a ~ U[100, 300] ms, d = 1.8, theta0 = 1."""
+    g = rng(req.seed % (2**63))
+    return layer_params(g, req.N, tau_mem=(10.0, 30.0), tau_adapt=(100.0, 300.0))

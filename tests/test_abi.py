@@ -92,3 +92,76 @@ def test_sizes_and_validation_host_side():
     assert lib.alif_forward(ctypes.byref(_desc()), ctypes.byref(p), None, None, None,
                             None, None, None, None, None, None, None) == L.ALIF_EINVAL
     assert b"required" in lib.alif_last_error()
+
+
+def _request(N=100, T=1000, dt=0.05, arp=2.0, **kw):
+    import numpy as np
+
+    from paper_2311_11390_amd.serving import Request
+    base = dict(T=T, dt=dt, arp=arp, tau_mem=np.full(N, 20.0), tau_adapt=np.full(N, 200.0),
+                d=np.full(N, 1.8), theta0=np.ones(N))
+    base.update(kw)
+    return Request(**base)
+
+
+def test_serving_footprint_and_validation_host_side():
+    import numpy as np
+
+    from paper_2311_11390_amd import serving
+    N, T = 100, 1000
+    fp = serving.footprint(_request(N, T))
+    nc = -(-T // 256)
+    want = sum(-(-x // 256) * 256 for x in (5 * N * 4, T * N * 4, T * N, nc * N * 8)) + 256
+    assert fp == want
+    fp_host = serving.footprint(_request(N, T, current=np.zeros((T, N), np.float32)))
+    assert fp_host == want - (-(-nc * N * 8 // 256) * 256)
+    bad = [
+        dict(dt=1.0, arp=1.0),                                   # T_R = 1
+        dict(dt=0.3, arp=2.0),                                   # not whole
+        dict(tau_mem=np.full(N, -1.0)),
+        dict(tau_adapt=np.zeros(N)),
+        dict(d=np.full(N, -0.1)),
+        dict(theta0=np.zeros(N)),
+        dict(theta0=np.full(N, np.nan)),
+        dict(ou_tau=0.0),
+        dict(ou_sd=-1.0),
+    ]
+    for kw in bad:
+        with pytest.raises(L.AlifError) as ei:
+            serving.footprint(_request(N, T, **kw))
+        assert ei.value.code == L.ALIF_EINVAL, kw
+    with pytest.raises(L.AlifError) as ei:
+        serving.footprint(_request(N, T, dt=0.01))              # T_R = 200 > ALIF_MAX_TR
+    assert ei.value.code == L.ALIF_EUNSUPPORTED
+    with pytest.raises(L.AlifError) as ei:
+        serving.footprint(_request(4096, 2 ** 17))              # T * N * 4 >= 2^31
+    assert ei.value.code == L.ALIF_EUNSUPPORTED
+    lib = L.load()
+    c, _ = serving.c_request(_request(N, T))
+    c.input = 5
+    n = ctypes.c_size_t()
+    assert lib.alif_request_footprint(ctypes.byref(c), ctypes.byref(n)) == L.ALIF_EINVAL
+    c.input = L.REQ_HOST_CURRENT
+    c.host_current = None
+    assert lib.alif_request_footprint(ctypes.byref(c), ctypes.byref(n)) == L.ALIF_EINVAL
+    assert lib.alif_request_footprint(None, ctypes.byref(n)) == L.ALIF_EINVAL
+    t = ctypes.c_uint64()
+    assert lib.alif_submit(None, ctypes.byref(c), ctypes.byref(t)) == L.ALIF_EINVAL
+    assert lib.alif_poll(None, 1, None) == L.ALIF_EINVAL
+    assert lib.alif_server_destroy(None) == L.ALIF_OK
+    h = ctypes.c_void_p()
+    assert lib.alif_server_create(1 << 30, 0, 0, ctypes.byref(h)) == L.ALIF_EINVAL
+    assert lib.alif_server_create(0, 4, 0, ctypes.byref(h)) == L.ALIF_EINVAL
+
+
+def test_ou_current_sizes_and_validation_host_side():
+    lib = L.load()
+    n = ctypes.c_size_t()
+    assert lib.alif_ou_workspace_bytes(1000, 100, ctypes.byref(n)) == 0
+    assert n.value == -(-(4 * 100 * 8) // 256) * 256
+    assert lib.alif_ou_workspace_bytes(-1, 100, ctypes.byref(n)) == L.ALIF_EINVAL
+    assert lib.alif_ou_current(10, 10, 0.05, 0.0, 0.8, 0.5, 1, None, None, 0, None) == L.ALIF_EINVAL
+    assert lib.alif_ou_current(10, 10, 0.05, 5.0, 0.8, -0.5, 1, None, None, 0, None) == L.ALIF_EINVAL
+    assert lib.alif_ou_current(10, 10, 0.0, 5.0, 0.8, 0.5, 1, None, None, 0, None) == L.ALIF_EINVAL
+    assert lib.alif_ou_current(10, 10, 0.05, 5.0, 0.8, 0.5, 1, None, None, 0, None) == L.ALIF_EINVAL
+    assert lib.alif_ou_current(0, 10, 0.05, 5.0, 0.8, 0.5, 1, None, None, 0, None) == L.ALIF_OK
