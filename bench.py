@@ -15,9 +15,10 @@ target trains simulated with perturbed parameters; it is computed once before
 timing (the loss is not part of the ALIF path).
 
 Printed JSON (last stdout line): whole-job neuron-steps/s (B * N * T / step
-time), the sequential per-step GPU kernels on the same work, per-kernel HIP
-event durations, the HBM roofline of the dominant kernel and the FP64 oracle on
-host cores over a bounded sample of rows.
+time), the sequential GPU kernels on the same work, per-kernel HIP event
+durations, the HBM roofline of the dominant kernel, the FP64 oracle on host
+cores over the same workload, and a serving leg (p50 / p99 latency and
+throughput of a Poisson stream of uneven requests under continuous batching).
 """
 from __future__ import annotations
 
@@ -85,25 +86,90 @@ def time_steps(fn_fwd, fn_bwd, steps, warmup):
     return wall, np.array(fwd), np.array(bwd)
 
 
-def cpu_baseline(w, rows, threads):
-    """FP64 oracle fwd + bwd on the first `rows` (batch, neuron) rows, full T."""
+def cpu_baseline(w, cpu_seconds, threads):
+    """FP64 oracle fwd + bwd over the whole workload (every (batch, neuron) row, all
+    T steps), repeated in whole passes until `cpu_seconds` of CPU time (summed
+    over the threads) have been spent."""
     import oracle
     from oracle import _to_rows
     I = w.inputs["I"]
+    Irows = _to_rows(I.astype(np.float64))
     B, T, N = I.shape
-    nb = max(1, rows // N)
-    Irows = _to_rows(I[:nb].astype(np.float64))
     lp = w.layers[0]
-    tile = lambda q: np.tile(np.asarray(q, np.float64), nb)
+    tile = lambda q: np.tile(np.asarray(q, np.float64), B)
     prm = [tile(lp.tau_mem), tile(lp.tau_adapt), tile(lp.d), tile(lp.theta0)]
     g = np.random.default_rng(1).standard_normal(Irows.shape)
     TR = oracle.refractory_steps(w.dt, w.arp)
     oracle.set_threads(threads)
-    t0 = time.perf_counter()
-    fw = oracle.forward_rows(Irows, *prm, w.dt, TR)
-    oracle.backward_rows(fw, *prm, w.dt, 10.0, gS=g, want_gI=False)
-    el = time.perf_counter() - t0
-    return Irows.size / el, el, Irows.shape[0]
+    passes, c0, t0 = 0, time.process_time(), time.perf_counter()
+    while passes == 0 or time.process_time() - c0 < cpu_seconds:
+        fw = oracle.forward_rows(Irows, *prm, w.dt, TR)
+        oracle.backward_rows(fw, *prm, w.dt, 10.0, gS=g, want_gI=False)
+        del fw
+        passes += 1
+    el, cpu = time.perf_counter() - t0, time.process_time() - c0
+    return Irows.size * passes / el, el, cpu, passes, Irows.shape[0]
+
+
+def serve_leg(n_requests, rate_hz, max_slots, budget_gib, seed=1):
+    """Replay a Poisson request stream (uneven N, T and DT; OU current drawn on the
+    device) against the library's server in real time, then the same stream
+    submitted all at once. Latency = completion - submission on the server's
+    clock; throughput = neuron-steps of all requests / (last completion - first
+    submission)."""
+    from paper_2311_11390_amd import serving, synth
+    stream = synth.request_stream(seed=seed, n=n_requests + 8, rate_hz=rate_hz)
+    warm, stream = stream[:8], stream[8:]
+    t_shift = stream[0].arrival_s
+
+    def req(q):
+        lp = synth.request_params(q)
+        return serving.Request(T=q.T, dt=q.dt, arp=q.arp, tau_mem=lp.tau_mem, tau_adapt=lp.tau_adapt,
+                               d=lp.d, theta0=lp.theta0, seed=q.seed,
+                               **{"ou_" + k: v for k, v in synth.REQUEST_OU.items()})
+
+    reqs = [req(q) for q in stream]
+    work = float(sum(q.N * q.T for q in stream))
+    out = {"requests": len(stream), "arrival_rate_hz": rate_hz, "max_slots": max_slots,
+           "budget_GiB": budget_gib, "neuron_steps": work,
+           "stream": "Poisson arrivals; N ~ U{64..2048}, T ~ U{500..50000}, DT in {1, 0.1, 0.05} ms, "
+                     "ARP 2 ms; OU current (tau 5 ms, mean 0.8, sd 0.5) drawn on the device; "
+                     "spike trains copied back to host memory"}
+    with serving.Server(int(budget_gib * (1 << 30)), max_slots=max_slots) as srv:
+        for t in [srv.submit(req(q)) for q in warm]:     # pool and staging warm-up
+            srv.wait(t, timeout=120)
+        for mode in ("realtime", "saturated"):
+            pending, results = {}, []
+            t0 = time.perf_counter()
+            for i, (q, r) in enumerate(zip(stream, reqs)):
+                if mode == "realtime":
+                    while time.perf_counter() - t0 < q.arrival_s - t_shift:
+                        for tk in list(pending):
+                            res = srv.poll(tk)
+                            if res is not None:
+                                res.spikes = None
+                                results.append(res)
+                                del pending[tk]
+                        time.sleep(2e-4)
+                pending[srv.submit(r)] = i
+            while pending:
+                for tk in list(pending):
+                    res = srv.poll(tk)
+                    if res is not None:
+                        res.spikes = None
+                        results.append(res)
+                        del pending[tk]
+                time.sleep(2e-4)
+            bad = [r.status for r in results if r.status != 0]
+            lat = np.array([r.latency for r in results]) * 1e3
+            span = max(r.t_done for r in results) - min(r.t_submit for r in results)
+            out[mode] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                         "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+                         "neuron_steps_per_s": work / span, "span_s": span, "failed": len(bad)}
+            log(f"[bench] serving {mode}: p50 {out[mode]['p50_ms']:.2f} ms, p99 {out[mode]['p99_ms']:.2f} ms, "
+                f"{out[mode]['neuron_steps_per_s']:.3e} neuron-steps/s over {span:.2f} s")
+            del results
+    return out
 
 
 def main():
@@ -113,7 +179,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=8192)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU time (summed over threads) the oracle baseline runs for, in whole passes")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests in the serving leg (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--B", type=int, default=64)
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--T", type=int, default=20000)
@@ -217,11 +289,19 @@ def main():
     if not args.no_cpu_baseline:
         threads = len(os.sched_getaffinity(0))
         threads = min(threads, 16)
-        log(f"[bench] oracle CPU baseline on {args.cpu_rows} rows x {T} steps, {threads} threads")
-        rate, el, rows = cpu_baseline(w, args.cpu_rows, threads)
+        log(f"[bench] oracle CPU baseline: whole workload, {threads} threads, >= {args.cpu_seconds} CPU-s")
+        rate, el, cpu_s, passes, rows = cpu_baseline(w, args.cpu_seconds, threads)
         cpu = {"value": rate, "unit": "neuron-steps/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {rows} (batch, neuron) rows of the workload, all {T} steps, "
-                         f"forward + backward, {el:.2f} s wall"}
+               "sample": f"the whole workload ({rows} (batch, neuron) rows x {T} steps), forward + "
+                         f"backward, {passes} passes: {el:.2f} s wall, {cpu_s:.1f} CPU-s"}
+
+    serve = None
+    if args.serve_requests > 0:
+        del I, P, Ptgt, gS, fb, bb
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        log(f"[bench] serving: {args.serve_requests} requests at {args.serve_rate}/s")
+        serve = serve_leg(args.serve_requests, args.serve_rate, args.serve_slots, args.serve_budget_gib)
 
     res = {
         "metric": "neuron-steps/s fwd+bwd, block-wise vs sequential ALIF on 1 GPU; p99 latency",
@@ -246,6 +326,7 @@ def main():
         "sequential": seq,
         "speedup_vs_sequential": (value / seq["value"]) if seq else None,
         "cpu_baseline": cpu,
+        "serving": serve,
     }
     print(json.dumps(res), flush=True)
 
