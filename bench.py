@@ -44,6 +44,42 @@ def algorithmic_bytes(TR):
     return {"fwd": 4.0 + 1.0 + 9.0 / TR, "bwd": 8.0 + 9.0 / TR}
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+COUNTERS = os.path.join(HERE, "profiles", "block_fwd_bwd_fine_dt_hbm_counters.md")
+KERNEL_SOURCES = ["alif_blocks.hip", "alif_blocks_impl.h", "alif_blocks_s1.hip", "alif_blocks_s16.hip",
+                  "alif_blocks_s2.hip", "alif_blocks_s4.hip", "alif_blocks_s8.hip", "alif_common.h",
+                  "alif_kernels.h"]
+
+
+def kernel_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(KERNEL_SOURCES):
+        h.update(name.encode())
+        with open(os.path.join(HERE, "paper_2311_11390_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a copy kernel of known size), or {} when the kernel
+    sources have changed since those counters were taken."""
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return {}
+    digest, traffic = None, {}
+    for line in text.splitlines():
+        if line.startswith("kernel_sources_sha256:"):
+            digest = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic_bytes_per_launch:"):
+            for kv in line.split(":", 1)[1].split():
+                k, v = kv.split("=")
+                traffic[k] = float(v)
+    return traffic if digest == kernel_sources_digest() else {}
+
+
 def smoothed_mse_grad(S, S_tgt, sigma_steps):
     """d/dS of mean((G*S - G*S_tgt)^2), G a unit-sum Gaussian (+-4 sigma), 'same'
     convolution along time; computed with torch on the GPU."""
@@ -321,7 +357,9 @@ def main():
                    "batch": B, "neurons": N, "T": T, "dt_ms": w.dt, "arp_ms": w.arp, "T_R": TR,
                    "firing_rate_hz": rate_hz},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": dom["achieved_GBs"],
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["frac_of_peak"], "traffic": None},
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["frac_of_peak"],
+                     "traffic": measured_traffic().get(dom_name),
+                     "algorithmic_bytes_per_launch": dom["bytes_per_launch"]},
         "kernels": {"block_fwd": k_fwd, "block_bwd": k_bwd},
         "sequential": seq,
         "speedup_vs_sequential": (value / seq["value"]) if seq else None,
