@@ -147,7 +147,7 @@ def cpu_baseline(w, cpu_seconds, threads):
     return Irows.size * passes / el, el, cpu, passes, Irows.shape[0]
 
 
-def serve_leg(n_requests, rate_hz, max_slots, budget_gib, seed=1):
+def serve_leg(n_requests, rate_hz, max_slots, budget_gib, output="events", seed=1):
     """Replay a Poisson request stream (uneven N, T and DT; OU current drawn on the
     device) against the library's server in real time, then the same stream
     submitted all at once. Latency = completion - submission on the server's
@@ -160,9 +160,11 @@ def serve_leg(n_requests, rate_hz, max_slots, budget_gib, seed=1):
 
     def req(q):
         lp = synth.request_params(q)
+        TR = int(round(q.arp / q.dt))
+        cap = max(1024, -(-q.T // TR) * q.N // 4) if output == "events" else 0
         return serving.Request(T=q.T, dt=q.dt, arp=q.arp, tau_mem=lp.tau_mem, tau_adapt=lp.tau_adapt,
-                               d=lp.d, theta0=lp.theta0, seed=q.seed,
-                               **{"ou_" + k: v for k, v in synth.REQUEST_OU.items()})
+                               d=lp.d, theta0=lp.theta0, seed=q.seed, want_spikes=output == "raster",
+                               events_capacity=cap, **{"ou_" + k: v for k, v in synth.REQUEST_OU.items()})
 
     reqs = [req(q) for q in stream]
     work = float(sum(q.N * q.T for q in stream))
@@ -170,7 +172,9 @@ def serve_leg(n_requests, rate_hz, max_slots, budget_gib, seed=1):
            "budget_GiB": budget_gib, "neuron_steps": work,
            "stream": "Poisson arrivals; N ~ U{64..2048}, T ~ U{500..50000}, DT in {1, 0.1, 0.05} ms, "
                      "ARP 2 ms; OU current (tau 5 ms, mean 0.8, sd 0.5) drawn on the device; "
-                     "spike trains copied back to host memory"}
+                     + ("spikes returned as event lists (flat t * N + n indices)" if output == "events" else
+                        "spikes returned as dense [T][N] rasters"),
+           "output": output}
     with serving.Server(int(budget_gib * (1 << 30)), max_slots=max_slots) as srv:
         for t in [srv.submit(req(q)) for q in warm]:     # pool and staging warm-up
             srv.wait(t, timeout=120)
@@ -183,7 +187,7 @@ def serve_leg(n_requests, rate_hz, max_slots, budget_gib, seed=1):
                         for tk in list(pending):
                             res = srv.poll(tk)
                             if res is not None:
-                                res.spikes = None
+                                res.spikes = res.events = None
                                 results.append(res)
                                 del pending[tk]
                         time.sleep(2e-4)
@@ -192,11 +196,11 @@ def serve_leg(n_requests, rate_hz, max_slots, budget_gib, seed=1):
                 for tk in list(pending):
                     res = srv.poll(tk)
                     if res is not None:
-                        res.spikes = None
+                        res.spikes = res.events = None
                         results.append(res)
                         del pending[tk]
                 time.sleep(2e-4)
-            bad = [r.status for r in results if r.status != 0]
+            bad = [r.status for r in results if r.status != 0 or r.events_truncated]
             lat = np.array([r.latency for r in results]) * 1e3
             span = max(r.t_done for r in results) - min(r.t_submit for r in results)
             out[mode] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
@@ -222,6 +226,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--serve-output", choices=("events", "raster"), default="events")
     ap.add_argument("--B", type=int, default=64)
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--T", type=int, default=20000)
@@ -337,7 +342,8 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         log(f"[bench] serving: {args.serve_requests} requests at {args.serve_rate}/s")
-        serve = serve_leg(args.serve_requests, args.serve_rate, args.serve_slots, args.serve_budget_gib)
+        serve = serve_leg(args.serve_requests, args.serve_rate, args.serve_slots, args.serve_budget_gib,
+                          args.serve_output)
 
     res = {
         "metric": "neuron-steps/s fwd+bwd, block-wise vs sequential ALIF on 1 GPU; p99 latency",

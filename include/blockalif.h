@@ -292,8 +292,17 @@ enum alif_request_input {
  * One single-layer simulation request (forward only, batch 1). Parameters are
  * host float [N] arrays copied at submit. ALIF_REQ_OU draws the current on the
  * device exactly as alif_ou_current does (with the request's dt_ms, ou_tau_ms,
- * ou_mean, ou_sd and seed). host_current (if used) and host_spikes must stay
- * valid until alif_poll has returned the request's result.
+ * ou_mean, ou_sd and seed).
+ *
+ * Outputs (either, both or neither):
+ *  - host_spikes: the dense uint8 [T][N] spike raster;
+ *  - host_events: the spikes as flat indices t * N + n (uint32, ascending, so
+ *    ordered by step, then neuron), at most events_capacity of them; the result
+ *    says how many spikes there were and whether the list was cut short. At
+ *    these firing rates this is orders of magnitude smaller than the raster, and
+ *    it is what crosses PCIe.
+ * host_current (if used), host_spikes and host_events must stay valid until
+ * alif_poll has returned the request's result.
  */
 typedef struct alif_request {
     int32_t n_neurons;
@@ -305,12 +314,14 @@ typedef struct alif_request {
     const float *host_current; /* ALIF_REQ_HOST_CURRENT: host [T][N] */
     float ou_tau_ms, ou_mean, ou_sd;
     uint64_t seed;
-    uint8_t *host_spikes;      /* host [T][N] output, caller-owned; written before done */
+    uint8_t *host_spikes;      /* host [T][N] raster, caller-owned, nullable */
+    uint32_t *host_events;     /* host [events_capacity] spike indices, caller-owned, nullable */
+    int64_t events_capacity;
 } alif_request;
 
 typedef struct alif_result {
     int32_t status;            /* ALIF_OK, or the request's error */
-    int32_t reserved;
+    int32_t events_truncated;  /* 1 if n_spikes > events_capacity (host_events holds the first ones) */
     int64_t n_spikes;
     double  t_submit_s, t_admit_s, t_done_s; /* server clock (CLOCK_MONOTONIC), seconds */
 } alif_result;

@@ -53,11 +53,12 @@ class AlifRequest(Structure):
                 ("tau_mem_ms", c_void_p), ("tau_adapt_ms", c_void_p), ("d", c_void_p),
                 ("theta0", c_void_p), ("bias", c_void_p), ("input", c_int32),
                 ("host_current", c_void_p), ("ou_tau_ms", c_float), ("ou_mean", c_float),
-                ("ou_sd", c_float), ("seed", c_uint64), ("host_spikes", c_void_p)]
+                ("ou_sd", c_float), ("seed", c_uint64), ("host_spikes", c_void_p),
+                ("host_events", c_void_p), ("events_capacity", c_int64)]
 
 
 class AlifResult(Structure):
-    _fields_ = [("status", c_int32), ("reserved", c_int32), ("n_spikes", c_int64),
+    _fields_ = [("status", c_int32), ("events_truncated", c_int32), ("n_spikes", c_int64),
                 ("t_submit_s", c_double), ("t_admit_s", c_double), ("t_done_s", c_double)]
 
 

@@ -8,10 +8,11 @@
 // work of requests that arrive while others are running overlaps on the device:
 //   device allocation (stream-ordered) -> parameters H2D -> input current
 //   (H2D from the slot's pinned staging, or OU drawn on the device) ->
-//   block-wise forward (the kernels behind alif_forward) -> spike count ->
-//   spikes D2H into the slot's pinned staging -> free -> completion event.
-// When the event has fired, the scheduler copies the spikes into the caller's
-// buffer, releases the slot and the budget, and files the result for
+//   block-wise forward (the kernels behind alif_forward) -> spike compaction
+//   (count, scan, and a scatter of the spike indices straight into the slot's
+//   pinned event staging) -> raster D2H if asked for -> free -> completion event.
+// When the event has fired, the scheduler copies the results into the caller's
+// buffers, releases the slot and the budget, and files the result for
 // alif_poll. Every bulk host buffer the device touches is pinned: an async copy
 // to pageable memory would block the scheduler thread until the copy ran, which
 // would serialise the requests.
@@ -160,12 +161,117 @@ hipError_t ou_launch(int T, int N, double dt, float tau, float mean, float sd, u
     return hipGetLastError();
 }
 
-__global__ void k_count_spikes(const uint8_t *s, size_t n, unsigned long long *out) {
-    unsigned long long c = 0;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        c += s[i];
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+// ---------------------------------------------------------------------------
+// spike-raster compaction: count per chunk -> exclusive scan -> scatter. The
+// events come out in ascending flat index (t * N + n), the same on every run.
+// ---------------------------------------------------------------------------
+constexpr int CMP_THREADS = 256;
+constexpr int CMP_BYTES = 32;                                   // raster bytes per thread
+constexpr size_t CMP_CHUNK = (size_t)CMP_THREADS * CMP_BYTES;   // raster bytes per workgroup
+
+// spikes among this thread's 32 raster bytes (each byte is 0 or 1)
+__device__ __forceinline__ int thread_spikes(const uint8_t *s, size_t n, size_t i0, uint32_t w[8]) {
+    if (i0 + CMP_BYTES <= n) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(s + i0);   // 32-byte aligned
+        const uint4 a = p[0], b = p[1];
+        w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+        w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            uint32_t v = 0;
+            for (int j = 0; j < 4; j++) {
+                const size_t i = i0 + 4 * k + j;
+                if (i < n) v |= (uint32_t)(s[i] != 0) << (8 * j);
+            }
+            w[k] = v;
+        }
+    }
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) c += __popc(w[k] & 0x01010101u);
+    return c;
+}
+
+// exclusive prefix over the workgroup's threads; returns the workgroup total in *total
+__device__ __forceinline__ int block_exclusive_scan(int v, int *lds, int *total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) lds[wv] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < CMP_THREADS / 64; k++) {
+        base += k < wv ? lds[k] : 0;
+        tot += lds[k];
+    }
+    *total = tot;
+    return base + x - v;
+}
+
+__global__ __launch_bounds__(CMP_THREADS) void k_cmp_count(const uint8_t *s, size_t n, uint32_t *counts) {
+    __shared__ int lds[CMP_THREADS / 64];
+    uint32_t w[8];
+    const size_t i0 = (size_t)blockIdx.x * CMP_CHUNK + (size_t)threadIdx.x * CMP_BYTES;
+    int tot;
+    block_exclusive_scan(thread_spikes(s, n, i0, w), lds, &tot);
+    if (threadIdx.x == 0) counts[blockIdx.x] = (uint32_t)tot;
+}
+
+// one workgroup: offsets[g] = sum of counts[0..g), *total = sum of all
+__global__ __launch_bounds__(1024) void k_cmp_scan(const uint32_t *counts, uint32_t G, uint32_t *offsets,
+                                                   unsigned long long *total) {
+    __shared__ int lds[16];
+    const uint32_t per = (G + 1023) / 1024;
+    const uint32_t g0 = threadIdx.x * per, g1 = min(G, g0 + per);
+    uint32_t mine = 0;
+    for (uint32_t g = g0; g < g1; g++) mine += counts[g];
+    // workgroup scan of the per-thread sums (16 waves)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t x = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) lds[wv] = (int)x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int k = 0; k < 16; k++) {
+        base += k < wv ? (uint32_t)lds[k] : 0u;
+        tot += (uint32_t)lds[k];
+    }
+    uint32_t run = base + x - mine;
+    for (uint32_t g = g0; g < g1; g++) {
+        offsets[g] = run;
+        run += counts[g];
+    }
+    if (threadIdx.x == 0) *total = tot;
+}
+
+__global__ __launch_bounds__(CMP_THREADS) void k_cmp_scatter(const uint8_t *s, size_t n, const uint32_t *offsets,
+                                                             uint32_t *events, uint32_t cap) {
+    __shared__ int lds[CMP_THREADS / 64];
+    uint32_t w[8];
+    const size_t i0 = (size_t)blockIdx.x * CMP_CHUNK + (size_t)threadIdx.x * CMP_BYTES;
+    int tot;
+    const int c = thread_spikes(s, n, i0, w);
+    uint32_t pos = offsets[blockIdx.x] + (uint32_t)block_exclusive_scan(c, lds, &tot);
+    if (c == 0) return;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        uint32_t m = w[k] & 0x01010101u;
+        while (m) {
+            const int bit = __ffs(m) - 1;
+            if (pos < cap) events[pos] = (uint32_t)(i0 + 4 * k + (bit >> 3));
+            pos++;
+            m &= m - 1;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -176,7 +282,8 @@ double now_s() {
 }
 
 struct Layout {   // offsets into a request's one device allocation
-    size_t prm, cur, spk, ends, cnt, total;
+    size_t prm, cur, spk, ends, counts, offsets, cnt, total;
+    uint32_t chunks;   // compaction workgroups
 };
 Layout layout(const alif_request &r) {
     Layout l;
@@ -186,6 +293,9 @@ Layout layout(const alif_request &r) {
     l.cur = o; o += a256(T * N * sizeof(float));
     l.spk = o; o += a256(T * N);
     l.ends = o; o += r.input == ALIF_REQ_OU ? a256(ou_chunks((int)T) * N * sizeof(double)) : 0;
+    l.chunks = (uint32_t)((T * N + CMP_CHUNK - 1) / CMP_CHUNK);
+    l.counts = o; o += a256((size_t)l.chunks * 4);
+    l.offsets = o; o += a256((size_t)l.chunks * 4);
     l.cnt = o; o += 256;
     l.total = o;
     return l;
@@ -194,6 +304,7 @@ Layout layout(const alif_request &r) {
 struct Req {
     uint64_t ticket = 0;
     alif_request r{};
+    uint32_t ev_cap = 0;       // events the scatter may write (<= the caller's capacity)
     std::vector<float> prm;    // tau_mem | tau_adapt | d | theta0 | bias, each [N]
     bool has_bias = false;
     int TR = 0;
@@ -208,8 +319,9 @@ struct Slot {
     Req *q = nullptr;
     float *h_in = nullptr;   // pinned staging, grown on demand
     uint8_t *h_out = nullptr;
+    uint32_t *h_ev = nullptr;   // written by the scatter kernel through its device mapping
     unsigned long long *h_cnt = nullptr;
-    size_t cap_in = 0, cap_out = 0;
+    size_t cap_in = 0, cap_out = 0, cap_ev = 0;
 };
 
 }  // namespace
@@ -252,10 +364,16 @@ int start_request(alif_server *s, Slot &sl) {
     const int N = r.n_neurons, T = r.T;
     const size_t TN = (size_t)T * N;
     hipStream_t st = sl.st;
-    hipError_t e = grow_pinned((void **)&sl.h_out, &sl.cap_out, std::max<size_t>(TN, 1));
+    hipError_t e = hipSuccess;
+    if (r.host_spikes) e = grow_pinned((void **)&sl.h_out, &sl.cap_out, std::max<size_t>(TN, 1));
+    if (e == hipSuccess && q->ev_cap > 0)
+        e = grow_pinned((void **)&sl.h_ev, &sl.cap_ev, (size_t)q->ev_cap * sizeof(uint32_t));
     if (e == hipSuccess && r.input == ALIF_REQ_HOST_CURRENT)
         e = grow_pinned((void **)&sl.h_in, &sl.cap_in, std::max<size_t>(TN * sizeof(float), 1));
     if (e != hipSuccess) return set_error(ALIF_ENOMEM, "pinned staging allocation failed");
+    uint32_t *ev_dev = nullptr;   // the events staging as the device sees it
+    if (q->ev_cap > 0 && hipHostGetDevicePointer((void **)&ev_dev, sl.h_ev, 0) != hipSuccess)
+        return set_error(ALIF_EHIP, "no device mapping of the pinned event staging");
     e = hipMallocAsync((void **)&q->dmem, q->lay.total, st);
     if (e != hipSuccess) {
         q->dmem = nullptr;
@@ -292,8 +410,14 @@ int start_request(alif_server *s, Slot &sl) {
             e = launch_blocks_fwd(a, st);
         }
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_count_spikes, dim3((unsigned)std::min<size_t>((TN + 255) / 256, 1024)),
-                               dim3(256), 0, st, spk, TN, cnt);
+            uint32_t *counts = (uint32_t *)(q->dmem + q->lay.counts);
+            uint32_t *offsets = (uint32_t *)(q->dmem + q->lay.offsets);
+            const unsigned G = q->lay.chunks;
+            hipLaunchKernelGGL(k_cmp_count, dim3(G), dim3(CMP_THREADS), 0, st, spk, TN, counts);
+            hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(1024), 0, st, counts, G, offsets, cnt);
+            if (q->ev_cap > 0)
+                hipLaunchKernelGGL(k_cmp_scatter, dim3(G), dim3(CMP_THREADS), 0, st, spk, TN, offsets, ev_dev,
+                                   q->ev_cap);
             e = hipGetLastError();
         }
         if (e == hipSuccess && r.host_spikes) e = hipMemcpyAsync(sl.h_out, spk, TN, hipMemcpyDeviceToHost, st);
@@ -312,7 +436,12 @@ void finish(alif_server *s, Slot &sl, int status) {
     if (status == ALIF_OK) {
         const size_t TN = (size_t)q->r.T * q->r.n_neurons;
         if (q->r.host_spikes && TN) std::memcpy(q->r.host_spikes, sl.h_out, TN);
-        q->res.n_spikes = (int64_t)*sl.h_cnt;
+        q->res.n_spikes = TN ? (int64_t)*sl.h_cnt : 0;
+        if (q->ev_cap > 0) {
+            const size_t k = std::min<size_t>((size_t)q->res.n_spikes, q->ev_cap);
+            std::memcpy(q->r.host_events, sl.h_ev, k * sizeof(uint32_t));
+        }
+        q->res.events_truncated = q->r.host_events && q->res.n_spikes > q->r.events_capacity;
     }
     q->res.status = status;
     q->res.t_done_s = now_s();
@@ -383,6 +512,7 @@ int validate(const alif_request *r, int *TR) {
         return set_error(ALIF_EINVAL, "request: parameter arrays are required");
     if (r->input != ALIF_REQ_HOST_CURRENT && r->input != ALIF_REQ_OU)
         return set_error(ALIF_EINVAL, "request: unknown input kind");
+    if (r->events_capacity < 0) return set_error(ALIF_EINVAL, "request: events_capacity < 0");
     if (r->input == ALIF_REQ_HOST_CURRENT && !r->host_current && r->T > 0)
         return set_error(ALIF_EINVAL, "request: host_current is NULL");
     if (r->input == ALIF_REQ_OU) {
@@ -408,6 +538,7 @@ void destroy_slots(alif_server *s) {
         }
         if (sl.h_in) hipHostFree(sl.h_in);
         if (sl.h_out) hipHostFree(sl.h_out);
+        if (sl.h_ev) hipHostFree(sl.h_ev);
         if (sl.h_cnt) hipHostFree(sl.h_cnt);
     }
     s->slots.clear();
@@ -508,6 +639,11 @@ int alif_submit(alif_server *s, const alif_request *req, uint64_t *ticket) {
     q->r = *req;
     q->TR = TR;
     q->lay = layout(*req);
+    if (req->host_events && req->events_capacity > 0) {
+        // at most one spike per neuron in each T_R-step block
+        const size_t bound = (size_t)((req->T + TR - 1) / TR) * (size_t)req->n_neurons;
+        q->ev_cap = (uint32_t)std::min<size_t>((size_t)req->events_capacity, bound);
+    }
     if (q->lay.total > s->budget) {
         delete q;
         return set_error(ALIF_EBUDGET, "request footprint exceeds the server's HBM budget");

@@ -30,7 +30,8 @@ class Request:
     ou_mean: float = 0.8
     ou_sd: float = 0.5
     seed: int = 0
-    want_spikes: bool = True
+    want_spikes: bool = True        # dense uint8 [T][N] raster
+    events_capacity: int = 0        # > 0: also the spikes as flat indices t * N + n
 
     @property
     def N(self) -> int:
@@ -42,6 +43,8 @@ class Result:
     status: int
     n_spikes: int
     spikes: np.ndarray | None     # uint8 [T][N]
+    events: np.ndarray | None     # uint32 flat indices t * N + n, ascending
+    events_truncated: bool
     t_submit: float
     t_admit: float
     t_done: float
@@ -68,6 +71,7 @@ def c_request(r: Request):
         if cur.shape != (r.T, N):
             raise ValueError(f"current must have shape ({r.T}, {N})")
     spk = np.empty((r.T, N), dtype=np.uint8) if r.want_spikes else None
+    ev = np.empty(int(r.events_capacity), dtype=np.uint32) if r.events_capacity > 0 else None
 
     def ptr(a):
         return None if a is None else a.ctypes.data
@@ -77,8 +81,9 @@ def c_request(r: Request):
                       d=ptr(arrs["d"]), theta0=ptr(arrs["theta0"]), bias=ptr(arrs["bias"]),
                       input=L.REQ_HOST_CURRENT if cur is not None else L.REQ_OU,
                       host_current=ptr(cur), ou_tau_ms=r.ou_tau, ou_mean=r.ou_mean,
-                      ou_sd=r.ou_sd, seed=r.seed & (2**64 - 1), host_spikes=ptr(spk))
-    return c, (arrs, cur, spk)
+                      ou_sd=r.ou_sd, seed=r.seed & (2**64 - 1), host_spikes=ptr(spk),
+                      host_events=ptr(ev), events_capacity=int(r.events_capacity))
+    return c, (arrs, cur, spk, ev)
 
 
 def footprint(r: Request) -> int:
@@ -113,8 +118,11 @@ class Server:
         if rc == L.ALIF_PENDING:
             return None
         keep = self._keep.pop(ticket, None)
-        spk = keep[2] if keep is not None else None
-        return Result(res.status, res.n_spikes, spk, res.t_submit_s, res.t_admit_s, res.t_done_s)
+        spk, ev = (keep[2], keep[3]) if keep is not None else (None, None)
+        if ev is not None:
+            ev = ev[:min(res.n_spikes, ev.shape[0])]
+        return Result(res.status, res.n_spikes, spk, ev, bool(res.events_truncated), res.t_submit_s,
+                      res.t_admit_s, res.t_done_s)
 
     def wait(self, ticket: int, timeout: float = 60.0, interval: float = 1e-4) -> Result:
         end = time.monotonic() + timeout

@@ -41,6 +41,8 @@ int main(void) {
          sizeof(alif_request), sizeof(alif_result));
   printf("%zu %zu %zu %zu\\n", offsetof(alif_desc, dt_ms), offsetof(alif_desc, sg_slope),
          offsetof(alif_request, seed), offsetof(alif_request, host_spikes));
+  printf("%zu %zu %zu\\n", offsetof(alif_request, host_events), offsetof(alif_request, events_capacity),
+         offsetof(alif_result, n_spikes));
   return 0;
 }""")
     exe = tmp_path / "layout"
@@ -50,7 +52,8 @@ int main(void) {
     py = [ctypes.sizeof(L.AlifDesc), ctypes.sizeof(L.AlifParams), ctypes.sizeof(L.AlifState),
           ctypes.sizeof(L.AlifRequest), ctypes.sizeof(L.AlifResult),
           L.AlifDesc.dt_ms.offset, L.AlifDesc.sg_slope.offset, L.AlifRequest.seed.offset,
-          L.AlifRequest.host_spikes.offset]
+          L.AlifRequest.host_spikes.offset, L.AlifRequest.host_events.offset,
+          L.AlifRequest.events_capacity.offset, L.AlifResult.n_spikes.offset]
     assert c == py
 
 
@@ -110,8 +113,9 @@ def test_serving_footprint_and_validation_host_side():
     from paper_2311_11390_amd import serving
     N, T = 100, 1000
     fp = serving.footprint(_request(N, T))
-    nc = -(-T // 256)
-    want = sum(-(-x // 256) * 256 for x in (5 * N * 4, T * N * 4, T * N, nc * N * 8)) + 256
+    nc = -(-T // 256)                    # OU chunks of 256 steps
+    g = -(-(T * N) // 8192)              # raster compaction workgroups
+    want = sum(-(-x // 256) * 256 for x in (5 * N * 4, T * N * 4, T * N, nc * N * 8, g * 4, g * 4)) + 256
     assert fp == want
     fp_host = serving.footprint(_request(N, T, current=np.zeros((T, N), np.float32)))
     assert fp_host == want - (-(-nc * N * 8 // 256) * 256)
@@ -125,6 +129,7 @@ def test_serving_footprint_and_validation_host_side():
         dict(theta0=np.full(N, np.nan)),
         dict(ou_tau=0.0),
         dict(ou_sd=-1.0),
+        dict(events_capacity=-1),
     ]
     for kw in bad:
         with pytest.raises(L.AlifError) as ei:

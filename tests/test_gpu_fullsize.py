@@ -1,0 +1,287 @@
+"""Parity at the workloads' full sizes, in the launch configurations the benchmark
+and the workloads use. The GPU runs every config at its full shape; the FP64
+oracle checks sampled outputs it can afford one by one (whole (batch, neuron)
+rows: neurons are independent given their input, and batch samples are
+independent through every layer) plus properties that hold at any size over the
+whole output. Each test logs a "[report]" line with the spike counts, excused
+near-threshold flips, +-1-step coincidence and trace / gradient errors of its
+config."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import log, np_, to_dev
+from oracle import ou_philox
+from parity import GRAD_TOL, check_forward, check_grad, coincidence, teacher_forced_forward
+from paper_2311_11390_amd.synth import LayerParams, rng
+
+pytestmark = pytest.mark.gpu
+
+
+def _isi_ok(S, TR):
+    """Every inter-spike interval of every (batch, neuron) row is >= T_R (at most
+    one spike per refractory period, Eq. 4), checked over the whole output."""
+    S = np.asarray(S)
+    B, T, N = S.shape
+    b, t, n = np.nonzero(S)
+    order = np.lexsort((t, n, b))
+    b, t, n = b[order], t[order], n[order]
+    same = (b[1:] == b[:-1]) & (n[1:] == n[:-1])
+    isi = (t[1:] - t[:-1])[same]
+    return int(isi.min()) if isi.size else None, int(S.sum())
+
+
+def _sub(lp, idx):
+    return LayerParams(lp.tau_mem[idx], lp.tau_adapt[idx], lp.d[idx], lp.theta0[idx],
+                       None if lp.bias is None else lp.bias[idx])
+
+
+def test_fine_dt_fit_full_size():
+    """64 x 256 neurons, T = 20000, DT = 0.05 ms (T_R = 40), OU current: the
+    benchmark's workload and launch. Whole output: ISI >= T_R. 32 sampled
+    neurons x all 64 batch rows: spikes (teacher-forced), and the per-neuron
+    gradients, which sum over the whole batch, against the oracle's adjoint."""
+    import torch
+
+    from paper_2311_11390_amd import alif
+    from paper_2311_11390_amd.synth import fine_dt_fit
+    w = fine_dt_fit(seed=0)
+    I, lp = w.inputs["I"], w.layers[0]
+    B, T, N = I.shape
+    TR = alif.refractory_steps(w.dt, w.arp)
+    gS = rng(77).standard_normal((B, T, N), dtype=np.float32)
+    log(f"[full] fine-DT fit B={B} N={N} T={T} T_R={TR}")
+    It = torch.as_tensor(I, device="cuda")
+    P = to_dev(lp)
+    f = alif.forward(It, P, w.dt, w.arp, save=True)
+    out = alif.backward(f, It, P, grad_spikes=torch.as_tensor(gS, device="cuda"))
+    torch.cuda.synchronize()
+    S = np_(f["spikes"])
+    isi_min, n_sp = _isi_ok(S, TR)
+    assert n_sp > 0 and isi_min >= TR
+    ns = np.sort(rng(5).choice(N, 32, replace=False))
+    rep = check_forward(S[:, :, ns], I[:, :, ns], _sub(lp, ns), w.dt, w.arp)
+    ob = oracle.alif_backward(rep["oracle"], w.dt, 10.0, gS=gS[:, :, ns], want_gI=False)
+    errs = {k: check_grad("grad_" + k, np_(out["grad_" + k])[ns], ob[o])["rel_l2"]
+            for k, o in (("tau_mem", "g_tau_m"), ("tau_adapt", "g_tau_a"), ("d", "g_d"), ("theta0", "g_theta0"))}
+    log(f"[report] fine-DT fit full: spikes {n_sp} (rate {n_sp / (B * N * T * w.dt * 1e-3):.2f} Hz), "
+        f"min ISI {isi_min}; sampled 32 neurons x 64: spikes {rep['n_spikes']}, excused {rep['excused']}; "
+        "grad rel L2 " + " ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+
+
+@pytest.mark.parametrize("driven", [False, True])
+def test_shd_like_training_full_size(driven):
+    """700 -> 512 ALIF -> 20 readout, B = 32, T = 1000, DT = 1 ms, cross-entropy
+    through torch.autograd with the library's ops; every output and gradient
+    against the oracle chain. As specified the hidden layer never fires (Eq. 2's
+    normalised membrane); the driven variant adds a bias so that it does."""
+    import torch
+
+    from paper_2311_11390_amd import alif
+    from paper_2311_11390_amd.synth import shd_like_training
+    w = shd_like_training(seed=3, driven=driven)
+    x, W, lp = w.inputs["x"], w.weights[0], w.layers[0]
+    Wr, taur, labels = w.extra["readout_W"], w.extra["readout_tau"], w.inputs["labels"]
+    B, T, n_in = x.shape
+    log(f"[full] SHD-like training step driven={driven} B={B} T={T}")
+    dev = "cuda"
+    xt = torch.as_tensor(x, device=dev)
+    Wt = torch.as_tensor(W, device=dev).requires_grad_()
+    names = ("tau_mem", "tau_adapt", "d", "theta0", "bias")
+    bias = lp.bias if lp.bias is not None else np.zeros(W.shape[0], np.float32)
+    vals = {"tau_mem": lp.tau_mem, "tau_adapt": lp.tau_adapt, "d": lp.d, "theta0": lp.theta0, "bias": bias}
+    P = {k: torch.as_tensor(vals[k], device=dev).requires_grad_() for k in names}
+    Wrt = torch.as_tensor(Wr, device=dev).requires_grad_()
+    trt = torch.as_tensor(taur, device=dev).requires_grad_()
+    S, _, _ = alif.BlockALIF.apply(xt, Wt, P["tau_mem"], P["tau_adapt"], P["d"], P["theta0"], P["bias"],
+                                   {"dt": w.dt, "arp": w.arp})
+    o = alif.Readout.apply(S, Wrt, trt, w.dt)
+    loss = torch.nn.functional.cross_entropy(o, torch.as_tensor(labels, device=dev))
+    loss.backward()
+    torch.cuda.synchronize()
+    I64 = oracle.input_current(x, W, bias)
+    S_gpu = S.detach().cpu().numpy()
+    orc, exc = teacher_forced_forward(S_gpu, I64, lp.tau_mem, lp.tau_adapt, lp.d, lp.theta0, w.dt, w.arp)
+    S64 = orc["S"].astype(np.float64)
+    Ir = S64.reshape(-1, S64.shape[2]) @ Wr.astype(np.float64).T
+    Ir = Ir.reshape(B, T, -1)
+    ro = oracle.readout_forward(Ir, taur, w.dt)
+    np.testing.assert_allclose(o.detach().cpu().numpy(), ro["o"], rtol=1e-4, atol=1e-3)
+    l_ref, go = oracle.softmax_cross_entropy(ro["o"], labels)
+    assert abs(loss.item() - l_ref) < 1e-4
+    rb = oracle.readout_backward(Ir, taur, w.dt, go)
+    gS = (rb["gIr"].reshape(B * T, -1) @ Wr.astype(np.float64)).reshape(B, T, -1)
+    ob = oracle.alif_backward(orc, w.dt, 10.0, gS=gS)
+    gI = ob["gI"].reshape(B * T, -1)
+    errs = {
+        "W_r": check_grad("grad_W_r", Wrt.grad.cpu().numpy(), rb["gIr"].reshape(B * T, -1).T @ S64.reshape(B * T, -1)),
+        "tau_r": check_grad("grad_tau_r", trt.grad.cpu().numpy(), rb["g_tau_r"]),
+        "W": check_grad("grad_W", Wt.grad.cpu().numpy(), gI.T @ x.reshape(B * T, -1).astype(np.float64)),
+        "tau_mem": check_grad("grad_tau_mem", P["tau_mem"].grad.cpu().numpy(), ob["g_tau_m"]),
+        "tau_adapt": check_grad("grad_tau_adapt", P["tau_adapt"].grad.cpu().numpy(), ob["g_tau_a"]),
+        "d": check_grad("grad_d", P["d"].grad.cpu().numpy(), ob["g_d"]),
+        "theta0": check_grad("grad_theta0", P["theta0"].grad.cpu().numpy(), ob["g_theta0"]),
+        "bias": check_grad("grad_bias", P["bias"].grad.cpu().numpy(), ob["gI"].sum(axis=(0, 1))),
+    }
+    n_sp = int(S_gpu.sum())
+    assert (n_sp > 0) == driven
+    log(f"[report] SHD-like full driven={driven}: spikes {n_sp}, excused {exc}, loss {loss.item():.6f} "
+        f"(oracle {l_ref:.6f}); grad rel L2 " + " ".join(f"{k} {v['rel_l2']:.1e}" for k, v in errs.items()))
+
+
+def _three_layer_gpu(x, Ws, lps, dt, arp, prec, want_v):
+    """Forward through the three layers, then the backward chain of loss = sum of
+    the last layer's spikes (each layer's input gradient is the gradient of the
+    spikes of the layer below)."""
+    import torch
+
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif
+    h = torch.as_tensor(x, device="cuda")
+    fs, ins, Ps, Wts = [], [], [], []
+    for W, lp in zip(Ws, lps):
+        Wt = torch.as_tensor(W, device="cuda")
+        P = to_dev(lp)
+        f = alif.forward(h, P, dt, arp, Wt, gemm_precision=prec, spike_dtype=L.SPIKES_U8, want_v=want_v,
+                         save=True)
+        fs.append(f)
+        ins.append(h)
+        Ps.append(P)
+        Wts.append(Wt)
+        h = f["spikes"]
+    g = torch.ones(h.shape, dtype=torch.float32, device="cuda")
+    grads = [None] * len(Ws)
+    for li in reversed(range(len(Ws))):
+        grads[li] = alif.backward(fs[li], ins[li], Ps[li], Wts[li], grad_spikes=g, want_grad_current=True,
+                                  want_grad_input=li > 0, want_grad_W=True)
+        g = grads[li]["grad_input"] if li > 0 else None
+    torch.cuda.synchronize()
+    return fs, grads
+
+
+@pytest.mark.parametrize("driven", [False, True])
+def test_three_layer_precision_form_full_size(driven):
+    """700 -> 1024 -> 1024 -> 20, B = 128, T = 2000, DT = 0.5 ms (T_R = 4), loss =
+    sum of the last layer's spikes; FP32-GEMM and BF16-GEMM paths at full size.
+    Four sampled batch rows through all three layers against the oracle chain:
+    FP32 path spikes (teacher-forced), membrane traces and per-step current
+    gradients; BF16 path spike coincidence and errors against the same oracle.
+    The full batch is checked for ISI >= T_R in every layer."""
+    from paper_2311_11390_amd import alif
+    from paper_2311_11390_amd.synth import three_layer
+    w = three_layer(seed=4, driven=driven)
+    x, Ws, lps = w.inputs["x"], w.weights, w.layers
+    B, T, _ = x.shape
+    TR = alif.refractory_steps(w.dt, w.arp)
+    import torch
+    bs = np.array([0, 37, 64, 127])
+    bt = torch.as_tensor(bs, device="cuda")
+    sel = lambda t: np_(t.index_select(0, bt))
+    log(f"[full] three-layer driven={driven} B={B} T={T} FP32 GEMM")
+    f32, g32 = _three_layer_gpu(x, Ws, lps, w.dt, w.arp, 0, True)
+    S32 = [sel(f["spikes"]) for f in f32]
+    V32 = [sel(f["v"]) for f in f32]
+    gI32 = [sel(g["grad_current"]) for g in g32]
+    counts32 = [_isi_ok(np_(f["spikes"]), TR) for f in f32]
+    dW32 = [np_(g["grad_W"]) for g in g32]
+    del f32, g32
+    log(f"[full] three-layer driven={driven} BF16 GEMM")
+    fbf, gbf = _three_layer_gpu(x, Ws, lps, w.dt, w.arp, 1, True)
+    Sbf = [sel(f["spikes"]) for f in fbf]
+    Vbf = [sel(f["v"]) for f in fbf]
+    gIbf = [sel(g["grad_current"]) for g in gbf]
+    countsbf = [_isi_ok(np_(f["spikes"]), TR) for f in fbf]
+    dWbf = [np_(g["grad_W"]) for g in gbf]
+    del fbf, gbf
+    for (isi, n), (isib, nb) in zip(counts32, countsbf):
+        assert isi is None or isi >= TR
+        assert isib is None or isib >= TR
+    # oracle chain on the sampled rows, teacher-forced to the FP32 path
+    h = x[bs]
+    orcs = []
+    lines = []
+    for li, (W, lp) in enumerate(zip(Ws, lps)):
+        I64 = oracle.input_current(np.asarray(h, np.uint8), W, lp.bias)
+        orc, exc = teacher_forced_forward(S32[li], I64, lp.tau_mem, lp.tau_adapt, lp.d, lp.theta0, w.dt, w.arp)
+        dv32 = float(np.abs(V32[li] - orc["V"]).max())
+        assert dv32 <= 1e-4
+        orc_free = oracle.alif_forward(I64, lp.tau_mem, lp.tau_adapt, lp.d, lp.theta0, w.dt, w.arp)
+        co_bf = coincidence(Sbf[li], orc_free["S"])
+        dvbf = np.abs(Vbf[li] - orc_free["V"])
+        lines.append(f"L{li + 1}: spikes fp32 {int(S32[li].sum())} (full batch {counts32[li][1]}), excused {exc}, "
+                     f"max|dV| {dv32:.1e}; bf16 coincidence {co_bf:.4f}, |dV| max {dvbf.max():.2e} "
+                     f"mean {dvbf.mean():.2e}")
+        orcs.append(orc)
+        h = orc["S"]
+        if driven:
+            assert co_bf > 0.8
+    # backward chain: loss = sum of the last layer's spikes
+    gS = np.ones(orcs[-1]["S"].shape)
+    for li in reversed(range(len(Ws))):
+        ob = oracle.alif_backward(orcs[li], w.dt, 10.0, gS=gS)
+        e32 = check_grad(f"L{li + 1} grad_current", gI32[li], ob["gI"])
+        den = np.linalg.norm(ob["gI"]) or 1.0
+        ebf = float(np.linalg.norm(gIbf[li] - ob["gI"]) / den)
+        rw = float(np.linalg.norm(dWbf[li] - dW32[li]) / (np.linalg.norm(dW32[li]) or 1.0))
+        lines.append(f"L{li + 1} grad: fp32 rel L2 {e32['rel_l2']:.1e}; bf16 rel L2 {ebf:.1e}; "
+                     f"bf16 vs fp32 dW (full batch) {rw:.1e}")
+        gS = (ob["gI"].reshape(-1, ob["gI"].shape[2]) @ Ws[li].astype(np.float64)).reshape(
+            ob["gI"].shape[0], ob["gI"].shape[1], -1)
+    log(f"[report] three-layer full driven={driven}: " + "; ".join(lines))
+
+
+def test_three_layer_sampled_batch_weight_grads():
+    """The same network on the four sampled rows alone (B = 4, T = 2000): weight
+    and parameter gradients, which sum over the batch, against the oracle."""
+    from paper_2311_11390_amd.synth import three_layer
+    w = three_layer(seed=4, driven=True)
+    bs = np.array([0, 37, 64, 127])
+    x, Ws, lps = np.ascontiguousarray(w.inputs["x"][bs]), w.weights, w.layers
+    log("[full] three-layer B=4 weight gradients")
+    fs, gs = _three_layer_gpu(x, Ws, lps, w.dt, w.arp, 0, False)
+    h = x
+    orcs = []
+    for li, (W, lp) in enumerate(zip(Ws, lps)):
+        I64 = oracle.input_current(np.asarray(h, np.uint8), W, lp.bias)
+        orc, _ = teacher_forced_forward(np_(fs[li]["spikes"]), I64, lp.tau_mem, lp.tau_adapt, lp.d, lp.theta0,
+                                        w.dt, w.arp)
+        orcs.append((orc, np.asarray(h, np.float64)))
+        h = orc["S"]
+    gS = np.ones(orcs[-1][0]["S"].shape)
+    errs = []
+    for li in reversed(range(len(Ws))):
+        orc, xin = orcs[li]
+        ob = oracle.alif_backward(orc, w.dt, 10.0, gS=gS)
+        gI = ob["gI"].reshape(-1, ob["gI"].shape[2])
+        errs.append(check_grad(f"L{li + 1} grad_W", np_(gs[li]["grad_W"]), gI.T @ xin.reshape(-1, xin.shape[2])))
+        for k, o in (("tau_mem", "g_tau_m"), ("tau_adapt", "g_tau_a"), ("d", "g_d"), ("theta0", "g_theta0")):
+            errs.append(check_grad(f"L{li + 1} grad_{k}", np_(gs[li]["grad_" + k]), ob[o]))
+        gS = (gI @ Ws[li].astype(np.float64)).reshape(ob["gI"].shape[0], ob["gI"].shape[1], -1)
+    log(f"[report] three-layer B=4 gradients: max rel L2 {max(e['rel_l2'] for e in errs):.1e} (bound {GRAD_TOL})")
+
+
+def test_serving_requests_full_size():
+    """The first four requests of the serving stream at their real sizes (up to
+    1920 neurons x 42942 steps, DT 1 / 0.05 / 0.1 ms), served concurrently,
+    each against the oracle on the oracle's own OU current."""
+    from paper_2311_11390_amd import serving
+    from paper_2311_11390_amd.synth import REQUEST_OU, request_params, request_stream
+    reqs = request_stream(seed=0, n=4)
+    prms = [request_params(q) for q in reqs]
+    log("[full] serving " + ", ".join(f"N={q.N} T={q.T} dt={q.dt}" for q in reqs))
+    with serving.Server(8 << 30, max_slots=4) as srv:
+        tickets = [srv.submit(serving.Request(T=q.T, dt=q.dt, arp=q.arp, tau_mem=p.tau_mem, tau_adapt=p.tau_adapt,
+                                              d=p.d, theta0=p.theta0, seed=q.seed,
+                                              **{"ou_" + k: v for k, v in REQUEST_OU.items()}))
+                   for q, p in zip(reqs, prms)]
+        res = [srv.wait(t, timeout=120) for t in tickets]
+    lines = []
+    for q, p, r in zip(reqs, prms, res):
+        assert r.status == 0
+        I32, _ = ou_philox.ou_current(q.T, q.N, q.dt, REQUEST_OU["tau"], REQUEST_OU["mean"], REQUEST_OU["sd"],
+                                      q.seed)
+        rep = check_forward(r.spikes[None], I32[None], p, q.dt, q.arp)
+        lines.append(f"N={q.N} T={q.T} dt={q.dt}: spikes {r.n_spikes}, excused {rep['excused']}, "
+                     f"latency {r.latency * 1e3:.1f} ms")
+        del I32, rep
+    log("[report] serving full-size requests: " + "; ".join(lines))

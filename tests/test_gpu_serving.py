@@ -48,11 +48,11 @@ def _params(N, seed):
     return random_params(seed, N, tm=(10.0, 30.0), ta=(100.0, 300.0), d=(0.0, 1.8), th=(0.9, 1.1))
 
 
-def _req(prm, T, dt, arp=2.0, current=None, seed=0):
+def _req(prm, T, dt, arp=2.0, current=None, seed=0, events=0, raster=True):
     from paper_2311_11390_amd.serving import Request
     return Request(T=T, dt=dt, arp=arp, tau_mem=prm.tau_mem, tau_adapt=prm.tau_adapt, d=prm.d,
-                   theta0=prm.theta0, bias=prm.bias, current=current, seed=seed, **{
-                       "ou_" + k: v for k, v in REQUEST_OU.items()})
+                   theta0=prm.theta0, bias=prm.bias, current=current, seed=seed, want_spikes=raster,
+                   events_capacity=events, **{"ou_" + k: v for k, v in REQUEST_OU.items()})
 
 
 def _forward_spikes(I, prm, dt, arp=2.0):
@@ -103,10 +103,10 @@ def _mix(n=14, seed=3):
     return [(q, request_params(q)) for q in reqs]
 
 
-def _run(srv, mix, stagger=0.0):
+def _run(srv, mix, stagger=0.0, events=0):
     tickets = []
     for q, prm in mix:
-        tickets.append(srv.submit(_req(prm, q.T, q.dt, seed=q.seed)))
+        tickets.append(srv.submit(_req(prm, q.T, q.dt, seed=q.seed, events=events)))
         if stagger:
             time.sleep(stagger)
     return [srv.wait(t, timeout=120) for t in tickets]
@@ -122,7 +122,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix():
     # all submitted at once: the budget admits about three at a time, the rest
     # are admitted as earlier requests complete
     with Server(budget, max_slots=6) as srv:
-        mixed = _run(srv, mix)
+        mixed = _run(srv, mix, events=1 << 20)
     alone = []
     for (q, prm) in mix:
         with Server(1 << 31, max_slots=1) as srv:
@@ -131,6 +131,9 @@ def test_each_result_is_the_same_alone_and_in_the_mix():
         assert a.status == m.status == L.ALIF_OK
         np.testing.assert_array_equal(a.spikes, m.spikes)
         assert a.n_spikes == m.n_spikes == int(a.spikes.sum())
+        # the event list is the raster's nonzeros in ascending flat order
+        assert not m.events_truncated
+        np.testing.assert_array_equal(m.events, np.flatnonzero(a.spikes.ravel()).astype(np.uint32))
     # admission in arrival order, never more than the budget resident, and the
     # work of different requests overlapped
     admits = [m.t_admit for m in mixed]
@@ -186,3 +189,22 @@ def test_tickets_budget_and_empty_requests():
     srv = Server(1 << 30, max_slots=2)
     ts = [srv.submit(_req(prm, 4000, 0.1, seed=s)) for s in range(6)]
     srv.close()
+
+
+def test_spike_events_and_truncation():
+    from paper_2311_11390_amd.serving import Server
+    T, N, dt = 20011, 333, 0.1
+    prm = _params(N, 12)
+    log(f"serve events T={T} N={N}")
+    with Server(1 << 30, max_slots=3) as srv:
+        full = srv.wait(srv.submit(_req(prm, T, dt, seed=5)))
+        only = srv.wait(srv.submit(_req(prm, T, dt, seed=5, events=10 ** 7, raster=False)))
+        cut = srv.wait(srv.submit(_req(prm, T, dt, seed=5, events=100, raster=False)))
+    idx = np.flatnonzero(full.spikes.ravel()).astype(np.uint32)
+    assert full.n_spikes == idx.size > 100 and full.events is None
+    assert only.spikes is None and not only.events_truncated
+    np.testing.assert_array_equal(only.events, idx)
+    assert cut.events_truncated and cut.n_spikes == idx.size
+    np.testing.assert_array_equal(cut.events, idx[:100])
+    t, n = np.divmod(only.events, N)
+    assert np.all(full.spikes[t, n] == 1)
