@@ -23,7 +23,7 @@
 // block's spike step is the minimum of the segment candidates. Each wave is
 // persistent over all T / T_R blocks; the carry (V0 and a in FP64) is kept,
 // identically, by every wave of a neuron, and input loads run DEPTH blocks
-// ahead. The loop body has no data-dependent branches around memory
+// ahead (more blocks for short blocks, see fwd_depth / bwd_depth). The loop body has no data-dependent branches around memory
 // operations; blocks that follow a spike take a wave-uniform branch to the
 // masked / reset arithmetic.
 //
@@ -354,58 +354,74 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_fwd(FwdArgs a) {
 #pragma unroll
         for (int k = 0; k < L; k++) buf[i][k] = ld_f32(rI, c.off(k, (uint32_t)min((size_t)i * blk4, TN * 4)));
 
-    for (int nb0 = 0; nb0 < a.NB; nb0 += DEPTH) {
+    // One block: integrate, find the crossing, write the outputs, carry on.
+    // buf[i] holds block nb's input and receives block nb + DEPTH's.
+    auto do_block = [&](float (&bi)[L], int nb) __attribute__((always_inline)) {
+        float x[L];
 #pragma unroll
-        for (int i = 0; i < DEPTH; i++) {
-            const int nb = nb0 + i;
-            if (nb >= a.NB) break;             // uniform over the workgroup
-            float x[L];
-#pragma unroll
-            for (int k = 0; k < L; k++) x[k] = buf[i][k];
-            // prefetch block nb + DEPTH (beyond the end of the row: out of range -> 0)
+        for (int k = 0; k < L; k++) x[k] = bi[k];
+
+        const float cv = (float)v0d, ca = (float)a0d;
+        const int mpre = cts > 0 ? cts - 1 : 0;
+        const float a1 = fmaf(c.pf, ca, cts == TR ? 1.0f : 0.0f);
+        {   // carry-in of this block, for the backward pass
+            const uint32_t e = (uint32_t)(nb * N);
+            st_f32(rCv, ck4 + e * 4u, cv);
+            st_f32(rCa, ck4 + e * 4u, ca);
+            st_u8(rCt, ck1 + e, (uint8_t)cts);
+        }
+        float vt[L], th[L], uTR;
+        const int ts = block_integrate<SEG, L, EVEN>(c, ex, x, cv, a1, mpre, vt, th, uTR);
+        const bool spk = ts <= TR;
+        // prefetch block nb + DEPTH into the registers block nb has just finished
+        // with (beyond the end of the row: out of range -> 0). Issued only now,
+        // after the last use of x, so that the load can target bi's own
+        // registers: loading earlier makes the compiler load into temporaries and
+        // copy them back at the end of the block, which waits for the load.
+        {
             const uint32_t nxt = (uint32_t)min((size_t)(nb + DEPTH) * blk4, TN * 4);
 #pragma unroll
-            for (int k = 0; k < L; k++) buf[i][k] = ld_f32(rI, c.off(k, nxt));
-
-            const float cv = (float)v0d, ca = (float)a0d;
-            const int mpre = cts > 0 ? cts - 1 : 0;
-            const float a1 = fmaf(c.pf, ca, cts == TR ? 1.0f : 0.0f);
-            {   // carry-in of this block, for the backward pass
-                const uint32_t e = (uint32_t)(nb * N);
-                st_f32(rCv, ck4 + e * 4u, cv);
-                st_f32(rCa, ck4 + e * 4u, ca);
-                st_u8(rCt, ck1 + e, (uint8_t)cts);
-            }
-            float vt[L], th[L], uTR;
-            const int ts = block_integrate<SEG, L, EVEN>(c, ex, x, cv, a1, mpre, vt, th, uTR);
-            const bool spk = ts <= TR;
-
-            // outputs: spikes and corrected traces (reset after t_s, Eqs. 2 and 5)
-            const uint32_t bo = (uint32_t)nb * blk4;
-#pragma unroll
-            for (int k = 0; k < L; k++) {
-                const int t = c.t0 + k + 1;
-                const uint32_t o4 = c.off(k, bo);
-                const bool sk = t == ts;
-                if constexpr (SDT == 0) st_u8(rS, o4 >> 2 | (o4 & ALIF_OOB), sk ? 1 : 0);
-                else if constexpr (SDT == 1) st_u16(rS, o4 >> 1 | (o4 & ALIF_OOB), sk ? (uint16_t)0x3F80 : (uint16_t)0);
-                else st_f32(rS, o4, sk ? 1.0f : 0.0f);
-                if constexpr (TRACES) {
-                    const bool after = t > ts;
-                    st_f32(rV, o4, after ? 0.0f : vt[k]);
-                    const float pa = pf_tab[pfrow - min(ts, TR) + k];
-                    st_f32(rT, o4, after ? fmaf(c.dd, pa, th[k]) : th[k]);
-                }
-            }
-            // carry to the next block (Props. 4-5), FP64
-            const double e1 = cts == TR ? c.pTm1 : 0.0;
-            const double e2 = pd_tab[pdrow + max(0, TR - 1 - min(ts, TR))];
-            const double extra = e1 + ((spk && ts < TR) ? e2 : 0.0);
-            v0d = spk ? 0.0 : fma(c.betaT, v0d, (double)uTR);
-            a0d = fma(c.pT, a0d, extra);
-            cts = spk ? ts : 0;
+            for (int k = 0; k < L; k++) bi[k] = ld_f32(rI, c.off(k, nxt));
         }
+
+        // outputs: spikes and corrected traces (reset after t_s, Eqs. 2 and 5)
+        const uint32_t bo = (uint32_t)nb * blk4;
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            const int t = c.t0 + k + 1;
+            const uint32_t o4 = c.off(k, bo);
+            const bool sk = t == ts;
+            if constexpr (SDT == 0) st_u8(rS, o4 >> 2 | (o4 & ALIF_OOB), sk ? 1 : 0);
+            else if constexpr (SDT == 1) st_u16(rS, o4 >> 1 | (o4 & ALIF_OOB), sk ? (uint16_t)0x3F80 : (uint16_t)0);
+            else st_f32(rS, o4, sk ? 1.0f : 0.0f);
+            if constexpr (TRACES) {
+                const bool after = t > ts;
+                st_f32(rV, o4, after ? 0.0f : vt[k]);
+                const float pa = pf_tab[pfrow - min(ts, TR) + k];
+                st_f32(rT, o4, after ? fmaf(c.dd, pa, th[k]) : th[k]);
+            }
+        }
+        // carry to the next block (Props. 4-5), FP64
+        const double e1 = cts == TR ? c.pTm1 : 0.0;
+        const double e2 = pd_tab[pdrow + max(0, TR - 1 - min(ts, TR))];
+        const double extra = e1 + ((spk && ts < TR) ? e2 : 0.0);
+        v0d = spk ? 0.0 : fma(c.betaT, v0d, (double)uTR);
+        a0d = fma(c.pT, a0d, extra);
+        cts = spk ? ts : 0;
+    };
+    // Full groups of DEPTH blocks with no per-block guard: a guard would give the
+    // loop paths from an early block straight to its latch, and the compiler's
+    // wait analysis at the loop head would then assume the shortest distance to
+    // every prefetch. The last NB % DEPTH blocks run after the loop.
+    wait_vmem_all();
+    int nb0 = 0;
+    for (; nb0 + DEPTH <= a.NB; nb0 += DEPTH) {
+#pragma unroll
+        for (int i = 0; i < DEPTH; i++) do_block(buf[i], nb0 + i);
     }
+#pragma unroll
+    for (int i = 0; i < DEPTH; i++)
+        if (nb0 + i < a.NB) do_block(buf[i], nb0 + i);   // uniform over the workgroup
     {   // the final carry, after the carry-in of the last block
         const uint32_t e = (uint32_t)(a.NB * N);
         st_f32(rCv, ck4 + e * 4u, (float)v0d);
@@ -498,148 +514,158 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     float lamV_c = 0.0f, lamA_c = 0.0f;  // lambda_V, lambda_a at step 1 of the next block
     double acc_b = 0.0, acc_p = 0.0, acc_d = 0.0, acc_th = 0.0, acc_bias = 0.0;
 
-    for (int r0 = 0; r0 < a.NB; r0 += DEPTH) {
-#pragma unroll
-        for (int i = 0; i < DEPTH; i++) {
-            const int nb = a.NB - 1 - (r0 + i);
-            if (nb < 0) break;                 // uniform over the workgroup
-            Slot cur = buf[i];
-            load_block(buf[i], nb - DEPTH);
-            const int cts = min(cur.cts, TR);
-            // the block's spike step, as the forward decided it (carry-in of block nb + 1)
-            const int ts = cur.tsn > 0 ? min(cur.tsn, TR) : ALIF_NO_SPIKE;
-            const float cv = cur.cv, ca = cur.ca;
-            const int mpre = cts > 0 ? cts - 1 : 0;
-            const float a1 = fmaf(c.pf, ca, cts == TR ? 1.0f : 0.0f);
-            float vt[L], th[L];
-            block_membrane<SEG, L, EVEN>(c, ex, cur.x, cv, a1, mpre, vt, th);
-            const int tsc = min(ts, TR);
-            // quiet block: no spike in this block and none at the end of the previous
-            // one anywhere in the wave -> no reset, no mask, no post-spike terms
-            const bool quiet = !__any(ts <= TR || mpre > 0);
+    // One block, from its saved carry-in: recompute, reverse adjoint, gradient sums.
+    // buf[i] holds block nb's inputs and receives block nb - DEPTH's.
+    auto do_block = [&](Slot &bi, int nb) __attribute__((always_inline)) {
+        const Slot &cur = bi;
+        const int cts = min(cur.cts, TR);
+        // the block's spike step, as the forward decided it (carry-in of block nb + 1)
+        const int ts = cur.tsn > 0 ? min(cur.tsn, TR) : ALIF_NO_SPIKE;
+        const float cv = cur.cv, ca = cur.ca;
+        const int mpre = cts > 0 ? cts - 1 : 0;
+        const float a1 = fmaf(c.pf, ca, cts == TR ? 1.0f : 0.0f);
+        float vt[L], th[L];
+        block_membrane<SEG, L, EVEN>(c, ex, cur.x, cv, a1, mpre, vt, th);
+        const int tsc = min(ts, TR);
+        // quiet block: no spike in this block and none at the end of the previous
+        // one anywhere in the wave -> no reset, no mask, no post-spike terms
+        const bool quiet = !__any(ts <= TR || mpre > 0);
 
-            // corrected forward quantities and the local reverse recurrences (from zero)
-            float Vk[L], ak[L], lt[L], rV[L], PVk[L], rA[L];
-            bool gate[L];
-            float rv = 0.0f, pv = 1.0f, ra = 0.0f;
-            if (quiet) {
+        // corrected forward quantities and the local reverse recurrences (from zero)
+        float Vk[L], ak[L], lt[L], rV[L], PVk[L], rA[L];
+        bool gate[L];
+        float rv = 0.0f, pv = 1.0f, ra = 0.0f;
+        if (quiet) {
 #pragma unroll
-                for (int k = L - 1; k >= 0; k--) {
-                    Vk[k] = vt[k];
-                    ak[k] = c.pt[k] * a1;
-                    gate[k] = true;
-                    const float sg = fast_sigmoid_grad(vt[k] - th[k], a.slope);
-                    const float gsk = cur.gs[k] * sg;
-                    const float gvk = GVT ? cur.gv[k] : 0.0f, gtk = GVT ? cur.gt[k] : 0.0f;
-                    lt[k] = gtk - gsk;
-                    rv = fmaf(c.bdec(k), rv, gvk + gsk);
-                    ra = fmaf(c.pdec(k), ra, c.dd * lt[k]);
-                    rV[k] = rv;
-                    PVk[k] = c.PB(k);
-                    rA[k] = ra;
-                }
-                pv = c.PB(0);
-            } else {
-#pragma unroll
-                for (int k = L - 1; k >= 0; k--) {
-                    const int t = c.t0 + k + 1;
-                    const bool after = t > ts;
-                    const float pa = pf_tab[pfrow - tsc + k];   // p^(t - 1 - t_s)
-                    Vk[k] = after ? 0.0f : vt[k];
-                    ak[k] = after ? fmaf(c.pt[k], a1, pa) : c.pt[k] * a1;
-                    const float thk = after ? fmaf(c.dd, pa, th[k]) : th[k];
-                    gate[k] = (t > mpre) && !after;
-                    const float sg = fast_sigmoid_grad(Vk[k] - thk, a.slope);
-                    const float gsk = cur.gs[k] * sg;
-                    const float gvk = GVT ? cur.gv[k] : 0.0f, gtk = GVT ? cur.gt[k] : 0.0f;
-                    lt[k] = gtk - gsk;
-                    const float fV = t == ts ? 0.0f : c.bdec(k);
-                    rv = fmaf(fV, rv, gvk + gsk);
-                    pv = pv * fV;
-                    ra = fmaf(c.pdec(k), ra, c.dd * lt[k]);
-                    rV[k] = rv;
-                    PVk[k] = pv;
-                    rA[k] = ra;
-                }
+            for (int k = L - 1; k >= 0; k--) {
+                Vk[k] = vt[k];
+                ak[k] = c.pt[k] * a1;
+                gate[k] = true;
+                const float sg = fast_sigmoid_grad(vt[k] - th[k], a.slope);
+                const float gsk = cur.gs[k] * sg;
+                const float gvk = GVT ? cur.gv[k] : 0.0f, gtk = GVT ? cur.gt[k] : 0.0f;
+                lt[k] = gtk - gsk;
+                rv = fmaf(c.bdec(k), rv, gvk + gsk);
+                ra = fmaf(c.pdec(k), ra, c.dd * lt[k]);
+                rV[k] = rv;
+                PVk[k] = c.PB(k);
+                rA[k] = ra;
             }
-            // incoming lambdas at this segment's end, and the block's lambdas at step 1
-            float lVin, lAin, Vprev0, nlV, nlA;
-            if constexpr (SEG > 1) {
-                ex.M[c.w * NWG + c.nl] = pv;
-                ex.R[c.w * NWG + c.nl] = rv;
-                ex.RA[c.w * NWG + c.nl] = ra;
-                ex.VL[c.w * NWG + c.nl] = Vk[L - 1];
-                __syncthreads();
-                float lv = lamV_c, la = lamA_c;
-                lVin = lv;
-                lAin = la;
+            pv = c.PB(0);
+        } else {
 #pragma unroll
-                for (int s = SEG - 1; s >= 0; s--) {
-                    lVin = (s == c.w) ? lv : lVin;
-                    lAin = (s == c.w) ? la : lAin;
-                    lv = fmaf(ex.M[s * NWG + c.nl], lv, ex.R[s * NWG + c.nl]);
-                    la = fmaf(c.pseg(s), la, ex.RA[s * NWG + c.nl]);
-                }
-                nlV = lv;
-                nlA = la;
-                Vprev0 = c.w > 0 ? ex.VL[(c.w - 1) * NWG + c.nl] : cv;
-            } else {
-                lVin = lamV_c;
-                lAin = lamA_c;
-                nlV = fmaf(pv, lamV_c, rv);
-                nlA = fmaf(c.pseg(0), lamA_c, ra);
-                Vprev0 = cv;
+            for (int k = L - 1; k >= 0; k--) {
+                const int t = c.t0 + k + 1;
+                const bool after = t > ts;
+                const float pa = pf_tab[pfrow - tsc + k];   // p^(t - 1 - t_s)
+                Vk[k] = after ? 0.0f : vt[k];
+                ak[k] = after ? fmaf(c.pt[k], a1, pa) : c.pt[k] * a1;
+                const float thk = after ? fmaf(c.dd, pa, th[k]) : th[k];
+                gate[k] = (t > mpre) && !after;
+                const float sg = fast_sigmoid_grad(Vk[k] - thk, a.slope);
+                const float gsk = cur.gs[k] * sg;
+                const float gvk = GVT ? cur.gv[k] : 0.0f, gtk = GVT ? cur.gt[k] : 0.0f;
+                lt[k] = gtk - gsk;
+                const float fV = t == ts ? 0.0f : c.bdec(k);
+                rv = fmaf(fV, rv, gvk + gsk);
+                pv = pv * fV;
+                ra = fmaf(c.pdec(k), ra, c.dd * lt[k]);
+                rV[k] = rv;
+                PVk[k] = pv;
+                rA[k] = ra;
             }
-
-            // gradient contributions of this lane's steps
-            float pb = 0.0f, pp = 0.0f, pdd = 0.0f, pth = 0.0f, pbias = 0.0f;
-            const uint32_t bo = (uint32_t)nb * blk4;
-            if (quiet) {
-                const float aprev0 = c.w == 0 ? ca : c.ptm1 * a1;
-#pragma unroll
-                for (int k = 0; k < L; k++) {
-                    const float lV = c.kvalid(k) ? fmaf(PVk[k], lVin, rV[k]) : 0.0f;
-                    const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
-                    const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
-                    const float aprev = (k == 0) ? aprev0 : ak[k > 0 ? k - 1 : 0];
-                    const float gIk = c.omb * lV;
-                    pb = fmaf(Vprev - (cur.x[k] + bias), lV, pb);
-                    pp = fmaf(aprev, lA, pp);
-                    pdd = fmaf(ak[k], lt[k], pdd);
-                    pth += lt[k];
-                    pbias += gIk;
-                    if constexpr (GI) st_f32(rGI, c.off(k, bo), gIk);
-                }
-            } else {
-                const float pa0 = pf_tab[pfrow - tsc - 1];     // p^(t0 - 1 - t_s)
-                const float aprev0 = c.w == 0 ? ca : (c.t0 > ts ? fmaf(c.ptm1, a1, pa0) : c.ptm1 * a1);
-#pragma unroll
-                for (int k = 0; k < L; k++) {
-                    const float lV = c.kvalid(k) ? fmaf(PVk[k], lVin, rV[k]) : 0.0f;
-                    const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
-                    const int t = c.t0 + k + 1;
-                    const bool sprev = (t == 1) ? (cts == TR) : (t - 1 == ts);
-                    const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
-                    const float aprev = (k == 0) ? aprev0 : ak[k > 0 ? k - 1 : 0];
-                    const float gIk = gate[k] ? c.omb * lV : 0.0f;
-                    const float im = gate[k] ? cur.x[k] + bias : 0.0f;
-                    pb = fmaf(sprev ? 0.0f : Vprev - im, lV, pb);
-                    pp = fmaf(aprev, lA, pp);
-                    pdd = fmaf(ak[k], lt[k], pdd);
-                    pth += lt[k];
-                    pbias += gIk;
-                    if constexpr (GI) st_f32(rGI, c.off(k, bo), gIk);
-                }
-            }
-            acc_b += (double)pb;
-            acc_p += (double)pp;
-            acc_d += (double)pdd;
-            acc_th += (double)pth;
-            acc_bias += (double)pbias;
-            lamV_c = nlV;
-            lamA_c = nlA;
         }
+        // incoming lambdas at this segment's end, and the block's lambdas at step 1
+        float lVin, lAin, Vprev0, nlV, nlA;
+        if constexpr (SEG > 1) {
+            ex.M[c.w * NWG + c.nl] = pv;
+            ex.R[c.w * NWG + c.nl] = rv;
+            ex.RA[c.w * NWG + c.nl] = ra;
+            ex.VL[c.w * NWG + c.nl] = Vk[L - 1];
+            __syncthreads();
+            float lv = lamV_c, la = lamA_c;
+            lVin = lv;
+            lAin = la;
+#pragma unroll
+            for (int s = SEG - 1; s >= 0; s--) {
+                lVin = (s == c.w) ? lv : lVin;
+                lAin = (s == c.w) ? la : lAin;
+                lv = fmaf(ex.M[s * NWG + c.nl], lv, ex.R[s * NWG + c.nl]);
+                la = fmaf(c.pseg(s), la, ex.RA[s * NWG + c.nl]);
+            }
+            nlV = lv;
+            nlA = la;
+            Vprev0 = c.w > 0 ? ex.VL[(c.w - 1) * NWG + c.nl] : cv;
+        } else {
+            lVin = lamV_c;
+            lAin = lamA_c;
+            nlV = fmaf(pv, lamV_c, rv);
+            nlA = fmaf(c.pseg(0), lamA_c, ra);
+            Vprev0 = cv;
+        }
+
+        // gradient contributions of this lane's steps
+        float pb = 0.0f, pp = 0.0f, pdd = 0.0f, pth = 0.0f, pbias = 0.0f;
+        const uint32_t bo = (uint32_t)nb * blk4;
+        if (quiet) {
+            const float aprev0 = c.w == 0 ? ca : c.ptm1 * a1;
+#pragma unroll
+            for (int k = 0; k < L; k++) {
+                const float lV = c.kvalid(k) ? fmaf(PVk[k], lVin, rV[k]) : 0.0f;
+                const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
+                const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
+                const float aprev = (k == 0) ? aprev0 : ak[k > 0 ? k - 1 : 0];
+                const float gIk = c.omb * lV;
+                pb = fmaf(Vprev - (cur.x[k] + bias), lV, pb);
+                pp = fmaf(aprev, lA, pp);
+                pdd = fmaf(ak[k], lt[k], pdd);
+                pth += lt[k];
+                pbias += gIk;
+                if constexpr (GI) st_f32(rGI, c.off(k, bo), gIk);
+            }
+        } else {
+            const float pa0 = pf_tab[pfrow - tsc - 1];     // p^(t0 - 1 - t_s)
+            const float aprev0 = c.w == 0 ? ca : (c.t0 > ts ? fmaf(c.ptm1, a1, pa0) : c.ptm1 * a1);
+#pragma unroll
+            for (int k = 0; k < L; k++) {
+                const float lV = c.kvalid(k) ? fmaf(PVk[k], lVin, rV[k]) : 0.0f;
+                const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
+                const int t = c.t0 + k + 1;
+                const bool sprev = (t == 1) ? (cts == TR) : (t - 1 == ts);
+                const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
+                const float aprev = (k == 0) ? aprev0 : ak[k > 0 ? k - 1 : 0];
+                const float gIk = gate[k] ? c.omb * lV : 0.0f;
+                const float im = gate[k] ? cur.x[k] + bias : 0.0f;
+                pb = fmaf(sprev ? 0.0f : Vprev - im, lV, pb);
+                pp = fmaf(aprev, lA, pp);
+                pdd = fmaf(ak[k], lt[k], pdd);
+                pth += lt[k];
+                pbias += gIk;
+                if constexpr (GI) st_f32(rGI, c.off(k, bo), gIk);
+            }
+        }
+        acc_b += (double)pb;
+        acc_p += (double)pp;
+        acc_d += (double)pdd;
+        acc_th += (double)pth;
+        acc_bias += (double)pbias;
+        lamV_c = nlV;
+        lamA_c = nlA;
+        // prefetch block nb - DEPTH into this slot, after the last use of cur (so
+        // the loads can target the slot's own registers; see the forward)
+        load_block(bi, nb - DEPTH);
+    };
+    // Full groups of DEPTH blocks without per-block guards, then the remainder
+    // (the reason is given at the forward's loop).
+    wait_vmem_all();
+    int r0 = 0;
+    for (; r0 + DEPTH <= a.NB; r0 += DEPTH) {
+#pragma unroll
+        for (int i = 0; i < DEPTH; i++) do_block(buf[i], a.NB - 1 - (r0 + i));
     }
+#pragma unroll
+    for (int i = 0; i < DEPTH; i++)
+        if (r0 + i < a.NB) do_block(buf[i], a.NB - 1 - (r0 + i));   // uniform over the workgroup
     // per-(b, n) sums over this neuron's segment-waves, in a fixed order
     if constexpr (SEG > 1) {
         double *red = reinterpret_cast<double *>(ex.X);   // reuse the exchange area
@@ -669,8 +695,29 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     }
 }
 
-#define ALIF_FWD_DEPTH 4
-#define ALIF_BWD_DEPTH 2
+// Register prefetch depth, in blocks. Between two blocks a wave does only the
+// block's arithmetic and the carry update, so short blocks need more of them in
+// flight to cover the HBM latency: the depth targets a number of time steps
+// ahead, at least ALIF_*_MIN_DEPTH blocks and within a register budget of
+// prefetched values per lane.
+#ifndef ALIF_FWD_AHEAD
+#define ALIF_FWD_AHEAD 64
+#endif
+#ifndef ALIF_BWD_AHEAD
+#define ALIF_BWD_AHEAD 32
+#endif
+#define ALIF_FWD_MIN_DEPTH 4
+#define ALIF_BWD_MIN_DEPTH 2
+
+constexpr int clamp_depth(int want, int lo, int hi) { return want < lo ? lo : (want > hi ? hi : want); }
+template <int SEG, int L>
+constexpr int fwd_depth() {   // <= 64 prefetched floats per lane
+    return clamp_depth((ALIF_FWD_AHEAD + SEG * L - 1) / (SEG * L), ALIF_FWD_MIN_DEPTH, 64 / L);
+}
+template <int SEG, int L>
+constexpr int bwd_depth() {   // <= 16 prefetched steps (x, dL/dS and maybe dL/dV, dL/dtheta) per lane
+    return clamp_depth((ALIF_BWD_AHEAD + SEG * L - 1) / (SEG * L), ALIF_BWD_MIN_DEPTH, 16 / L);
+}
 
 template <int SEG, int L>
 hipError_t blocks_fwd_launch(const FwdArgs &a, hipStream_t st) {
@@ -682,10 +729,10 @@ hipError_t blocks_fwd_launch(const FwdArgs &a, hipStream_t st) {
 #define ALIF_LF(TRC, SD)                                                                          \
     do {                                                                                          \
         if (a.TR == SEG * L)                                                                      \
-            hipLaunchKernelGGL((k_blocks_fwd<SEG, L, true, ALIF_FWD_DEPTH, TRC, SD>), dim3(grid), \
+            hipLaunchKernelGGL((k_blocks_fwd<SEG, L, true, fwd_depth<SEG, L>(), TRC, SD>), dim3(grid), \
                                dim3(TH), sm, st, a);                                              \
         else                                                                                      \
-            hipLaunchKernelGGL((k_blocks_fwd<SEG, L, false, ALIF_FWD_DEPTH, TRC, SD>), dim3(grid),\
+            hipLaunchKernelGGL((k_blocks_fwd<SEG, L, false, fwd_depth<SEG, L>(), TRC, SD>), dim3(grid),\
                                dim3(TH), sm, st, a);                                              \
     } while (0)
     if (tr) {
@@ -711,10 +758,10 @@ hipError_t blocks_bwd_launch(const BwdArgs &a, hipStream_t st) {
 #define ALIF_LB(G1, G2)                                                                           \
     do {                                                                                          \
         if (a.TR == SEG * L)                                                                      \
-            hipLaunchKernelGGL((k_blocks_bwd<SEG, L, true, ALIF_BWD_DEPTH, G1, G2>), dim3(grid),  \
+            hipLaunchKernelGGL((k_blocks_bwd<SEG, L, true, bwd_depth<SEG, L>(), G1, G2>), dim3(grid),  \
                                dim3(TH), sm, st, a);                                              \
         else                                                                                      \
-            hipLaunchKernelGGL((k_blocks_bwd<SEG, L, false, ALIF_BWD_DEPTH, G1, G2>), dim3(grid), \
+            hipLaunchKernelGGL((k_blocks_bwd<SEG, L, false, bwd_depth<SEG, L>(), G1, G2>), dim3(grid), \
                                dim3(TH), sm, st, a);                                              \
     } while (0)
     if (gvt) { if (gi) ALIF_LB(true, true); else ALIF_LB(true, false); }

@@ -28,6 +28,13 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
                                              ALIF_BUFFER_DWORD3);
 }
 
+// Wait until every vector-memory operation this wave has issued is done
+// (s_waitcnt vmcnt(0); expcnt and lgkmcnt fields left at "no wait"). Issued once
+// in front of a software-pipelined loop: with the loads and stores of the
+// set-up code retired, the compiler's wait analysis at the loop head only sees
+// the loop's own prefetches and no longer drains the queue every iteration.
+__device__ __forceinline__ void wait_vmem_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Offset used for "no access": beyond any num_records we create (< 2^31).
 #define ALIF_OOB 0x80000000u
 
