@@ -38,9 +38,11 @@ def log(msg):
 
 
 def algorithmic_bytes(TR):
-    """Bytes per neuron-step the method must move (see the design notes):
-    forward: read I (4) + write S (1) + block carry (9 B per neuron-block);
-    backward: read I (4) + read dL/dS (4) + read block carry."""
+    """Bytes per neuron-step the method must move: forward reads I (4 B) and writes
+    the spike (1 B) and, once per T_R-step block, the block's carry-in (V0 and a
+    as float, the previous spike step as a byte: 9 B); the backward reads I and
+    dL/dS (4 + 4 B) and the carries. Traces, gradients of I and anything the
+    method could avoid are not counted."""
     return {"fwd": 4.0 + 1.0 + 9.0 / TR, "bwd": 8.0 + 9.0 / TR}
 
 
@@ -235,7 +237,7 @@ def main():
                          "traffic, for scaling HBM byte counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the path would "
+        print(f"bench.py: this benchmark runs on one GPU only (got --gpus {args.gpus}); the path would "
               "shard independent (batch, neuron) rows across GPUs with no exchange, which is not run here.",
               file=sys.stderr)
         sys.exit(2)

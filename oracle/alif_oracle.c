@@ -26,7 +26,7 @@
  * factor (1 - S[t-1]), in the adaptation increment and in the refractory mask are
  * constants. The leak path beta*V and the threshold path stay attached.
  *
- * Readings where the paper is silent (listed with reasons in the design notes):
+ * Readings where the paper is silent:
  *   - T_R = round(ARP/DT) steps; C[t] = t - t_last, input passes iff C >= T_R.
  *   - The surrogate argument is u = V - th for every surrogate.
  *   - dS/dth = -sigma'(u) (the threshold is learnable here).

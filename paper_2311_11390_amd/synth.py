@@ -5,7 +5,7 @@ arithmetic, so the GPU path and the FP64 oracle can both be fed from it. All
 draws use numpy's PCG64 with an explicit seed and are returned as the exact
 float32 / uint8 arrays the GPU consumes (the oracle upcasts them).
 
-Workload shapes (see the configuration table in the design notes):
+Workload shapes:
 
 * Bernoulli input spikes per step (the supplementary "Synthetic spike dataset"
   draws a homogeneous Poisson train per sample; the workloads here fix the rate
