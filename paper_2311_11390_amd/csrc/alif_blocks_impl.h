@@ -52,11 +52,11 @@ struct Geo {
 // row length of the padded FP32 p^e table (e in [-T_R, T_R + L))
 __host__ __device__ constexpr int ptab_row(int TR, int L) { return 2 * TR + L; }
 
-// LDS layout: pd [NWG][TR] f64 | pfp [NWG][RL] f32 | exchange 6 x [SEG][NWG] f32
+// LDS layout: pd [NWG][TR] f64 | pfp [NWG][RL] f32 | exchange 6 x [SEG][NWG] + 2 x [NWG] f32
 template <int SEG, int L>
 size_t smem_bytes(int TR) {
     constexpr int NWG = Geo<SEG>::NWG;
-    const size_t ex = SEG > 1 ? (size_t)6 * SEG * NWG * sizeof(float) : 0;
+    const size_t ex = SEG > 1 ? (size_t)(6 * SEG + 2) * NWG * sizeof(float) : 0;
     return (size_t)NWG * TR * sizeof(double) + (size_t)NWG * ptab_row(TR, L) * sizeof(float) + ex;
 }
 
@@ -103,7 +103,7 @@ __device__ __forceinline__ void lane_setup(Lane<SEG, L, EVEN> &c, int N, int TR,
                                            const float *theta0, const float *bias) {
     constexpr int NG = Geo<SEG>::NG;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    c.w = wave / NG;
+    c.w = __builtin_amdgcn_readfirstlane(wave / NG);   // uniform over the wave
     c.nl = (wave % NG) * 64 + lane;
     c.n = n0 + c.nl;
     c.valid = c.n < N;
@@ -173,17 +173,19 @@ __device__ __forceinline__ void build_p_tables(double *pd, float *pfp, int n0, i
 }
 
 template <int SEG>
-struct Exch {  // LDS exchange arrays, each [SEG][NWG]
+struct Exch {  // LDS exchange arrays: six of [SEG][NWG], then two of [NWG]
     float *X;
     int *C;
     float *M, *R, *RA, *VL;
+    float *LV, *LA;   // backward: the block's lambdas at step 1, from wave 0
 };
 
 template <int SEG>
 __device__ __forceinline__ Exch<SEG> exch_at(unsigned char *base) {
     constexpr int SZ = SEG * Geo<SEG>::NWG;
     float *f = reinterpret_cast<float *>(base);
-    return Exch<SEG>{f, reinterpret_cast<int *>(f + SZ), f + 2 * SZ, f + 3 * SZ, f + 4 * SZ, f + 5 * SZ};
+    return Exch<SEG>{f, reinterpret_cast<int *>(f + SZ), f + 2 * SZ, f + 3 * SZ, f + 4 * SZ, f + 5 * SZ,
+                     f + 6 * SZ, f + 6 * SZ + Geo<SEG>::NWG};
 }
 
 // The per-block integration shared by forward and backward (identical
@@ -511,7 +513,17 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
 #pragma unroll
     for (int i = 0; i < DEPTH; i++) load_block(buf[i], a.NB - 1 - i);
 
-    float lamV_c = 0.0f, lamA_c = 0.0f;  // lambda_V, lambda_a at step 1 of the next block
+    // lambda_V and lambda_a' at step 1 of the block after the current one. The
+    // adaptation adjoint is carried without its factor d (lambda_a = d lambda_a',
+    // exact by linearity, also for d = 0), so the per-step recurrence has no
+    // multiply by d; d is applied once per block to its parameter-gradient sum.
+    float lamV_c = 0.0f, lamA_c = 0.0f;
+    if constexpr (SEG > 1) {
+        if (c.w == 0) {   // published by wave 0 each block, read by all after the next barrier
+            ex.LV[c.nl] = 0.0f;
+            ex.LA[c.nl] = 0.0f;
+        }
+    }
     double acc_b = 0.0, acc_p = 0.0, acc_d = 0.0, acc_th = 0.0, acc_bias = 0.0;
 
     // One block, from its saved carry-in: recompute, reverse adjoint, gradient sums.
@@ -526,29 +538,38 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
         const float a1 = fmaf(c.pf, ca, cts == TR ? 1.0f : 0.0f);
         float vt[L], th[L];
         block_membrane<SEG, L, EVEN>(c, ex, cur.x, cv, a1, mpre, vt, th);
+        if constexpr (SEG > 1) {
+            // wave 0's lambdas of block nb + 1 (read before this block's exchange
+            // barrier, after which wave 0 overwrites them)
+            lamV_c = ex.LV[c.nl];
+            lamA_c = ex.LA[c.nl];
+        }
         const int tsc = min(ts, TR);
         // quiet block: no spike in this block and none at the end of the previous
         // one anywhere in the wave -> no reset, no mask, no post-spike terms
         const bool quiet = !__any(ts <= TR || mpre > 0);
 
-        // corrected forward quantities and the local reverse recurrences (from zero)
+        // local reverse recurrences over this segment's steps, from zero:
+        //   rv: lambda_V (source dL/dV + dL/dS s'), pv: its decay across the segment,
+        //   ra: lambda_a' (source lambda_theta = dL/dtheta - dL/dS s')
         float Vk[L], ak[L], lt[L], rV[L], PVk[L], rA[L];
         bool gate[L];
         float rv = 0.0f, pv = 1.0f, ra = 0.0f;
         if (quiet) {
 #pragma unroll
             for (int k = L - 1; k >= 0; k--) {
-                Vk[k] = vt[k];
-                ak[k] = c.pt[k] * a1;
-                gate[k] = true;
-                const float sg = fast_sigmoid_grad(vt[k] - th[k], a.slope);
-                const float gsk = cur.gs[k] * sg;
-                const float gvk = GVT ? cur.gv[k] : 0.0f, gtk = GVT ? cur.gt[k] : 0.0f;
-                lt[k] = gtk - gsk;
-                rv = fmaf(c.bdec(k), rv, gvk + gsk);
-                ra = fmaf(c.pdec(k), ra, c.dd * lt[k]);
+                const float gsk = cur.gs[k] * fast_sigmoid_grad(vt[k] - th[k], a.slope);
+                float src;
+                if constexpr (GVT) {
+                    src = cur.gv[k] + gsk;
+                    lt[k] = cur.gt[k] - gsk;
+                } else {
+                    src = gsk;
+                    lt[k] = -gsk;
+                }
+                rv = fmaf(c.bdec(k), rv, src);
+                ra = fmaf(c.pdec(k), ra, lt[k]);
                 rV[k] = rv;
-                PVk[k] = c.PB(k);
                 rA[k] = ra;
             }
             pv = c.PB(0);
@@ -562,70 +583,90 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
                 ak[k] = after ? fmaf(c.pt[k], a1, pa) : c.pt[k] * a1;
                 const float thk = after ? fmaf(c.dd, pa, th[k]) : th[k];
                 gate[k] = (t > mpre) && !after;
-                const float sg = fast_sigmoid_grad(Vk[k] - thk, a.slope);
-                const float gsk = cur.gs[k] * sg;
-                const float gvk = GVT ? cur.gv[k] : 0.0f, gtk = GVT ? cur.gt[k] : 0.0f;
-                lt[k] = gtk - gsk;
+                const float gsk = cur.gs[k] * fast_sigmoid_grad(Vk[k] - thk, a.slope);
+                float src;
+                if constexpr (GVT) {
+                    src = cur.gv[k] + gsk;
+                    lt[k] = cur.gt[k] - gsk;
+                } else {
+                    src = gsk;
+                    lt[k] = -gsk;
+                }
                 const float fV = t == ts ? 0.0f : c.bdec(k);
-                rv = fmaf(fV, rv, gvk + gsk);
+                rv = fmaf(fV, rv, src);
                 pv = pv * fV;
-                ra = fmaf(c.pdec(k), ra, c.dd * lt[k]);
+                ra = fmaf(c.pdec(k), ra, lt[k]);
                 rV[k] = rv;
                 PVk[k] = pv;
                 rA[k] = ra;
             }
         }
-        // incoming lambdas at this segment's end, and the block's lambdas at step 1
-        float lVin, lAin, Vprev0, nlV, nlA;
+        // incoming lambdas at this segment's end: compose the later segments' maps
+        // (lam_start = R + M lam_end) from the block end; wave 0 also forms the
+        // block's lambdas at step 1 and publishes them for the block before
+        float lVin, lAin, Vprev0;
         if constexpr (SEG > 1) {
             ex.M[c.w * NWG + c.nl] = pv;
             ex.R[c.w * NWG + c.nl] = rv;
             ex.RA[c.w * NWG + c.nl] = ra;
-            ex.VL[c.w * NWG + c.nl] = Vk[L - 1];
+            ex.VL[c.w * NWG + c.nl] = quiet ? vt[L - 1] : Vk[L - 1];
             __syncthreads();
             float lv = lamV_c, la = lamA_c;
+#pragma unroll
+            for (int s = SEG - 1; s >= 1; s--) {
+                if (s > c.w) {   // wave-uniform
+                    lv = fmaf(ex.M[s * NWG + c.nl], lv, ex.R[s * NWG + c.nl]);
+                    la = fmaf(c.pseg(s), la, ex.RA[s * NWG + c.nl]);
+                }
+            }
             lVin = lv;
             lAin = la;
-#pragma unroll
-            for (int s = SEG - 1; s >= 0; s--) {
-                lVin = (s == c.w) ? lv : lVin;
-                lAin = (s == c.w) ? la : lAin;
-                lv = fmaf(ex.M[s * NWG + c.nl], lv, ex.R[s * NWG + c.nl]);
-                la = fmaf(c.pseg(s), la, ex.RA[s * NWG + c.nl]);
-            }
-            nlV = lv;
-            nlA = la;
             Vprev0 = c.w > 0 ? ex.VL[(c.w - 1) * NWG + c.nl] : cv;
+            if (c.w == 0) {
+                ex.LV[c.nl] = fmaf(pv, lVin, rv);
+                ex.LA[c.nl] = fmaf(c.pseg(0), lAin, ra);
+            }
         } else {
             lVin = lamV_c;
             lAin = lamA_c;
-            nlV = fmaf(pv, lamV_c, rv);
-            nlA = fmaf(c.pseg(0), lamA_c, ra);
+            lamV_c = fmaf(pv, lVin, rv);
+            lamA_c = fmaf(c.pseg(0), lAin, ra);
             Vprev0 = cv;
         }
 
-        // gradient contributions of this lane's steps
+        // gradient contributions of this lane's steps:
+        //   d/dbeta   += (1 - S[t-1]) (V[t-1] - gate I[t]) lambda_V[t]
+        //   d/dp      += a[t-1] lambda_a[t] = d a[t-1] lambda_a'[t]
+        //   d/dd      += a[t] lambda_theta[t],   d/dtheta0 += lambda_theta[t]
+        //   d/dbias   += (1 - beta) gate lambda_V[t]
         float pb = 0.0f, pp = 0.0f, pdd = 0.0f, pth = 0.0f, pbias = 0.0f;
         const uint32_t bo = (uint32_t)nb * blk4;
         if (quiet) {
+            // a[t] = p^(t-1) a1 throughout a quiet block, so a1 factors out of the
+            // d and p sums; the bias term of I factors out of the beta sum
             const float aprev0 = c.w == 0 ? ca : c.ptm1 * a1;
+            float slV = 0.0f, qd = 0.0f, qp = 0.0f, lA0 = 0.0f;
 #pragma unroll
             for (int k = 0; k < L; k++) {
-                const float lV = c.kvalid(k) ? fmaf(PVk[k], lVin, rV[k]) : 0.0f;
+                const float lV = c.kvalid(k) ? fmaf(c.PB(k), lVin, rV[k]) : 0.0f;
                 const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
-                const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
-                const float aprev = (k == 0) ? aprev0 : ak[k > 0 ? k - 1 : 0];
-                const float gIk = c.omb * lV;
-                pb = fmaf(Vprev - (cur.x[k] + bias), lV, pb);
-                pp = fmaf(aprev, lA, pp);
-                pdd = fmaf(ak[k], lt[k], pdd);
+                const float Vprev = (k == 0) ? Vprev0 : vt[k > 0 ? k - 1 : 0];
+                slV += lV;
+                pb = fmaf(Vprev - cur.x[k], lV, pb);
+                qd = fmaf(c.pt[k], lt[k], qd);
+                if (k == 0) lA0 = lA;
+                else qp = fmaf(c.pt[k > 0 ? k - 1 : 0], lA, qp);
                 pth += lt[k];
-                pbias += gIk;
-                if constexpr (GI) st_f32(rGI, c.off(k, bo), gIk);
+                if constexpr (GI) st_f32(rGI, c.off(k, bo), c.omb * lV);
             }
+            pb = fmaf(-bias, slV, pb);
+            pp = c.dd * fmaf(a1, qp, aprev0 * lA0);
+            pdd = a1 * qd;
+            pbias = c.omb * slV;
         } else {
             const float pa0 = pf_tab[pfrow - tsc - 1];     // p^(t0 - 1 - t_s)
             const float aprev0 = c.w == 0 ? ca : (c.t0 > ts ? fmaf(c.ptm1, a1, pa0) : c.ptm1 * a1);
+            float sglV = 0.0f;
 #pragma unroll
             for (int k = 0; k < L; k++) {
                 const float lV = c.kvalid(k) ? fmaf(PVk[k], lVin, rV[k]) : 0.0f;
@@ -634,23 +675,23 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
                 const bool sprev = (t == 1) ? (cts == TR) : (t - 1 == ts);
                 const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
                 const float aprev = (k == 0) ? aprev0 : ak[k > 0 ? k - 1 : 0];
-                const float gIk = gate[k] ? c.omb * lV : 0.0f;
+                const float glV = gate[k] ? lV : 0.0f;
                 const float im = gate[k] ? cur.x[k] + bias : 0.0f;
                 pb = fmaf(sprev ? 0.0f : Vprev - im, lV, pb);
                 pp = fmaf(aprev, lA, pp);
                 pdd = fmaf(ak[k], lt[k], pdd);
                 pth += lt[k];
-                pbias += gIk;
-                if constexpr (GI) st_f32(rGI, c.off(k, bo), gIk);
+                sglV += glV;
+                if constexpr (GI) st_f32(rGI, c.off(k, bo), c.omb * glV);
             }
+            pp *= c.dd;
+            pbias = c.omb * sglV;
         }
         acc_b += (double)pb;
         acc_p += (double)pp;
         acc_d += (double)pdd;
         acc_th += (double)pth;
         acc_bias += (double)pbias;
-        lamV_c = nlV;
-        lamA_c = nlA;
         // prefetch block nb - DEPTH into this slot, after the last use of cur (so
         // the loads can target the slot's own registers; see the forward)
         load_block(bi, nb - DEPTH);

@@ -180,10 +180,13 @@ __device__ __forceinline__ int xcd_remap(int wg, int total) {
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-// fast-sigmoid surrogate derivative (k|u| + 1)^-2
+// Fast-sigmoid surrogate derivative (k|u| + 1)^-2 (Supplementary, "Surrogate
+// gradient"). The reciprocal is the hardware one (v_rcp_f32, within 1 ulp)
+// rather than an IEEE division, which compiles to about ten instructions: the
+// value only scales gradients, whose tolerance is far above 1 ulp.
 __device__ __forceinline__ float fast_sigmoid_grad(float u, float k) {
-    float q = fmaf(k, fabsf(u), 1.0f);
-    return 1.0f / (q * q);
+    const float r = __builtin_amdgcn_rcpf(fmaf(k, fabsf(u), 1.0f));
+    return r * r;
 }
 
 // parameter sanity for the block method (positive threshold during refractory)
