@@ -61,18 +61,8 @@ int block_neurons_per_wg(int seg) { return 64 * (seg >= 4 ? 1 : 4 / seg); }
 
 #define ALIF_EXTERN(S, L)                                                                  \
     extern template hipError_t blocks_fwd_launch<S, L>(const FwdArgs &, hipStream_t);     \
-    extern template hipError_t blocks_bwd_launch<S, L>(const BwdArgs &, hipStream_t);     \
-    extern template size_t smem_bytes<S, L>(int);
+    extern template hipError_t blocks_bwd_launch<S, L>(const BwdArgs &, hipStream_t);
 ALIF_CONFIGS(ALIF_EXTERN)
-
-size_t block_smem_bytes(int seg, int TR) {
-    BlockConfig c = block_config(TR);
-    (void)seg;
-#define ALIF_SM(S, L) if (c.seg == S && c.len == L) return smem_bytes<S, L>(TR);
-    ALIF_CONFIGS(ALIF_SM)
-#undef ALIF_SM
-    return 0;
-}
 
 hipError_t launch_blocks_fwd(const FwdArgs &a, hipStream_t st) {
     BlockConfig c = block_config(a.TR);

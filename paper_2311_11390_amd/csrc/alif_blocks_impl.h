@@ -52,12 +52,35 @@ struct Geo {
 // row length of the padded FP32 p^e table (e in [-T_R, T_R + L))
 __host__ __device__ constexpr int ptab_row(int TR, int L) { return 2 * TR + L; }
 
-// LDS layout: pd [NWG][TR] f64 | pfp [NWG][RL] f32 | exchange 6 x [SEG][NWG] + 2 x [NWG] f32
+template <int SEG>
+struct Exch {  // LDS exchange arrays, each [SEG][NWG]
+    float *X;
+    int *C;
+    float *M, *R, *RA, *VL;
+    // floats in one copy of the arrays; the backward keeps two copies (block parity)
+    static constexpr int SIZE = 6 * SEG * Geo<SEG>::NWG;
+};
+
+template <int SEG>
+__device__ __forceinline__ Exch<SEG> exch_at(unsigned char *base) {
+    constexpr int SZ = SEG * Geo<SEG>::NWG;
+    float *f = reinterpret_cast<float *>(base);
+    return Exch<SEG>{f, reinterpret_cast<int *>(f + SZ), f + 2 * SZ, f + 3 * SZ, f + 4 * SZ, f + 5 * SZ};
+}
+
+// LDS layouts. Forward: pd [NWG][TR] f64 | pfp [NWG][RL] f32 | exchange 6 x [SEG][NWG] f32.
+// Backward (no carry, so no pd): pfp | two copies of the exchange arrays.
 template <int SEG, int L>
-size_t smem_bytes(int TR) {
+size_t fwd_smem_bytes(int TR) {
     constexpr int NWG = Geo<SEG>::NWG;
-    const size_t ex = SEG > 1 ? (size_t)(6 * SEG + 2) * NWG * sizeof(float) : 0;
+    const size_t ex = SEG > 1 ? (size_t)Exch<SEG>::SIZE * sizeof(float) : 0;
     return (size_t)NWG * TR * sizeof(double) + (size_t)NWG * ptab_row(TR, L) * sizeof(float) + ex;
+}
+template <int SEG, int L>
+size_t bwd_smem_bytes(int TR) {
+    constexpr int NWG = Geo<SEG>::NWG;
+    const size_t ex = SEG > 1 ? (size_t)2 * Exch<SEG>::SIZE * sizeof(float) : 0;
+    return (size_t)NWG * ptab_row(TR, L) * sizeof(float) + ex;
 }
 
 // Per-lane constants of the block recurrence. EVEN (T_R == SEG * L) means no
@@ -103,7 +126,8 @@ __device__ __forceinline__ void lane_setup(Lane<SEG, L, EVEN> &c, int N, int TR,
                                            const float *theta0, const float *bias) {
     constexpr int NG = Geo<SEG>::NG;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    c.w = __builtin_amdgcn_readfirstlane(wave / NG);   // uniform over the wave
+    // uniform over the wave (and the constant 0 with one segment per block)
+    c.w = SEG == 1 ? 0 : __builtin_amdgcn_readfirstlane(wave / NG);
     c.nl = (wave % NG) * 64 + lane;
     c.n = n0 + c.nl;
     c.valid = c.n < N;
@@ -161,9 +185,11 @@ __device__ __forceinline__ void build_p_tables(double *pd, float *pfp, int n0, i
                                                double dt, const float *tau_a) {
     constexpr int NWG = Geo<SEG>::NWG;
     const int RL = ptab_row(TR, L);
-    for (int idx = threadIdx.x; idx < NWG * TR; idx += blockDim.x) {
-        const int jj = idx / TR, k = idx - jj * TR;
-        pd[idx] = exp(-dt / (double)tau_a[min(n0 + jj, N - 1)] * (double)k);
+    if (pd) {
+        for (int idx = threadIdx.x; idx < NWG * TR; idx += blockDim.x) {
+            const int jj = idx / TR, k = idx - jj * TR;
+            pd[idx] = exp(-dt / (double)tau_a[min(n0 + jj, N - 1)] * (double)k);
+        }
     }
     for (int idx = threadIdx.x; idx < NWG * RL; idx += blockDim.x) {
         const int jj = idx / RL, e = idx - jj * RL - TR;
@@ -172,97 +198,13 @@ __device__ __forceinline__ void build_p_tables(double *pd, float *pfp, int n0, i
     __syncthreads();
 }
 
-template <int SEG>
-struct Exch {  // LDS exchange arrays: six of [SEG][NWG], then two of [NWG]
-    float *X;
-    int *C;
-    float *M, *R, *RA, *VL;
-    float *LV, *LA;   // backward: the block's lambdas at step 1, from wave 0
-};
-
-template <int SEG>
-__device__ __forceinline__ Exch<SEG> exch_at(unsigned char *base) {
-    constexpr int SZ = SEG * Geo<SEG>::NWG;
-    float *f = reinterpret_cast<float *>(base);
-    return Exch<SEG>{f, reinterpret_cast<int *>(f + SZ), f + 2 * SZ, f + 3 * SZ, f + 4 * SZ, f + 5 * SZ,
-                     f + 6 * SZ, f + 6 * SZ + Geo<SEG>::NWG};
-}
-
-// The per-block integration shared by forward and backward (identical
-// arithmetic, so the backward recovers exactly the forward's spike steps).
-//   x[k]  input current at t_k, a1 = a[1] of the block, cv = V0 (float),
-//   mpre  = masked leading steps (t_s of the previous block - 1).
-// Returns the block's spike step t_s (ALIF_NO_SPIKE if none), the no-reset
-// membrane vt[k], the threshold th[k] (valid up to t_s), and U[T_R] (input part
-// of the membrane at the block end). Contains two workgroup barriers if SEG > 1.
+// Local part of the no-reset membrane over this lane's segment (Prop. 1): the
+// input decayed from the segment start, uu[k] = sum over the valid, unmasked
+// steps j <= k of beta^(k - j) (1 - beta) (I[t_j] + b), where the first
+// mpre steps of the block are masked (the refractory steps, Prop. 3).
 template <int SEG, int L, bool EVEN>
-__device__ __forceinline__ int block_integrate(const Lane<SEG, L, EVEN> &c, const Exch<SEG> &ex,
-                                               const float (&x)[L], float cv, float a1, int mpre,
-                                               float (&vt)[L], float (&th)[L], float &uTR) {
-    constexpr int NWG = Geo<SEG>::NWG;
-    float uu[L];
-    float u = 0.0f;
-    if (__any(mpre > 0)) {                 // after a spike: mask the refractory steps (Prop. 3)
-        const int kmin = mpre - c.t0;
-#pragma unroll
-        for (int k = 0; k < L; k++) {
-            const float in = k >= kmin ? fmaf(c.omb, x[k], c.obk(k)) : 0.0f;
-            u = fmaf(c.bdec(k), u, in);
-            uu[k] = u;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < L; k++) {
-            u = fmaf(c.bdec(k), u, fmaf(c.omb, x[k], c.obk(k)));   // Prop. 1, local part
-            uu[k] = u;
-        }
-    }
-    float E = 0.0f;  // U at this segment's start
-    if constexpr (SEG > 1) {
-        ex.X[c.w * NWG + c.nl] = uu[L - 1];
-        __syncthreads();
-        float U = 0.0f;
-#pragma unroll
-        for (int s = 0; s < SEG; s++) {
-            const float xs = ex.X[s * NWG + c.nl];
-            E = (s == c.w) ? U : E;
-            U = fmaf(c.bseg(s), U, xs);
-        }
-        uTR = U;
-    } else {
-        uTR = uu[L - 1];
-    }
-    const float C = fmaf(c.bsL, cv, E);                              // V~ at the segment start
-    const float da1 = c.dd * a1;
-    int cand = ALIF_NO_SPIKE;
-#pragma unroll
-    for (int k = L - 1; k >= 0; k--) {
-        vt[k] = fmaf(c.bk[k], C, uu[k]);                             // V~[t_k]
-        th[k] = fmaf(c.pt[k], da1, c.thk(k));                        // Prop. 5
-        cand = vt[k] > th[k] ? c.t0 + k + 1 : cand;                  // Eq. 7, strict
-    }
-    if constexpr (SEG > 1) {                                         // Eqs. 8-9 / Prop. 2
-        ex.C[c.w * NWG + c.nl] = cand;
-        __syncthreads();
-        int ts = ALIF_NO_SPIKE;
-#pragma unroll
-        for (int s = 0; s < SEG; s++) ts = min(ts, ex.C[s * NWG + c.nl]);
-        return ts;
-    } else {
-        return cand;
-    }
-}
-
-// The backward's recompute of a block whose spike step is already known (from
-// the carry-in of the next block): the same no-reset membrane and threshold as
-// block_integrate, with the same arithmetic, but no crossing search. One
-// workgroup barrier if SEG > 1.
-template <int SEG, int L, bool EVEN>
-__device__ __forceinline__ void block_membrane(const Lane<SEG, L, EVEN> &c, const Exch<SEG> &ex,
-                                               const float (&x)[L], float cv, float a1, int mpre,
-                                               float (&vt)[L], float (&th)[L]) {
-    constexpr int NWG = Geo<SEG>::NWG;
-    float uu[L];
+__device__ __forceinline__ void seg_scan(const Lane<SEG, L, EVEN> &c, const float (&x)[L], int mpre,
+                                         float (&uu)[L]) {
     float u = 0.0f;
     if (__any(mpre > 0)) {
         const int kmin = mpre - c.t0;
@@ -279,24 +221,76 @@ __device__ __forceinline__ void block_membrane(const Lane<SEG, L, EVEN> &c, cons
             uu[k] = u;
         }
     }
-    float E = 0.0f;
-    if constexpr (SEG > 1) {
-        ex.X[c.w * NWG + c.nl] = uu[L - 1];
-        __syncthreads();
-        float U = 0.0f;
+}
+
+// From the segment ends X[s] of one block (each lane's own neuron): the input
+// part of the membrane at this lane's segment start (E) and at the block end (U),
+// combined in segment order (Horner).
+template <int SEG, int L, bool EVEN>
+__device__ __forceinline__ void seg_horner(const Lane<SEG, L, EVEN> &c, const float *X, float &E, float &U) {
+    constexpr int NWG = Geo<SEG>::NWG;
+    float e = 0.0f, u = 0.0f;
 #pragma unroll
-        for (int s = 0; s < SEG; s++) {
-            const float xs = ex.X[s * NWG + c.nl];
-            E = (s == c.w) ? U : E;
-            U = fmaf(c.bseg(s), U, xs);
-        }
+    for (int s = 0; s < SEG; s++) {
+        const float xs = X[s * NWG + c.nl];
+        e = (s == c.w) ? u : e;
+        u = fmaf(c.bseg(s), u, xs);
     }
-    const float C = fmaf(c.bsL, cv, E);
+    E = e;
+    U = u;
+}
+
+// The no-reset membrane V~[t_k] = beta^(t_k) V0 + U[t_k] (Prop. 1) and the
+// threshold theta0 + d p^(t_k - 1) a1 (Prop. 5) over this lane's steps, and the
+// first step where V~ > theta (Eq. 7, strict; ALIF_NO_SPIKE if none).
+template <int SEG, int L, bool EVEN>
+__device__ __forceinline__ int seg_membrane(const Lane<SEG, L, EVEN> &c, float cv, float E, float a1,
+                                            const float (&uu)[L], float (&vt)[L], float (&th)[L]) {
+    const float C = fmaf(c.bsL, cv, E);                              // V~ at the segment start
     const float da1 = c.dd * a1;
+    int cand = ALIF_NO_SPIKE;
 #pragma unroll
     for (int k = L - 1; k >= 0; k--) {
         vt[k] = fmaf(c.bk[k], C, uu[k]);
         th[k] = fmaf(c.pt[k], da1, c.thk(k));
+        cand = vt[k] > th[k] ? c.t0 + k + 1 : cand;
+    }
+    return cand;
+}
+
+// One block of the forward, for every segment-wave of the workgroup:
+//   x[k]  input current at t_k, a1 = a[1] of the block, cv = V0 (float),
+//   mpre  = masked leading steps (t_s of the previous block - 1).
+// Returns the block's spike step t_s (ALIF_NO_SPIKE if none; the minimum of the
+// segments' candidates, Eqs. 8-9 / Prop. 2), the no-reset membrane vt[k], the
+// threshold th[k] (valid up to t_s), and U[T_R] (the input part of the membrane
+// at the block end). Two workgroup barriers if SEG > 1. The backward recomputes
+// blocks with the same helpers, so its V~ and theta are the forward's.
+template <int SEG, int L, bool EVEN>
+__device__ __forceinline__ int block_integrate(const Lane<SEG, L, EVEN> &c, const Exch<SEG> &ex,
+                                               const float (&x)[L], float cv, float a1, int mpre,
+                                               float (&vt)[L], float (&th)[L], float &uTR) {
+    constexpr int NWG = Geo<SEG>::NWG;
+    float uu[L];
+    seg_scan(c, x, mpre, uu);
+    float E = 0.0f;
+    if constexpr (SEG > 1) {
+        ex.X[c.w * NWG + c.nl] = uu[L - 1];
+        __syncthreads();
+        seg_horner(c, ex.X, E, uTR);
+    } else {
+        uTR = uu[L - 1];
+    }
+    const int cand = seg_membrane(c, cv, E, a1, uu, vt, th);
+    if constexpr (SEG > 1) {
+        ex.C[c.w * NWG + c.nl] = cand;
+        __syncthreads();
+        int ts = ALIF_NO_SPIKE;
+#pragma unroll
+        for (int s = 0; s < SEG; s++) ts = min(ts, ex.C[s * NWG + c.nl]);
+        return ts;
+    } else {
+        return cand;
     }
 }
 
@@ -458,14 +452,13 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     constexpr int NWG = Geo<SEG>::NWG;
     extern __shared__ __align__(16) unsigned char smem[];
     const int TR = a.TR, N = a.N, T = a.T, RL = ptab_row(TR, L);
-    double *pd_tab = reinterpret_cast<double *>(smem);
-    float *pf_tab = reinterpret_cast<float *>(smem + (size_t)NWG * TR * sizeof(double));
+    float *pf_tab = reinterpret_cast<float *>(smem);
     const Exch<SEG> ex = exch_at<SEG>(reinterpret_cast<unsigned char *>(pf_tab + (size_t)NWG * RL));
 
     const int work = xcd_remap(blockIdx.x, gridDim.x);
     const int b = work / a.n_groups, g = work - b * a.n_groups;
     const int n0 = g * NWG;
-    build_p_tables<SEG, L>(pd_tab, pf_tab, n0, N, TR, a.dt, a.tau_a);
+    build_p_tables<SEG, L>(nullptr, pf_tab, n0, N, TR, a.dt, a.tau_a);
     Lane<SEG, L, EVEN> c;
     lane_setup(c, N, TR, a.dt, n0, a.tau_m, a.tau_a, a.d, a.theta0, a.bias_k);
     const int pfrow = c.nl * RL + TR + c.t0;
@@ -513,22 +506,61 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
 #pragma unroll
     for (int i = 0; i < DEPTH; i++) load_block(buf[i], a.NB - 1 - i);
 
+    // The blocks are processed last to first, as a two-stage pipeline with one
+    // workgroup barrier per block: the iteration for block nb runs the masked
+    // scan of block nb - 1 (which needs only that block's input and saved
+    // carry-in) and the reverse scans of block nb, publishes both through LDS,
+    // waits once, then finishes block nb (lambda composition, parameter sums)
+    // and block nb - 1's membrane, which the next iteration uses. The exchange
+    // arrays come in two copies selected by block parity: a copy is rewritten
+    // two iterations later, after a barrier that follows its last read.
+    // With one segment per block there is no barrier to share, and each block's
+    // membrane is computed in its own iteration instead.
+    constexpr bool PIPE = SEG > 1;
+    const auto par = [](int nb) { return (nb & 1) * Exch<SEG>::SIZE; };
+    float vtn[L], thn[L];   // V~ and theta of the block the next iteration finishes
+    if constexpr (PIPE) {
+        const Slot &s0 = buf[0];
+        const int cts0 = min(s0.cts, TR);
+        float uu[L];
+        seg_scan(c, s0.x, cts0 > 0 ? cts0 - 1 : 0, uu);
+        float E = 0.0f, U;
+        if constexpr (SEG > 1) {
+            ex.X[par(a.NB - 1) + c.w * NWG + c.nl] = uu[L - 1];
+            __syncthreads();
+            seg_horner(c, ex.X + par(a.NB - 1), E, U);
+        }
+        seg_membrane(c, s0.cv, E, fmaf(c.pf, s0.ca, cts0 == TR ? 1.0f : 0.0f), uu, vtn, thn);
+    }
+
     // lambda_V and lambda_a' at step 1 of the block after the current one. The
     // adaptation adjoint is carried without its factor d (lambda_a = d lambda_a',
     // exact by linearity, also for d = 0), so the per-step recurrence has no
     // multiply by d; d is applied once per block to its parameter-gradient sum.
     float lamV_c = 0.0f, lamA_c = 0.0f;
-    if constexpr (SEG > 1) {
-        if (c.w == 0) {   // published by wave 0 each block, read by all after the next barrier
-            ex.LV[c.nl] = 0.0f;
-            ex.LA[c.nl] = 0.0f;
-        }
-    }
     double acc_b = 0.0, acc_p = 0.0, acc_d = 0.0, acc_th = 0.0, acc_bias = 0.0;
 
-    // One block, from its saved carry-in: recompute, reverse adjoint, gradient sums.
-    // buf[i] holds block nb's inputs and receives block nb - DEPTH's.
-    auto do_block = [&](Slot &bi, int nb) __attribute__((always_inline)) {
+    // One block, from its saved carry-in: reverse adjoint and parameter sums for
+    // block nb (slot bi), and the membrane of block nb - 1 (slot bj).
+    auto do_block = [&](Slot &bi, const Slot &bj, int nb) __attribute__((always_inline)) {
+        const bool has_prev = PIPE && nb >= 1;   // uniform over the workgroup
+        if constexpr (!PIPE) {   // this block's membrane, now
+            const int cts0 = min(bi.cts, TR);
+            float uu[L];
+            seg_scan(c, bi.x, cts0 > 0 ? cts0 - 1 : 0, uu);
+            seg_membrane(c, bi.cv, 0.0f, fmaf(c.pf, bi.ca, cts0 == TR ? 1.0f : 0.0f), uu, vtn, thn);
+        }
+        // stage 1a: masked scan of block nb - 1
+        float uun[L];
+        float a1n = 0.0f;
+        if (has_prev) {
+            const int ctsn = min(bj.cts, TR);
+            a1n = fmaf(c.pf, bj.ca, ctsn == TR ? 1.0f : 0.0f);
+            seg_scan(c, bj.x, ctsn > 0 ? ctsn - 1 : 0, uun);
+            if constexpr (SEG > 1) ex.X[par(nb - 1) + c.w * NWG + c.nl] = uun[L - 1];
+        }
+
+        // stage 1b: block nb, with V~ and theta from the previous iteration
         const Slot &cur = bi;
         const int cts = min(cur.cts, TR);
         // the block's spike step, as the forward decided it (carry-in of block nb + 1)
@@ -536,14 +568,8 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
         const float cv = cur.cv, ca = cur.ca;
         const int mpre = cts > 0 ? cts - 1 : 0;
         const float a1 = fmaf(c.pf, ca, cts == TR ? 1.0f : 0.0f);
-        float vt[L], th[L];
-        block_membrane<SEG, L, EVEN>(c, ex, cur.x, cv, a1, mpre, vt, th);
-        if constexpr (SEG > 1) {
-            // wave 0's lambdas of block nb + 1 (read before this block's exchange
-            // barrier, after which wave 0 overwrites them)
-            lamV_c = ex.LV[c.nl];
-            lamA_c = ex.LA[c.nl];
-        }
+        const float (&vt)[L] = vtn;
+        const float (&th)[L] = thn;
         const int tsc = min(ts, TR);
         // quiet block: no spike in this block and none at the end of the previous
         // one anywhere in the wave -> no reset, no mask, no post-spike terms
@@ -601,36 +627,36 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
                 rA[k] = ra;
             }
         }
-        // incoming lambdas at this segment's end: compose the later segments' maps
-        // (lam_start = R + M lam_end) from the block end; wave 0 also forms the
-        // block's lambdas at step 1 and publishes them for the block before
-        float lVin, lAin, Vprev0;
+
+        // stage 2: one barrier, then the incoming lambdas at this segment's end
+        // (composing the later segments' maps lam_start = R + M lam_end from the
+        // block end) and the block's lambdas at step 1
+        float lVin, lAin, Vprev0, nlV, nlA;
         if constexpr (SEG > 1) {
-            ex.M[c.w * NWG + c.nl] = pv;
-            ex.R[c.w * NWG + c.nl] = rv;
-            ex.RA[c.w * NWG + c.nl] = ra;
-            ex.VL[c.w * NWG + c.nl] = quiet ? vt[L - 1] : Vk[L - 1];
+            const int po = par(nb);
+            ex.M[po + c.w * NWG + c.nl] = pv;
+            ex.R[po + c.w * NWG + c.nl] = rv;
+            ex.RA[po + c.w * NWG + c.nl] = ra;
+            ex.VL[po + c.w * NWG + c.nl] = quiet ? vt[L - 1] : Vk[L - 1];
             __syncthreads();
             float lv = lamV_c, la = lamA_c;
-#pragma unroll
-            for (int s = SEG - 1; s >= 1; s--) {
-                if (s > c.w) {   // wave-uniform
-                    lv = fmaf(ex.M[s * NWG + c.nl], lv, ex.R[s * NWG + c.nl]);
-                    la = fmaf(c.pseg(s), la, ex.RA[s * NWG + c.nl]);
-                }
-            }
             lVin = lv;
             lAin = la;
-            Vprev0 = c.w > 0 ? ex.VL[(c.w - 1) * NWG + c.nl] : cv;
-            if (c.w == 0) {
-                ex.LV[c.nl] = fmaf(pv, lVin, rv);
-                ex.LA[c.nl] = fmaf(c.pseg(0), lAin, ra);
+#pragma unroll
+            for (int s = SEG - 1; s >= 0; s--) {
+                lVin = (s == c.w) ? lv : lVin;
+                lAin = (s == c.w) ? la : lAin;
+                lv = fmaf(ex.M[po + s * NWG + c.nl], lv, ex.R[po + s * NWG + c.nl]);
+                la = fmaf(c.pseg(s), la, ex.RA[po + s * NWG + c.nl]);
             }
+            nlV = lv;
+            nlA = la;
+            Vprev0 = c.w > 0 ? ex.VL[po + (c.w - 1) * NWG + c.nl] : cv;
         } else {
             lVin = lamV_c;
             lAin = lamA_c;
-            lamV_c = fmaf(pv, lVin, rv);
-            lamA_c = fmaf(c.pseg(0), lAin, ra);
+            nlV = fmaf(pv, lamV_c, rv);
+            nlA = fmaf(c.pseg(0), lamA_c, ra);
             Vprev0 = cv;
         }
 
@@ -692,21 +718,33 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
         acc_d += (double)pdd;
         acc_th += (double)pth;
         acc_bias += (double)pbias;
+        lamV_c = nlV;
+        lamA_c = nlA;
+
+        // stage 2b: the membrane of block nb - 1, for the next iteration
+        if (has_prev) {
+            float E = 0.0f, U;
+            if constexpr (SEG > 1) seg_horner(c, ex.X + par(nb - 1), E, U);
+            seg_membrane(c, bj.cv, E, a1n, uun, vtn, thn);
+        }
         // prefetch block nb - DEPTH into this slot, after the last use of cur (so
         // the loads can target the slot's own registers; see the forward)
         load_block(bi, nb - DEPTH);
     };
     // Full groups of DEPTH blocks without per-block guards, then the remainder
-    // (the reason is given at the forward's loop).
+    // (the reason is given at the forward's loop). Slot i holds block nb, slot
+    // i + 1 (mod DEPTH) block nb - 1; DEPTH >= 3 keeps a whole iteration between
+    // a slot's prefetch and its first use by the masked scan.
+    static_assert(!PIPE || DEPTH >= 3, "the backward pipeline reads the next block's slot one iteration early");
     wait_vmem_all();
     int r0 = 0;
     for (; r0 + DEPTH <= a.NB; r0 += DEPTH) {
 #pragma unroll
-        for (int i = 0; i < DEPTH; i++) do_block(buf[i], a.NB - 1 - (r0 + i));
+        for (int i = 0; i < DEPTH; i++) do_block(buf[i], buf[(i + 1) % DEPTH], a.NB - 1 - (r0 + i));
     }
 #pragma unroll
     for (int i = 0; i < DEPTH; i++)
-        if (r0 + i < a.NB) do_block(buf[i], a.NB - 1 - (r0 + i));   // uniform over the workgroup
+        if (r0 + i < a.NB) do_block(buf[i], buf[(i + 1) % DEPTH], a.NB - 1 - (r0 + i));   // uniform
     // per-(b, n) sums over this neuron's segment-waves, in a fixed order
     if constexpr (SEG > 1) {
         double *red = reinterpret_cast<double *>(ex.X);   // reuse the exchange area
@@ -748,7 +786,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
 #define ALIF_BWD_AHEAD 32
 #endif
 #define ALIF_FWD_MIN_DEPTH 4
-#define ALIF_BWD_MIN_DEPTH 2
+#define ALIF_BWD_MIN_DEPTH (SEG > 1 ? 3 : 2)   // the pipelined backward needs 3
 
 constexpr int clamp_depth(int want, int lo, int hi) { return want < lo ? lo : (want > hi ? hi : want); }
 template <int SEG, int L>
@@ -756,15 +794,15 @@ constexpr int fwd_depth() {   // <= 64 prefetched floats per lane
     return clamp_depth((ALIF_FWD_AHEAD + SEG * L - 1) / (SEG * L), ALIF_FWD_MIN_DEPTH, 64 / L);
 }
 template <int SEG, int L>
-constexpr int bwd_depth() {   // <= 16 prefetched steps (x, dL/dS and maybe dL/dV, dL/dtheta) per lane
-    return clamp_depth((ALIF_BWD_AHEAD + SEG * L - 1) / (SEG * L), ALIF_BWD_MIN_DEPTH, 16 / L);
+constexpr int bwd_depth() {   // <= 12 prefetched steps (x, dL/dS and maybe dL/dV, dL/dtheta) per lane
+    return clamp_depth((ALIF_BWD_AHEAD + SEG * L - 1) / (SEG * L), ALIF_BWD_MIN_DEPTH, 12 / L);
 }
 
 template <int SEG, int L>
 hipError_t blocks_fwd_launch(const FwdArgs &a, hipStream_t st) {
     const int grid = a.B * a.n_groups;
     if (grid == 0) return hipSuccess;
-    const size_t sm = smem_bytes<SEG, L>(a.TR);
+    const size_t sm = fwd_smem_bytes<SEG, L>(a.TR);
     constexpr int TH = Geo<SEG>::THREADS;
     const bool tr = a.V || a.TH;
 #define ALIF_LF(TRC, SD)                                                                          \
@@ -793,7 +831,7 @@ template <int SEG, int L>
 hipError_t blocks_bwd_launch(const BwdArgs &a, hipStream_t st) {
     const int grid = a.B * a.n_groups;
     if (grid == 0) return hipSuccess;
-    const size_t sm = smem_bytes<SEG, L>(a.TR);
+    const size_t sm = bwd_smem_bytes<SEG, L>(a.TR);
     constexpr int TH = Geo<SEG>::THREADS;
     const bool gvt = a.gV || a.gTH, gi = a.gI != nullptr;
 #define ALIF_LB(G1, G2)                                                                           \
@@ -813,7 +851,6 @@ hipError_t blocks_bwd_launch(const BwdArgs &a, hipStream_t st) {
 
 #define ALIF_INSTANTIATE(SEG, L)                                                        \
     template hipError_t blocks_fwd_launch<SEG, L>(const FwdArgs &, hipStream_t);       \
-    template hipError_t blocks_bwd_launch<SEG, L>(const BwdArgs &, hipStream_t);       \
-    template size_t smem_bytes<SEG, L>(int);
+    template hipError_t blocks_bwd_launch<SEG, L>(const BwdArgs &, hipStream_t);
 
 }  // namespace alif

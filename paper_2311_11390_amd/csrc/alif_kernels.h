@@ -93,7 +93,6 @@ struct BlockConfig {
 };
 BlockConfig block_config(int TR);
 int block_neurons_per_wg(int seg);
-size_t block_smem_bytes(int seg, int TR);
 
 hipError_t launch_blocks_fwd(const FwdArgs &a, hipStream_t st);
 hipError_t launch_blocks_bwd(const BwdArgs &a, hipStream_t st);
