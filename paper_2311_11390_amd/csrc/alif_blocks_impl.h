@@ -68,12 +68,16 @@ __device__ __forceinline__ Exch<SEG> exch_at(unsigned char *base) {
     return Exch<SEG>{f, reinterpret_cast<int *>(f + SZ), f + 2 * SZ, f + 3 * SZ, f + 4 * SZ, f + 5 * SZ};
 }
 
-// LDS layouts. Forward: pd [NWG][TR] f64 | pfp [NWG][RL] f32 | exchange 6 x [SEG][NWG] f32.
+// LDS layouts. Forward: pd [NWG][TR] f64 | pfp [NWG][RL] f32 | one or two copies of the exchange arrays.
 // Backward (no carry, so no pd): pfp | two copies of the exchange arrays.
+// whether the forward runs as a two-stage pipeline (see k_blocks_fwd)
+template <int SEG>
+__host__ __device__ constexpr bool fwd_pipelined() { return SEG == 4 || SEG == 8; }
+
 template <int SEG, int L>
-size_t fwd_smem_bytes(int TR) {
+size_t fwd_smem_bytes(int TR) {   // two exchange copies when the forward is pipelined
     constexpr int NWG = Geo<SEG>::NWG;
-    const size_t ex = SEG > 1 ? (size_t)Exch<SEG>::SIZE * sizeof(float) : 0;
+    const size_t ex = SEG > 1 ? (size_t)(fwd_pipelined<SEG>() ? 2 : 1) * Exch<SEG>::SIZE * sizeof(float) : 0;
     return (size_t)NWG * TR * sizeof(double) + (size_t)NWG * ptab_row(TR, L) * sizeof(float) + ex;
 }
 template <int SEG, int L>
@@ -350,37 +354,11 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_fwd(FwdArgs a) {
 #pragma unroll
         for (int k = 0; k < L; k++) buf[i][k] = ld_f32(rI, c.off(k, (uint32_t)min((size_t)i * blk4, TN * 4)));
 
-    // One block: integrate, find the crossing, write the outputs, carry on.
-    // buf[i] holds block nb's input and receives block nb + DEPTH's.
-    auto do_block = [&](float (&bi)[L], int nb) __attribute__((always_inline)) {
-        float x[L];
-#pragma unroll
-        for (int k = 0; k < L; k++) x[k] = bi[k];
-
-        const float cv = (float)v0d, ca = (float)a0d;
-        const int mpre = cts > 0 ? cts - 1 : 0;
-        const float a1 = fmaf(c.pf, ca, cts == TR ? 1.0f : 0.0f);
-        {   // carry-in of this block, for the backward pass
-            const uint32_t e = (uint32_t)(nb * N);
-            st_f32(rCv, ck4 + e * 4u, cv);
-            st_f32(rCa, ck4 + e * 4u, ca);
-            st_u8(rCt, ck1 + e, (uint8_t)cts);
-        }
-        float vt[L], th[L], uTR;
-        const int ts = block_integrate<SEG, L, EVEN>(c, ex, x, cv, a1, mpre, vt, th, uTR);
+    // The block's outputs (spikes and corrected traces: reset after t_s, Eqs. 2
+    // and 5) and the carry to the next block (Props. 4-5, FP64).
+    auto finish_block = [&](int nb, int ts, const float (&vt)[L], const float (&th)[L], float uTR)
+        __attribute__((always_inline)) {
         const bool spk = ts <= TR;
-        // prefetch block nb + DEPTH into the registers block nb has just finished
-        // with (beyond the end of the row: out of range -> 0). Issued only now,
-        // after the last use of x, so that the load can target bi's own
-        // registers: loading earlier makes the compiler load into temporaries and
-        // copy them back at the end of the block, which waits for the load.
-        {
-            const uint32_t nxt = (uint32_t)min((size_t)(nb + DEPTH) * blk4, TN * 4);
-#pragma unroll
-            for (int k = 0; k < L; k++) bi[k] = ld_f32(rI, c.off(k, nxt));
-        }
-
-        // outputs: spikes and corrected traces (reset after t_s, Eqs. 2 and 5)
         const uint32_t bo = (uint32_t)nb * blk4;
 #pragma unroll
         for (int k = 0; k < L; k++) {
@@ -397,7 +375,6 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_fwd(FwdArgs a) {
                 st_f32(rT, o4, after ? fmaf(c.dd, pa, th[k]) : th[k]);
             }
         }
-        // carry to the next block (Props. 4-5), FP64
         const double e1 = cts == TR ? c.pTm1 : 0.0;
         const double e2 = pd_tab[pdrow + max(0, TR - 1 - min(ts, TR))];
         const double extra = e1 + ((spk && ts < TR) ? e2 : 0.0);
@@ -405,19 +382,124 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_fwd(FwdArgs a) {
         a0d = fma(c.pT, a0d, extra);
         cts = spk ? ts : 0;
     };
+    // carry-in of block nb, for the backward pass
+    auto store_carry_in = [&](int nb, float cv, float ca) __attribute__((always_inline)) {
+        const uint32_t e = (uint32_t)(nb * N);
+        st_f32(rCv, ck4 + e * 4u, cv);
+        st_f32(rCa, ck4 + e * 4u, ca);
+        st_u8(rCt, ck1 + e, (uint8_t)cts);
+    };
+
+    // One block: integrate, find the crossing, write the outputs, carry on.
+    // buf[i] holds block nb's input and receives block nb + DEPTH's.
+    auto do_block = [&](float (&bi)[L], int nb) __attribute__((always_inline)) {
+        float x[L];
+#pragma unroll
+        for (int k = 0; k < L; k++) x[k] = bi[k];
+        const float cv = (float)v0d, ca = (float)a0d;
+        const int mpre = cts > 0 ? cts - 1 : 0;
+        const float a1 = fmaf(c.pf, ca, cts == TR ? 1.0f : 0.0f);
+        store_carry_in(nb, cv, ca);
+        float vt[L], th[L], uTR;
+        const int ts = block_integrate<SEG, L, EVEN>(c, ex, x, cv, a1, mpre, vt, th, uTR);
+        // prefetch block nb + DEPTH into the registers block nb has just finished
+        // with (beyond the end of the row: out of range -> 0). Issued only now,
+        // after the last use of x, so that the load can target bi's own
+        // registers: loading earlier makes the compiler load into temporaries and
+        // copy them back at the end of the block, which waits for the load.
+        {
+            const uint32_t nxt = (uint32_t)min((size_t)(nb + DEPTH) * blk4, TN * 4);
+#pragma unroll
+            for (int k = 0; k < L; k++) bi[k] = ld_f32(rI, c.off(k, nxt));
+        }
+        finish_block(nb, ts, vt, th, uTR);
+    };
+
+    // Pipelined form (SEG 4 or 8: every wave of a workgroup holds the same 64
+    // neurons, so a vote over one wave is a vote over the workgroup; 16 segments
+    // would not fit two copies of the exchange arrays in LDS at T_R = 128). The
+    // iteration for block nb integrates block nb from its scan and Horner sums,
+    // done one iteration earlier, and scans block nb + 1 assuming no refractory
+    // mask; both results go through LDS behind a single barrier. Once t_s of
+    // block nb is known, block nb + 1 is rescanned (with a second barrier) only if
+    // some neuron of the workgroup needs the mask; otherwise the assumption held
+    // and the scan took exactly the unmasked path. The exchange arrays come in
+    // two copies selected by block parity. Slot (i + 1) mod DEPTH holds block
+    // nb + 1 and is refilled with block nb + 1 + DEPTH after its scan.
+    constexpr bool PIPE = fwd_pipelined<SEG>();
+    const auto par = [](int nb) { return (nb & 1) * Exch<SEG>::SIZE; };
+    float uuc[L];               // scan of the block the next iteration integrates
+    float Ec = 0.0f, Uc = 0.0f; // its input part at this segment's start and at the block end
+    auto do_block_pipe = [&](float (&bj)[L], int nb, bool has_next) __attribute__((always_inline)) {
+        constexpr int NWG_ = Geo<SEG>::NWG;
+        const float cv = (float)v0d, ca = (float)a0d;
+        const float a1 = fmaf(c.pf, ca, cts == TR ? 1.0f : 0.0f);
+        store_carry_in(nb, cv, ca);
+        float vt[L], th[L];
+        const int cand = seg_membrane(c, cv, Ec, a1, uuc, vt, th);
+        const float uTR = Uc;
+        ex.C[par(nb) + c.w * NWG_ + c.nl] = cand;
+        float uun[L];
+        if (has_next) {
+            seg_scan(c, bj, 0, uun);
+            ex.X[par(nb + 1) + c.w * NWG_ + c.nl] = uun[L - 1];
+        }
+        __syncthreads();
+        int ts = ALIF_NO_SPIKE;
+#pragma unroll
+        for (int s2 = 0; s2 < SEG; s2++) ts = min(ts, ex.C[par(nb) + s2 * NWG_ + c.nl]);
+        finish_block(nb, ts, vt, th, uTR);
+        if (has_next) {
+            const int mpren = cts > 0 ? cts - 1 : 0;
+            if (__any(mpren > 0)) {   // uniform over the workgroup
+                seg_scan(c, bj, mpren, uun);
+                ex.X[par(nb + 1) + c.w * NWG_ + c.nl] = uun[L - 1];
+                __syncthreads();
+            }
+            seg_horner(c, ex.X + par(nb + 1), Ec, Uc);
+#pragma unroll
+            for (int k = 0; k < L; k++) uuc[k] = uun[k];
+            // prefetch block nb + 1 + DEPTH into the slot block nb + 1 has left
+            const uint32_t nxt = (uint32_t)min((size_t)(nb + 1 + DEPTH) * blk4, TN * 4);
+#pragma unroll
+            for (int k = 0; k < L; k++) bj[k] = ld_f32(rI, c.off(k, nxt));
+        }
+    };
+
     // Full groups of DEPTH blocks with no per-block guard: a guard would give the
     // loop paths from an early block straight to its latch, and the compiler's
     // wait analysis at the loop head would then assume the shortest distance to
-    // every prefetch. The last NB % DEPTH blocks run after the loop.
-    wait_vmem_all();
-    int nb0 = 0;
-    for (; nb0 + DEPTH <= a.NB; nb0 += DEPTH) {
+    // every prefetch. The remaining blocks run after the loop.
+    if constexpr (PIPE) {
+        {   // block 0's scan and Horner sums
+            seg_scan(c, buf[0], cts > 0 ? cts - 1 : 0, uuc);
+            ex.X[par(0) + c.w * NWG + c.nl] = uuc[L - 1];
+            __syncthreads();
+            seg_horner(c, ex.X + par(0), Ec, Uc);
+            const uint32_t nxt = (uint32_t)min((size_t)DEPTH * blk4, TN * 4);
 #pragma unroll
-        for (int i = 0; i < DEPTH; i++) do_block(buf[i], nb0 + i);
+            for (int k = 0; k < L; k++) buf[0][k] = ld_f32(rI, c.off(k, nxt));
+        }
+        wait_vmem_all();
+        int nb0 = 0;
+        for (; nb0 + DEPTH < a.NB; nb0 += DEPTH) {   // block nb + 1 always exists here
+#pragma unroll
+            for (int i = 0; i < DEPTH; i++) do_block_pipe(buf[(i + 1) % DEPTH], nb0 + i, true);
+        }
+#pragma unroll
+        for (int i = 0; i < DEPTH; i++)
+            if (nb0 + i < a.NB) do_block_pipe(buf[(i + 1) % DEPTH], nb0 + i, nb0 + i + 1 < a.NB);   // uniform
+    } else {
+        wait_vmem_all();
+        int nb0 = 0;
+        for (; nb0 + DEPTH <= a.NB; nb0 += DEPTH) {
+#pragma unroll
+            for (int i = 0; i < DEPTH; i++) do_block(buf[i], nb0 + i);
+        }
+#pragma unroll
+        for (int i = 0; i < DEPTH; i++)
+            if (nb0 + i < a.NB) do_block(buf[i], nb0 + i);   // uniform over the workgroup
     }
-#pragma unroll
-    for (int i = 0; i < DEPTH; i++)
-        if (nb0 + i < a.NB) do_block(buf[i], nb0 + i);   // uniform over the workgroup
     {   // the final carry, after the carry-in of the last block
         const uint32_t e = (uint32_t)(a.NB * N);
         st_f32(rCv, ck4 + e * 4u, (float)v0d);
