@@ -149,6 +149,26 @@ def cpu_baseline(w, cpu_seconds, threads):
     return Irows.size * passes / el, el, cpu, passes, Irows.shape[0]
 
 
+def cpu_baseline_one_core(w, rows):
+    """The same oracle on one thread over the first `rows` (batch, neuron) rows."""
+    import oracle
+    from oracle import _to_rows
+    I = w.inputs["I"]
+    B, T, N = I.shape
+    Irows = _to_rows(I.astype(np.float64))[:rows]
+    lp = w.layers[0]
+    tile = lambda q: np.tile(np.asarray(q, np.float64), B)[:rows]
+    prm = [tile(lp.tau_mem), tile(lp.tau_adapt), tile(lp.d), tile(lp.theta0)]
+    g = np.random.default_rng(1).standard_normal(Irows.shape)
+    TR = oracle.refractory_steps(w.dt, w.arp)
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    fw = oracle.forward_rows(Irows, *prm, w.dt, TR)
+    oracle.backward_rows(fw, *prm, w.dt, 10.0, gS=g, want_gI=False)
+    el = time.perf_counter() - t0
+    return Irows.size / el, el, Irows.shape[0]
+
+
 def serve_leg(n_requests, rate_hz, max_slots, budget_gib, output="events", seed=1):
     """Replay a Poisson request stream (uneven N, T and DT; OU current drawn on the
     device) against the library's server in real time, then the same stream
@@ -334,9 +354,13 @@ def main():
         threads = min(threads, 16)
         log(f"[bench] oracle CPU baseline: whole workload, {threads} threads, >= {args.cpu_seconds} CPU-s")
         rate, el, cpu_s, passes, rows = cpu_baseline(w, args.cpu_seconds, threads)
+        r1, el1, rows1 = cpu_baseline_one_core(w, 512)
         cpu = {"value": rate, "unit": "neuron-steps/s", "cores": threads, "kind": "oracle",
                "sample": f"the whole workload ({rows} (batch, neuron) rows x {T} steps), forward + "
-                         f"backward, {passes} passes: {el:.2f} s wall, {cpu_s:.1f} CPU-s"}
+                         f"backward, {passes} passes: {el:.2f} s wall, {cpu_s:.1f} CPU-s",
+               "one_core": {"value": r1, "cores": 1,
+                            "sample": f"the first {rows1} (batch, neuron) rows x {T} steps, forward + "
+                                      f"backward: {el1:.2f} s"}}
 
     serve = None
     if args.serve_requests > 0:
