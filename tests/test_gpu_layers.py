@@ -31,7 +31,7 @@ def _as_torch_spikes(x, kind):
 
 @pytest.mark.parametrize("kind", ["u8", "bf16", "f32"])
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("shape", [(2, 77, 37, 19), (3, 150, 700, 130), (1, 260, 200, 100)])
+@pytest.mark.parametrize("shape", [(2, 77, 37, 19), (3, 150, 700, 130), (1, 260, 200, 100), (2, 301, 100, 257)])
 def test_input_current_gemm(kind, prec, shape):
     import torch
     from paper_2311_11390_amd import alif
