@@ -176,6 +176,29 @@ int alif_input_current(const alif_desc *desc, const void *input, const float *W,
                        const float *bias, float *current, void *stream);
 
 /*
+ * Gradients of the Eq. 3 projection for a spike-input layer, given the gradient
+ * of the loss with respect to its input current (what alif_backward writes to
+ * grad_current), as MFMA GEMMs in desc->gemm_precision (BF16 rounds
+ * grad_current and W to bfloat16 and accumulates in FP32):
+ *   alif_weight_grad  grad_W[n][i] = sum over b, t of grad_current[b][t][n] x[b][t][i]
+ *                     (device float [N][n_in]); the sum over b, t is split into
+ *                     partial sums in `workspace` (device, of
+ *                     alif_weight_grad_workspace_bytes() bytes; NULL when that is 0)
+ *                     and reduced in a fixed order, so results are reproducible
+ *   alif_input_grad   grad_input[b][t][i] = sum over n of grad_current[b][t][n] W[n][i]
+ *                     (device float [B][T][n_in]), the gradient passed to the layer
+ *                     below as its spike gradient
+ * input: device spikes [B][T][n_in] of desc->input_kind; W device float
+ * [N][n_in]; grad_current device float [B][T][N]. alif_backward makes the same
+ * two calls when given grad_W / grad_input.
+ */
+int alif_weight_grad_workspace_bytes(const alif_desc *desc, size_t *bytes);
+int alif_weight_grad(const alif_desc *desc, const float *grad_current, const void *input,
+                     float *grad_W, void *workspace, void *stream);
+int alif_input_grad(const alif_desc *desc, const float *grad_current, const float *W,
+                    float *grad_input, void *stream);
+
+/*
  * Forward pass of one ALIF layer over T steps (Eqs. 1-5 computed by Blocks,
  * Props. 1-5; or, with desc->algo, by the sequential baselines).
  *   input    device: current float [B][T][N] (ALIF_INPUT_CURRENT_F32; the bias is

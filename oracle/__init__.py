@@ -104,6 +104,21 @@ def input_current(x: np.ndarray, W: np.ndarray, bias=None) -> np.ndarray:
     return out.reshape(*lead, n)
 
 
+def weight_grad(gI: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """Gradient with respect to W of the Eq. 3 projection I = b + W x, given the
+    current gradient gI[..., n]: dL/dW[n][i] = sum over (b, t) of gI[n] x[i]
+    (one FP64 matrix product; x may be spikes or any real input)."""
+    gI = np.asarray(gI, np.float64)
+    x = np.asarray(x, np.float64)
+    return gI.reshape(-1, gI.shape[-1]).T @ x.reshape(-1, x.shape[-1])
+
+
+def input_grad(gI: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """Gradient with respect to the input x of the Eq. 3 projection I = b + W x:
+    dL/dx[..., i] = sum over n of gI[..., n] W[n][i] (one FP64 matrix product)."""
+    return np.asarray(gI, np.float64) @ np.asarray(W, np.float64)
+
+
 def forward_rows(I, tau_m, tau_a, d, theta0, dt, TR, force=None):
     """Standard ALIF (Eqs. 1-5) on independent rows I[R][T]; params are [R].
 

@@ -69,6 +69,9 @@ _SIGNATURES = {
     "alif_backward_workspace_bytes": (c_int, [POINTER(AlifDesc), POINTER(c_size_t)]),
     "alif_decay_tables": (c_int, [POINTER(AlifDesc), POINTER(AlifParams), _P, _P, _P]),
     "alif_input_current": (c_int, [POINTER(AlifDesc), _P, _P, _P, _P, _P]),
+    "alif_weight_grad_workspace_bytes": (c_int, [POINTER(AlifDesc), POINTER(c_size_t)]),
+    "alif_weight_grad": (c_int, [POINTER(AlifDesc), _P, _P, _P, _P, _P]),
+    "alif_input_grad": (c_int, [POINTER(AlifDesc), _P, _P, _P, _P]),
     "alif_forward": (c_int, [POINTER(AlifDesc), POINTER(AlifParams), _P, _P, _P,
                              POINTER(AlifState), POINTER(AlifState), _P, _P, _P, _P, _P]),
     "alif_backward": (c_int, [POINTER(AlifDesc), POINTER(AlifParams), _P, _P, _P, _P,

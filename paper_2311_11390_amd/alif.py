@@ -183,6 +183,33 @@ def input_current(x: torch.Tensor, W: torch.Tensor, bias=None, gemm_precision=L.
     return out
 
 
+def weight_grad(grad_current: torch.Tensor, x: torch.Tensor, gemm_precision=L.GEMM_FP32, workspace=None):
+    """grad_W [N][n_in] = sum_{b,t} grad_current[b][t][:]^T x[b][t][:] (alif_weight_grad)."""
+    B, T, n_in = x.shape
+    N = grad_current.shape[2]
+    desc = make_desc(B, T, N, 1.0, 2.0, n_in, _INPUT_KIND[x.dtype], gemm_precision)
+    if workspace is None:
+        n = ctypes.c_size_t()
+        L.check(L.load().alif_weight_grad_workspace_bytes(ctypes.byref(desc), ctypes.byref(n)))
+        workspace = torch.empty(max(1, n.value), dtype=torch.uint8, device=x.device)
+    out = torch.empty(N, n_in, dtype=torch.float32, device=x.device)
+    L.check(L.load().alif_weight_grad(ctypes.byref(desc), _p(grad_current), _p(x), _p(out), _p(workspace),
+                                      _stream(x.device)))
+    return out
+
+
+def input_grad(grad_current: torch.Tensor, W: torch.Tensor, input_kind=L.INPUT_SPIKES_U8,
+               gemm_precision=L.GEMM_FP32):
+    """grad_input [B][T][n_in] = grad_current[b][t][:] W (alif_input_grad)."""
+    B, T, N = grad_current.shape
+    n_in = W.shape[1]
+    desc = make_desc(B, T, N, 1.0, 2.0, n_in, input_kind, gemm_precision)
+    out = torch.empty(B, T, n_in, dtype=torch.float32, device=W.device)
+    L.check(L.load().alif_input_grad(ctypes.byref(desc), _p(grad_current), _p(W), _p(out),
+                                     _stream(W.device)))
+    return out
+
+
 def device_status(device=None) -> int:
     bits = ctypes.c_uint32()
     L.check(L.load().alif_device_status(ctypes.byref(bits), _stream(device)))

@@ -214,6 +214,46 @@ int alif_input_current(const alif_desc *desc, const void *input, const float *W,
     return ALIF_OK;
 }
 
+int alif_weight_grad_workspace_bytes(const alif_desc *desc, size_t *bytes) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    if (!bytes) return fail(ALIF_EINVAL, "bytes is NULL");
+    *bytes = p.spikes_in ? gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.n_in) : 0;
+    return ALIF_OK;
+}
+
+int alif_weight_grad(const alif_desc *desc, const float *grad_current, const void *input, float *grad_W,
+                     void *workspace, void *stream) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    if (!p.spikes_in) return fail(ALIF_EINVAL, "alif_weight_grad needs a spike input_kind");
+    if (!grad_current || !input || !grad_W) return fail(ALIF_EINVAL, "grad_current, input and grad_W are required");
+    if (!workspace && gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.n_in) > 0)
+        return fail(ALIF_EINVAL, "workspace is NULL");
+    GemmIn in;
+    in.kind = desc->input_kind;
+    in.ptr = input;
+    hipError_t e = gemm_weight_grad((size_t)p.B * p.T, p.N, p.n_in, grad_current, in, grad_W,
+                                    desc->gemm_precision == ALIF_GEMM_BF16, workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "weight-gradient GEMM");
+    return ALIF_OK;
+}
+
+int alif_input_grad(const alif_desc *desc, const float *grad_current, const float *W, float *grad_input,
+                    void *stream) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    if (!p.spikes_in) return fail(ALIF_EINVAL, "alif_input_grad needs a spike input_kind");
+    if (!grad_current || !W || !grad_input) return fail(ALIF_EINVAL, "grad_current, W and grad_input are required");
+    hipError_t e = gemm_input_grad((size_t)p.B * p.T, p.N, p.n_in, grad_current, W, grad_input,
+                                   desc->gemm_precision == ALIF_GEMM_BF16, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "input-gradient GEMM");
+    return ALIF_OK;
+}
+
 int alif_forward(const alif_desc *desc, const alif_params *prm, const void *input, const float *W,
                  float *current, const alif_state *init, alif_state *final, void *spikes, float *v,
                  float *theta, void *carries, void *stream) {

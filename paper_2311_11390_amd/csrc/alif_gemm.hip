@@ -121,122 +121,192 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// Fast path for C = A W^T (+ bias) with both operands k-contiguous: the Eq. 3
-// current I = b + x W^T of a spike-input layer (A = x [M][K] as float, uint8 or
-// bf16; W [N][K] float). A 256-thread workgroup owns a 128 x 128 tile of C (four
-// waves of 64 x 64, 4 x 4 MFMA accumulators each). K moves in stages of BK:
-// every thread loads half a row of A and of W (raw buffer loads: rows beyond M
-// or N read 0; steps beyond K are zeroed), converts them to the MFMA operand
-// type in registers and stores them to one of two LDS buffers; while a stage is
-// multiplied, the next one is loaded. One barrier per stage. Workgroups are
-// numbered so that the N tiles of one M tile run on one XCD and share its rows
-// of A in that XCD's L2.
+// Tiled fast path. C = A B^T (+ bias) on MFMA tiles fed by a two-stage register
+// pipeline: while the LDS buffer of one K stage is multiplied, every thread
+// loads its share of the next stage with raw buffer loads, converts it to the
+// MFMA operand type and stores it to the other LDS buffer; one barrier per stage.
+// Both operands sit in LDS as [row][k] (k contiguous) whatever their layout in
+// memory:
+//   k-contiguous operand ([row][k] in memory): a thread loads EPT consecutive k
+//     of one row;
+//   row-contiguous operand ([k][row] in memory): a thread loads RR consecutive
+//     rows for 8 consecutive k and transposes them in registers.
+// BF16 tiles are 256 x 128 over eight waves (the operand read as float is reused
+// over more rows), FP32 tiles 128 x 128 over four; each wave owns 64 x 64 as
+// 4 x 4 MFMA 16 x 16 accumulators. Workgroups are numbered so that the N tiles
+// of one M tile (and K split) run on one XCD and share its rows of A in that
+// XCD's L2. A split over K writes partial tiles that k_split_reduce sums.
+// The three uses: the Eq. 3 current (A = spikes [M][K], B = W [N][K], both
+// k-contiguous), the input gradient (A = gI k-contiguous, B = W row-contiguous)
+// and the weight gradient (A = gI and B = spikes, both row-contiguous).
 // ---------------------------------------------------------------------------
-// BF16: 256 x 128 tiles with eight waves (W, read as float, is reused over more
-// rows of A); FP32: 128 x 128 with four waves.
 template <bool BF16>
-struct NT {
+struct Tile {
     static constexpr int BM = BF16 ? 256 : 128, BN = 128;
     static constexpr int THREADS = BF16 ? 512 : 256;
     static constexpr int BK = BF16 ? 64 : 32;           // k per stage
-    static constexpr int AH = BK * BM / THREADS;          // A elements per thread per stage
-    static constexpr int BH = BK * BN / THREADS;          // W elements per thread per stage
     static constexpr int LDK = BF16 ? BK + 8 : BK + 4;   // LDS row (elements), 16-byte multiple
     using T = typename std::conditional<BF16, __bf16, float>::type;
     static constexpr size_t lds_bytes() { return (size_t)2 * (BM + BN) * LDK * sizeof(T); }
 };
 
-// HALF consecutive elements of one row, as float; k >= kmax read as 0
-template <int DT, int HALF>
-__device__ __forceinline__ void load_half_row(rsrc_t r, uint32_t off, int kmax, float (&v)[HALF]) {
-    if constexpr (DT == 0) {            // float, rows 16-byte aligned
+template <int DT>
+constexpr uint32_t elem_bytes() { return DT == 0 ? 4 : (DT == 1 ? 1 : 2); }
+
+// N consecutive elements at byte offset off, as float (one load of N * elem bytes)
+template <int DT, int N>
+__device__ __forceinline__ void load_run(rsrc_t r, uint32_t off, float *v) {
+    static_assert(N == 2 || N == 4, "runs of 2 or 4");
+    if constexpr (DT == 0) {
+        if constexpr (N == 4) {
+            const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
 #pragma unroll
-        for (int q = 0; q < HALF / 4; q++) {
-            const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u * q, 0, 0);
-#pragma unroll
-            for (int e = 0; e < 4; e++) v[4 * q + e] = __uint_as_float(w[e]);
+            for (int e = 0; e < 4; e++) v[e] = __uint_as_float(w[e]);
+        } else {
+            const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+            v[0] = __uint_as_float(w[0]);
+            v[1] = __uint_as_float(w[1]);
         }
-    } else if constexpr (DT == 1) {     // uint8, rows 4-byte aligned
+    } else if constexpr (DT == 1) {
+        const uint32_t w = N == 4 ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0)
+                                  : (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
 #pragma unroll
-        for (int q = 0; q < HALF / 4; q++) {
-            const uint32_t w = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off + 4u * q, 0, 0);
+        for (int e = 0; e < N; e++) v[e] = (float)((w >> (8 * e)) & 0xffu);
+    } else {
+        if constexpr (N == 4) {
+            const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
 #pragma unroll
-            for (int e = 0; e < 4; e++) v[4 * q + e] = (float)((w >> (8 * e)) & 0xffu);
-        }
-    } else {                            // bf16, rows 4-byte aligned
-#pragma unroll
-        for (int q = 0; q < HALF / 2; q++) {
-            const uint32_t w = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off + 4u * q, 0, 0);
-            v[2 * q] = __uint_as_float(w << 16);
-            v[2 * q + 1] = __uint_as_float(w & 0xffff0000u);
+            for (int q = 0; q < 2; q++) {
+                v[2 * q] = __uint_as_float((uint32_t)w[q] << 16);
+                v[2 * q + 1] = __uint_as_float((uint32_t)w[q] & 0xffff0000u);
+            }
+        } else {
+            const uint32_t w = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+            v[0] = __uint_as_float(w << 16);
+            v[1] = __uint_as_float(w & 0xffff0000u);
         }
     }
-#pragma unroll
-    for (int e = 0; e < HALF; e++) v[e] = e < kmax ? v[e] : 0.0f;
 }
 
-template <int ADT, bool BF16>
-__global__ __launch_bounds__(NT<BF16>::THREADS) void k_gemm_nt(GemmArgs g, int n_tiles, int tiles) {
-    using P = NT<BF16>;
+// 8 values to LDS row p (k contiguous) in the MFMA operand type
+template <bool BF16>
+__device__ __forceinline__ void lds_store8(typename Tile<BF16>::T *p, const float *v) {
+    if constexpr (BF16) {
+        bf16x8 q;
+#pragma unroll
+        for (int e = 0; e < 8; e++) q[e] = (__bf16)v[e];
+        *reinterpret_cast<bf16x8 *>(p) = q;
+    } else {
+        *reinterpret_cast<floatx4 *>(p) = floatx4{v[0], v[1], v[2], v[3]};
+        *reinterpret_cast<floatx4 *>(p + 4) = floatx4{v[4], v[5], v[6], v[7]};
+    }
+}
+
+// One operand's ROWS x BK stage: where this thread loads it from and where it
+// puts it in LDS.
+//   ptr, ld: operand base and elements between consecutive rows (k-contiguous)
+//            or consecutive k (row-contiguous);
+//   rows:    valid rows (M or N), row0 the tile's first row;
+//   kb, ke:  the K range of this workgroup's split.
+// k-contiguous: the buffer starts at the tile's first row and ends after its last
+//   valid row, so rows beyond it read 0; k >= ke is zeroed explicitly.
+// row-contiguous: the buffer starts at (kb, row0) and ends after the last valid
+//   row of k = ke - 1, so k >= ke reads 0; rows beyond the valid ones may read
+//   other data, which only reaches rows of C that are never stored.
+template <int DT, bool KM, int ROWS, bool BF16>
+struct Stage {
+    using P = Tile<BF16>;
+    static constexpr int BK = P::BK, LDK = P::LDK;
+    static constexpr int EPT = ROWS * BK / P::THREADS;   // elements per thread per stage
+    static constexpr int RR = EPT / 8;                    // row-contiguous: rows per thread
+    static constexpr int RG = ROWS / RR;                  // row-contiguous: row groups
+    static constexpr int TPR = BK / EPT;                  // k-contiguous: threads per row
+    static constexpr uint32_t ES = elem_bytes<DT>();
+    static_assert(EPT % 8 == 0 && (!KM || P::THREADS / RG == BK / 8), "stage shape");
+
+    rsrc_t r;
+    uint32_t toff;   // byte offset of this thread's first element at k = 0 of the split
+    uint32_t kstep;  // row-contiguous: bytes between consecutive k
+    int kmax0;       // k-contiguous: valid k of this thread at stage 0
+    int lrow, lk;    // LDS row and first k of this thread
+    float v[EPT];
+
+    __device__ __forceinline__ void init(const void *ptr, long long ld, long long rows, long long row0, int kb,
+                                         int ke, int tid) {
+        const char *base = static_cast<const char *>(ptr);
+        const long long vr = rows - row0;                  // valid rows from row0 (> 0)
+        if constexpr (KM) {
+            const int rg = tid % RG, kg = tid / RG;
+            lrow = rg * RR;
+            lk = kg * 8;
+            r = make_rsrc(base + ((size_t)kb * ld + row0) * ES,
+                          (uint32_t)(((size_t)(ke - kb - 1) * ld + vr) * ES));
+            toff = (uint32_t)(((size_t)lk * ld + lrow) * ES);
+            kstep = (uint32_t)(ld * ES);
+        } else {
+            lrow = tid / TPR;
+            lk = (tid % TPR) * EPT;
+            const long long nr = vr < ROWS ? vr : ROWS;
+            r = make_rsrc(base + (size_t)row0 * ld * ES, (uint32_t)((size_t)nr * ld * ES));
+            toff = (uint32_t)(((size_t)lrow * ld + kb + lk) * ES);
+            kmax0 = ke - kb - lk;
+            kstep = 0;
+        }
+    }
+    // load stage s (k = kb + s * BK ...)
+    __device__ __forceinline__ void load(int s) {
+        if constexpr (KM) {
+            const uint32_t o = toff + (uint32_t)(s * BK) * kstep;
+#pragma unroll
+            for (int j = 0; j < 8; j++) load_run<DT, RR>(r, o + (uint32_t)j * kstep, v + j * RR);
+        } else {
+            const uint32_t o = toff + (uint32_t)(s * BK) * ES;
+#pragma unroll
+            for (int q = 0; q < EPT / 4; q++) load_run<DT, 4>(r, o + (uint32_t)(q * 4) * ES, v + q * 4);
+            const int kmax = kmax0 - s * BK;
+#pragma unroll
+            for (int e = 0; e < EPT; e++) v[e] = e < kmax ? v[e] : 0.0f;
+        }
+    }
+    __device__ __forceinline__ void store(typename P::T *buf) const {
+        if constexpr (KM) {
+#pragma unroll
+            for (int rr = 0; rr < RR; rr++) {
+                float c[8];
+#pragma unroll
+                for (int j = 0; j < 8; j++) c[j] = v[j * RR + rr];
+                lds_store8<BF16>(buf + (size_t)(lrow + rr) * LDK + lk, c);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < EPT / 8; q++) lds_store8<BF16>(buf + (size_t)lrow * LDK + lk + 8 * q, v + 8 * q);
+        }
+    }
+};
+
+template <int ADT, bool AKM, int BDT, bool BKM, bool BF16>
+__global__ __launch_bounds__(Tile<BF16>::THREADS) void k_gemm_tiled(GemmArgs g, int m_tiles, int n_tiles,
+                                                                     int kps, int total) {
+    using P = Tile<BF16>;
     using T = typename P::T;
-    constexpr int BM = P::BM, BN = P::BN, BK = P::BK, AH = P::AH, BH = P::BH, LDK = P::LDK;
-    constexpr int APR = BK / AH, BPR = BK / BH;           // threads per staged row of A, of W
-    constexpr uint32_t AES = ADT == 0 ? 4 : (ADT == 1 ? 1 : 2);
+    constexpr int BM = P::BM, BN = P::BN, BK = P::BK, LDK = P::LDK;
     extern __shared__ __align__(16) unsigned char lds[];
     T *As = reinterpret_cast<T *>(lds);                   // [2][BM][LDK]
     T *Bs = As + 2 * BM * LDK;                            // [2][BN][LDK]
 
-    const int work = xcd_remap(blockIdx.x, tiles);
-    const long long m0 = (long long)(work / n_tiles) * BM;
-    const int n0 = (work % n_tiles) * BN;
+    const int work = xcd_remap(blockIdx.x, total);
+    const int tiles = m_tiles * n_tiles;
+    const int z = work / tiles, t = work % tiles;
+    const long long m0 = (long long)(t / n_tiles) * BM;
+    const int n0 = (t % n_tiles) * BN;
+    const int kb = z * kps, ke = min(g.K, kb + kps);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;              // wave tile (wm, wn) of 64 x 64
-    const int K = g.K;
 
-    const rsrc_t rA = make_rsrc(g.A, (uint32_t)((size_t)g.M * K * AES));
-    const rsrc_t rB = make_rsrc(g.B, (uint32_t)((size_t)g.N * K * 4));
-    // staged row and k part of this thread, for A and for W
-    const int ra = tid / APR, ha = tid % APR, rb = tid / BPR, hb = tid % BPR;
-    // byte offsets of the staged rows; a row beyond M or N uses an offset past
-    // the buffer, so its loads read 0
-    const bool a_in = (m0 + ra) < g.M, b_in = (n0 + rb) < g.N;
-    const uint32_t arow = a_in ? (uint32_t)((m0 + ra) * K * AES) : 0u;
-    const uint32_t brow = b_in ? (uint32_t)((size_t)(n0 + rb) * K * 4) : 0u;
-
-    float va[AH], vb[BH];
-    auto load_stage = [&](int k0) {
-        const int ka = k0 + ha * AH, kb = k0 + hb * BH;
-        load_half_row<ADT, AH>(rA, a_in ? arow + (uint32_t)ka * AES : ALIF_OOB, K - ka, va);
-        load_half_row<0, BH>(rB, b_in ? brow + (uint32_t)kb * 4u : ALIF_OOB, K - kb, vb);
-    };
-    auto store_stage = [&](int buf) {
-        T *a = As + (size_t)(buf * BM + ra) * LDK + ha * AH;
-        T *b = Bs + (size_t)(buf * BN + rb) * LDK + hb * BH;
-        if constexpr (BF16) {
-            typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-#pragma unroll
-            for (int q = 0; q < AH / 8; q++) {
-                bf16x8_t pa;
-#pragma unroll
-                for (int e = 0; e < 8; e++) pa[e] = (__bf16)va[8 * q + e];
-                *reinterpret_cast<bf16x8_t *>(a + 8 * q) = pa;
-            }
-#pragma unroll
-            for (int q = 0; q < BH / 8; q++) {
-                bf16x8_t pb;
-#pragma unroll
-                for (int e = 0; e < 8; e++) pb[e] = (__bf16)vb[8 * q + e];
-                *reinterpret_cast<bf16x8_t *>(b + 8 * q) = pb;
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < AH / 4; q++)
-                *reinterpret_cast<floatx4 *>(a + 4 * q) = floatx4{va[4 * q], va[4 * q + 1], va[4 * q + 2], va[4 * q + 3]};
-#pragma unroll
-            for (int q = 0; q < BH / 4; q++)
-                *reinterpret_cast<floatx4 *>(b + 4 * q) = floatx4{vb[4 * q], vb[4 * q + 1], vb[4 * q + 2], vb[4 * q + 3]};
-        }
-    };
+    Stage<ADT, AKM, BM, BF16> sa;
+    Stage<BDT, BKM, BN, BF16> sb;
+    sa.init(g.A, g.lda, g.M, m0, kb, ke, tid);
+    sb.init(g.B, g.ldb, g.N, n0, kb, ke, tid);
 
     floatx4 acc[4][4];
 #pragma unroll
@@ -244,14 +314,19 @@ __global__ __launch_bounds__(NT<BF16>::THREADS) void k_gemm_nt(GemmArgs g, int n
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    const int nk = (K + BK - 1) / BK;
-    load_stage(0);
-    store_stage(0);
+    const int nk = (ke - kb + BK - 1) / BK;
+    sa.load(0);
+    sb.load(0);
+    sa.store(As);
+    sb.store(Bs);
     __syncthreads();
     for (int kt = 0; kt < nk; kt++) {
         const int buf = kt & 1;
         const bool more = kt + 1 < nk;
-        if (more) load_stage((kt + 1) * BK);
+        if (more) {
+            sa.load(kt + 1);
+            sb.load(kt + 1);
+        }
         const T *a = As + (size_t)buf * BM * LDK;
         const T *b = Bs + (size_t)buf * BN * LDK;
         if constexpr (BF16) {
@@ -287,46 +362,86 @@ __global__ __launch_bounds__(NT<BF16>::THREADS) void k_gemm_nt(GemmArgs g, int n
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
             }
         }
-        if (more) store_stage(buf ^ 1);
+        if (more) {
+            sa.store(As + (size_t)(buf ^ 1) * BM * LDK);
+            sb.store(Bs + (size_t)(buf ^ 1) * BN * LDK);
+        }
         __syncthreads();
     }
     // epilogue: lane holds rows 4 * (lane / 16) + r of column lane % 16 of each 16 x 16 block
+    const bool split = total > tiles;
+    float *out = split ? g.C_part + (size_t)z * g.M * g.N : g.C;
+    const long long ldc = split ? g.N : g.ldc;
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int n = n0 + wn * 64 + j * 16 + (lane & 15);
-        const float bias = (g.bias && n < g.N) ? g.bias[n] : 0.0f;
+        const float bias = (g.bias && !split && n < g.N) ? g.bias[n] : 0.0f;
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
             for (int rr = 0; rr < 4; rr++) {
                 const long long m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + rr;
-                if (m < g.M && n < g.N) g.C[m * g.ldc + n] = acc[i][j][rr] + bias;
+                if (m < g.M && n < g.N) out[m * ldc + n] = acc[i][j][rr] + bias;
             }
     }
 }
 
-// whether k_gemm_nt covers this call: both operands k-contiguous and packed,
-// W float, rows aligned for its loads, byte offsets within 31 bits
-static bool nt_ok(const GemmArgs &g) {
-    if (!(g.a_kc && g.b_kc && g.b_dt == 0 && g.splits == 1 && g.lda == g.K && g.ldb == g.K)) return false;
-    if (g.K % 4 != 0 || g.K == 0) return false;
+// K per split of the tiled path: a multiple of the stage depth
+static int tiled_kps(const GemmArgs &g, int bk) {
+    const int s = g.splits < 1 ? 1 : g.splits;
+    const int k = (g.K + s - 1) / s;
+    return (k + bk - 1) / bk * bk;
+}
+
+// whether the tiled path covers this call: one of the three operand patterns,
+// rows and bases aligned for its vector loads, every buffer extent within 31 bits
+static bool tiled_ok(const GemmArgs &g, bool bf16) {
+    const bool fwd = g.a_kc && g.b_kc && g.b_dt == 0;
+    const bool dx = g.a_kc && g.a_dt == 0 && !g.b_kc && g.b_dt == 0;
+    const bool dw = !g.a_kc && g.a_dt == 0 && !g.b_kc;
+    if (!(fwd || dx || dw) || g.K <= 0) return false;
     if ((reinterpret_cast<uintptr_t>(g.A) & 15) || (reinterpret_cast<uintptr_t>(g.B) & 15)) return false;
-    const size_t aes = g.a_dt == 0 ? 4 : (g.a_dt == 1 ? 1 : 2);
-    if ((size_t)g.M * g.K * aes >= ((size_t)1 << 31) || (size_t)g.N * g.K * 4 >= ((size_t)1 << 31)) return false;
-    return true;
+    if (g.lda % 4 != 0 || g.ldb % 4 != 0) return false;
+    if (!g.a_kc && g.M % 4 != 0) return false;
+    if (!g.b_kc && g.N % 4 != 0) return false;
+    if (g.splits > 1 && (g.a_kc || g.b_kc)) return false;
+    const int bk = bf16 ? Tile<true>::BK : Tile<false>::BK;
+    const size_t kps = (size_t)tiled_kps(g, bk) + bk;
+    const size_t lim = (size_t)1 << 31;
+    const size_t aes = g.a_dt == 0 ? 4 : (g.a_dt == 1 ? 1 : 2), bes = g.b_dt == 0 ? 4 : (g.b_dt == 1 ? 1 : 2);
+    const size_t a_ext = g.a_kc ? (size_t)Tile<true>::BM * g.lda * aes : kps * g.lda * aes;
+    const size_t b_ext = g.b_kc ? (size_t)Tile<true>::BN * g.ldb * bes : kps * g.ldb * bes;
+    return a_ext < lim && b_ext < lim;
+}
+
+template <int ADT, bool AKM, int BDT, bool BKM, bool BF16>
+static void tiled_go(const GemmArgs &g, int m_tiles, int n_tiles, int kps, int total, hipStream_t st) {
+    hipLaunchKernelGGL((k_gemm_tiled<ADT, AKM, BDT, BKM, BF16>), dim3((unsigned)total),
+                       dim3(Tile<BF16>::THREADS), Tile<BF16>::lds_bytes(), st, g, m_tiles, n_tiles, kps, total);
 }
 
 template <bool BF16>
-static hipError_t nt_launch(const GemmArgs &g, hipStream_t st) {
-    const int n_tiles = (g.N + NT<BF16>::BN - 1) / NT<BF16>::BN;
-    const long long m_tiles = (g.M + NT<BF16>::BM - 1) / NT<BF16>::BM;
-    const long long tiles = m_tiles * n_tiles;
-    if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-    const size_t sm = NT<BF16>::lds_bytes();
-    const dim3 grid((unsigned)tiles), block(NT<BF16>::THREADS);
-    if (g.a_dt == 0) hipLaunchKernelGGL((k_gemm_nt<0, BF16>), grid, block, sm, st, g, n_tiles, (int)tiles);
-    else if (g.a_dt == 1) hipLaunchKernelGGL((k_gemm_nt<1, BF16>), grid, block, sm, st, g, n_tiles, (int)tiles);
-    else hipLaunchKernelGGL((k_gemm_nt<2, BF16>), grid, block, sm, st, g, n_tiles, (int)tiles);
+static hipError_t tiled_launch(const GemmArgs &g, hipStream_t st, int *splits_out) {
+    using P = Tile<BF16>;
+    const long long m_tiles = (g.M + P::BM - 1) / P::BM;
+    const int n_tiles = (g.N + P::BN - 1) / P::BN;
+    const int kps = tiled_kps(g, P::BK);
+    const int splits = (g.K + kps - 1) / kps;
+    const long long total = m_tiles * n_tiles * splits;
+    if (total > 0x7fffffffLL || m_tiles * n_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int mt = (int)m_tiles, tt = (int)total;
+    *splits_out = splits;
+    if (g.a_kc && g.b_kc) {
+        if (g.a_dt == 0) tiled_go<0, false, 0, false, BF16>(g, mt, n_tiles, kps, tt, st);
+        else if (g.a_dt == 1) tiled_go<1, false, 0, false, BF16>(g, mt, n_tiles, kps, tt, st);
+        else tiled_go<2, false, 0, false, BF16>(g, mt, n_tiles, kps, tt, st);
+    } else if (g.a_kc) {
+        tiled_go<0, false, 0, true, BF16>(g, mt, n_tiles, kps, tt, st);
+    } else {
+        if (g.b_dt == 0) tiled_go<0, true, 0, true, BF16>(g, mt, n_tiles, kps, tt, st);
+        else if (g.b_dt == 1) tiled_go<0, true, 1, true, BF16>(g, mt, n_tiles, kps, tt, st);
+        else tiled_go<0, true, 2, true, BF16>(g, mt, n_tiles, kps, tt, st);
+    }
     return hipGetLastError();
 }
 
@@ -343,7 +458,15 @@ __global__ void k_split_reduce(long long MN, int N, int splits, const float *P, 
 
 hipError_t gemm_launch(const GemmArgs &g, bool bf16, hipStream_t st) {
     if (g.M == 0 || g.N == 0) return hipSuccess;
-    if (nt_ok(g)) return bf16 ? nt_launch<true>(g, st) : nt_launch<false>(g, st);
+    if (tiled_ok(g, bf16)) {
+        int splits = 1;
+        hipError_t e = bf16 ? tiled_launch<true>(g, st, &splits) : tiled_launch<false>(g, st, &splits);
+        if (e != hipSuccess || splits == 1) return e;
+        const long long MN = g.M * (long long)g.N;
+        hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st, MN, g.N,
+                           splits, g.C_part, g.C, g.bias);
+        return hipGetLastError();
+    }
     dim3 grid((g.N + GBN - 1) / GBN, (unsigned)((g.M + GBM - 1) / GBM), g.splits);
     if (grid.y > 65535) return hipErrorInvalidValue;
     if (bf16) hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, st, g);

@@ -51,6 +51,66 @@ def test_input_current_gemm(kind, prec, shape):
     assert (err <= 1e-6 * bound + 1e-7).all(), float((err / (bound + 1e-30)).max())
 
 
+# (B, T, n_in, N): ragged M and N tiles with a 2-way K split; N = 20 (the
+# three-layer output layer); a narrow input with 7 K splits of unequal use; a
+# 25-way split; n_in not a multiple of 4 (the general kernel)
+_GRAD_SHAPES = [(2, 301, 700, 260), (1, 500, 1024, 20), (3, 700, 36, 132), (4, 2000, 200, 100),
+                (2, 77, 37, 19)]
+
+
+def _gemm_bound(a, b, n):
+    """Worst-case FP32 accumulation error of sum_k a_k b_k over n terms,
+    n * 2^-24 * sum |a_k b_k| (+1 for the rounding of each product)."""
+    return (n + 1) * 2.0 ** -24 * (np.abs(a) @ np.abs(b)) + 1e-30
+
+
+@pytest.mark.parametrize("kind", ["u8", "bf16", "f32"])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape", _GRAD_SHAPES)
+def test_weight_grad_gemm(kind, prec, shape):
+    """alif_weight_grad: dW = sum_{b,t} gI^T x against the oracle, within the
+    worst-case FP32 accumulation bound; BF16 rounds gI on both sides."""
+    import torch
+    from paper_2311_11390_amd import alif
+    B, T, n_in, N = shape
+    g = rng(sum(shape) + 10 * prec)
+    x = bernoulli_spikes(g, (B, T, n_in), 0.2)
+    gI = g.standard_normal((B, T, N)).astype(np.float32)
+    log(f"[wgrad] {kind} prec={prec} B={B} T={T} n_in={n_in} N={N}")
+    out = alif.weight_grad(torch.as_tensor(gI, device="cuda"), _as_torch_spikes(x, kind), gemm_precision=prec)
+    torch.cuda.synchronize()
+    gr = _bf16_round(gI) if prec == 1 else gI.astype(np.float64)
+    ref = oracle.weight_grad(gr, x)
+    M = B * T
+    bound = _gemm_bound(gr.reshape(M, N).T, x.reshape(M, n_in).astype(np.float64), M)
+    err = np.abs(np_(out) - ref)
+    assert (err <= bound).all(), float((err / bound).max())
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape", _GRAD_SHAPES)
+def test_input_grad_gemm(prec, shape):
+    """alif_input_grad: dx = gI W against the oracle, within the worst-case FP32
+    accumulation bound; BF16 rounds gI and W on both sides."""
+    import torch
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif
+    B, T, n_in, N = shape
+    g = rng(sum(shape) + 10 * prec + 1)
+    W = normal_weights(g, N, n_in)
+    gI = g.standard_normal((B, T, N)).astype(np.float32)
+    log(f"[igrad] prec={prec} B={B} T={T} n_in={n_in} N={N}")
+    out = alif.input_grad(torch.as_tensor(gI, device="cuda"), torch.as_tensor(W, device="cuda"),
+                          L.INPUT_SPIKES_U8, gemm_precision=prec)
+    torch.cuda.synchronize()
+    rnd = _bf16_round if prec == 1 else (lambda a: np.asarray(a, np.float64))
+    gr, Wr = rnd(gI), rnd(W)
+    ref = oracle.input_grad(gr, Wr)
+    bound = _gemm_bound(gr.reshape(-1, N), Wr, N).reshape(ref.shape)
+    err = np.abs(np_(out) - ref)
+    assert (err <= bound).all(), float((err / bound).max())
+
+
 def _spike_layer_case(seed, B, T, n_in, N, dt, rate=0.05, bias=(1.0, 2.0)):
     g = rng(seed)
     x = bernoulli_spikes(g, (B, T, n_in), rate)

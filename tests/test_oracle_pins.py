@@ -205,6 +205,37 @@ def test_input_current_matches_matmul():
     np.testing.assert_allclose(out, ref, rtol=0, atol=1e-12)
 
 
+def test_projection_gradients_brute_force_and_fd():
+    """Eq. 3 gradients: weight_grad and input_grad against explicit loops over
+    (b, t, n, i), and weight_grad against central differences of the C oracle's
+    input current (the loss sum(gI * I) is linear in W, so differences are exact
+    up to rounding)."""
+    g = np.random.default_rng(8)
+    B, T, n_in, N = 2, 5, 4, 3
+    x = (g.random((B, T, n_in)) < 0.5).astype(np.uint8)
+    W = g.standard_normal((N, n_in))
+    gI = g.standard_normal((B, T, N))
+    dW = np.zeros((N, n_in))
+    dx = np.zeros((B, T, n_in))
+    for b in range(B):
+        for t in range(T):
+            for n in range(N):
+                for i in range(n_in):
+                    dW[n, i] += gI[b, t, n] * x[b, t, i]
+                    dx[b, t, i] += gI[b, t, n] * W[n, i]
+    np.testing.assert_allclose(oracle.weight_grad(gI, x), dW, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(oracle.input_grad(gI, W), dx, rtol=0, atol=1e-12)
+    eps = 1e-3
+    fd = np.zeros_like(W)
+    for n in range(N):
+        for i in range(n_in):
+            Wp, Wm = W.copy(), W.copy()
+            Wp[n, i] += eps
+            Wm[n, i] -= eps
+            fd[n, i] = ((gI * oracle.input_current(x, Wp)).sum() - (gI * oracle.input_current(x, Wm)).sum()) / (2 * eps)
+    np.testing.assert_allclose(oracle.weight_grad(gI, x), fd, rtol=0, atol=1e-9)
+
+
 def test_bth_layout_roundtrip():
     """The [B][T][N] wrapper is the row core transposed (row = (b, n))."""
     g = np.random.default_rng(7)
