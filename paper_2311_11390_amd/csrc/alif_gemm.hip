@@ -153,133 +153,189 @@ struct Tile {
 template <int DT>
 constexpr uint32_t elem_bytes() { return DT == 0 ? 4 : (DT == 1 ? 1 : 2); }
 
-// N consecutive elements at byte offset off, as float (one load of N * elem bytes)
+// A run of N consecutive elements (one buffer load of N * elem bytes). The raw
+// words stay in registers until get() converts them, so that the wait for the
+// load falls after the work placed between load() and get().
 template <int DT, int N>
-__device__ __forceinline__ void load_run(rsrc_t r, uint32_t off, float *v) {
+struct Run {
     static_assert(N == 2 || N == 4, "runs of 2 or 4");
-    if constexpr (DT == 0) {
-        if constexpr (N == 4) {
-            const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    static constexpr uint32_t BYTES = N * elem_bytes<DT>();
+    static constexpr int DW = BYTES < 4 ? 1 : (int)(BYTES / 4);
+    uint32_t w[DW];
+
+    __device__ __forceinline__ void load(rsrc_t r, uint32_t off) {
+        if constexpr (BYTES == 16) {
+            const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
 #pragma unroll
-            for (int e = 0; e < 4; e++) v[e] = __uint_as_float(w[e]);
+            for (int e = 0; e < 4; e++) w[e] = x[e];
+        } else if constexpr (BYTES == 8) {
+            const auto x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+            w[0] = x[0];
+            w[1] = x[1];
+        } else if constexpr (BYTES == 4) {
+            w[0] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
         } else {
-            const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-            v[0] = __uint_as_float(w[0]);
-            v[1] = __uint_as_float(w[1]);
+            w[0] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
         }
-    } else if constexpr (DT == 1) {
-        const uint32_t w = N == 4 ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0)
-                                  : (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+    }
+    __device__ __forceinline__ void get(float *v) const {
+        if constexpr (DT == 0) {
 #pragma unroll
-        for (int e = 0; e < N; e++) v[e] = (float)((w >> (8 * e)) & 0xffu);
-    } else {
-        if constexpr (N == 4) {
-            const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+            for (int e = 0; e < N; e++) v[e] = __uint_as_float(w[e]);
+        } else if constexpr (DT == 1) {
 #pragma unroll
-            for (int q = 0; q < 2; q++) {
-                v[2 * q] = __uint_as_float((uint32_t)w[q] << 16);
-                v[2 * q + 1] = __uint_as_float((uint32_t)w[q] & 0xffff0000u);
+            for (int e = 0; e < N; e++) v[e] = (float)((w[0] >> (8 * e)) & 0xffu);
+        } else {
+#pragma unroll
+            for (int q = 0; q < N / 2; q++) {
+                v[2 * q] = __uint_as_float(w[q] << 16);
+                v[2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u);
             }
-        } else {
-            const uint32_t w = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
-            v[0] = __uint_as_float(w << 16);
-            v[1] = __uint_as_float(w & 0xffff0000u);
         }
+    }
+};
+
+// LDS tiles hold rows of the operand, k contiguous, in 16-byte chunks (8 bf16 or
+// 4 floats). Chunk c of row r sits at chunk position c ^ ((r / 16) % 4): the
+// MFMA fragment reads (16 consecutive rows, one chunk each) stay conflict-free
+// and the transposing stores of row-contiguous operands, whose lanes write rows
+// RR apart, spread over all banks instead of a quarter of them.
+template <bool BF16>
+__device__ __forceinline__ int lds_at(int row, int chunk) {
+    constexpr int CE = BF16 ? 8 : 4;
+    return row * Tile<BF16>::LDK + (chunk ^ ((row >> 4) & 3)) * CE;
+}
+
+// 4 values (k = 4 h .. 4 h + 3 of chunk c) to LDS row `row` in the MFMA operand type
+template <bool BF16>
+__device__ __forceinline__ void lds_store4(typename Tile<BF16>::T *buf, int row, int k, const float *v) {
+    if constexpr (BF16) {
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        bf16x4 q;
+#pragma unroll
+        for (int e = 0; e < 4; e++) q[e] = (__bf16)v[e];
+        *reinterpret_cast<bf16x4 *>(buf + lds_at<true>(row, k >> 3) + (k & 4)) = q;
+    } else {
+        *reinterpret_cast<floatx4 *>(buf + lds_at<false>(row, k >> 2)) = floatx4{v[0], v[1], v[2], v[3]};
     }
 }
 
-// 8 values to LDS row p (k contiguous) in the MFMA operand type
+// 8 values (k = k0 .. k0 + 7, k0 a multiple of 8) to LDS row `row`
 template <bool BF16>
-__device__ __forceinline__ void lds_store8(typename Tile<BF16>::T *p, const float *v) {
+__device__ __forceinline__ void lds_store8(typename Tile<BF16>::T *buf, int row, int k0, const float *v) {
     if constexpr (BF16) {
         bf16x8 q;
 #pragma unroll
         for (int e = 0; e < 8; e++) q[e] = (__bf16)v[e];
-        *reinterpret_cast<bf16x8 *>(p) = q;
+        *reinterpret_cast<bf16x8 *>(buf + lds_at<true>(row, k0 >> 3)) = q;
     } else {
-        *reinterpret_cast<floatx4 *>(p) = floatx4{v[0], v[1], v[2], v[3]};
-        *reinterpret_cast<floatx4 *>(p + 4) = floatx4{v[4], v[5], v[6], v[7]};
+        *reinterpret_cast<floatx4 *>(buf + lds_at<false>(row, k0 >> 2)) = floatx4{v[0], v[1], v[2], v[3]};
+        *reinterpret_cast<floatx4 *>(buf + lds_at<false>(row, (k0 >> 2) + 1)) = floatx4{v[4], v[5], v[6], v[7]};
     }
 }
 
 // One operand's ROWS x BK stage: where this thread loads it from and where it
-// puts it in LDS.
+// puts it in LDS. Loads are coalesced along memory's contiguous direction:
+//   k-contiguous: BK / 4 consecutive threads read one row's BK elements of the
+//     stage in runs of 4, and a thread covers NI rows RPP apart;
+//   row-contiguous: RG consecutive threads read RR * RG consecutive rows of one k,
+//     and a thread covers 8 consecutive k.
 //   ptr, ld: operand base and elements between consecutive rows (k-contiguous)
 //            or consecutive k (row-contiguous);
 //   rows:    valid rows (M or N), row0 the tile's first row;
 //   kb, ke:  the K range of this workgroup's split.
-// k-contiguous: the buffer starts at the tile's first row and ends after its last
-//   valid row, so rows beyond it read 0; k >= ke is zeroed explicitly.
-// row-contiguous: the buffer starts at (kb, row0) and ends after the last valid
-//   row of k = ke - 1, so k >= ke reads 0; rows beyond the valid ones may read
-//   other data, which only reaches rows of C that are never stored.
+// Each stage gets its own buffer descriptor, starting at the stage and ending
+// where the operand's valid data ends, so the per-thread offsets stay fixed:
+// k-contiguous: rows beyond the valid ones read 0, and k >= ke is zeroed in the
+//   last stage;
+// row-contiguous: k >= ke reads 0; rows beyond the valid ones may read other
+//   data, which only reaches rows of C that are never stored.
 template <int DT, bool KM, int ROWS, bool BF16>
 struct Stage {
     using P = Tile<BF16>;
-    static constexpr int BK = P::BK, LDK = P::LDK;
+    static constexpr int BK = P::BK;
     static constexpr int EPT = ROWS * BK / P::THREADS;   // elements per thread per stage
     static constexpr int RR = EPT / 8;                    // row-contiguous: rows per thread
     static constexpr int RG = ROWS / RR;                  // row-contiguous: row groups
-    static constexpr int TPR = BK / EPT;                  // k-contiguous: threads per row
+    static constexpr int CPR = BK / 4;                    // k-contiguous: threads per row
+    static constexpr int RPP = P::THREADS / CPR;          // k-contiguous: rows per pass
+    static constexpr int NI = ROWS / RPP;                 // k-contiguous: passes
+    static constexpr int NL = KM ? 8 : NI;                // loads per thread per stage
     static constexpr uint32_t ES = elem_bytes<DT>();
-    static_assert(EPT % 8 == 0 && (!KM || P::THREADS / RG == BK / 8), "stage shape");
+    static_assert(EPT % 8 == 0 && (!KM || P::THREADS / RG == BK / 8) && (KM || NI * 4 == EPT),
+                  "stage shape");
 
-    rsrc_t r;
-    uint32_t toff;   // byte offset of this thread's first element at k = 0 of the split
-    uint32_t kstep;  // row-contiguous: bytes between consecutive k
-    int kmax0;       // k-contiguous: valid k of this thread at stage 0
-    int lrow, lk;    // LDS row and first k of this thread
-    float v[EPT];
+    const char *sbase;  // the operand at stage 0 of this split and tile
+    uint32_t ext;       // bytes of valid data from sbase
+    uint32_t sstep;     // bytes between stages
+    int kspan;          // K steps in this split
+    uint32_t voff[NL];  // byte offsets of this thread's loads within a stage
+    int kmax0;          // k-contiguous: valid k of this thread at stage 0
+    int kmax;           // k-contiguous: valid k of this thread in the loaded stage
+    bool tail;          // the loaded stage runs past ke
+    int lrow, lk;       // LDS row and first k of this thread
+    Run<DT, KM ? RR : 4> run[NL];
 
     __device__ __forceinline__ void init(const void *ptr, long long ld, long long rows, long long row0, int kb,
                                          int ke, int tid) {
         const char *base = static_cast<const char *>(ptr);
         const long long vr = rows - row0;                  // valid rows from row0 (> 0)
+        kspan = ke - kb;
         if constexpr (KM) {
             const int rg = tid % RG, kg = tid / RG;
             lrow = rg * RR;
             lk = kg * 8;
-            r = make_rsrc(base + ((size_t)kb * ld + row0) * ES,
-                          (uint32_t)(((size_t)(ke - kb - 1) * ld + vr) * ES));
-            toff = (uint32_t)(((size_t)lk * ld + lrow) * ES);
-            kstep = (uint32_t)(ld * ES);
+            sbase = base + ((size_t)kb * ld + row0) * ES;
+            ext = (uint32_t)(((size_t)(ke - kb - 1) * ld + vr) * ES);
+            sstep = (uint32_t)((size_t)BK * ld * ES);
+#pragma unroll
+            for (int j = 0; j < 8; j++) voff[j] = (uint32_t)(((size_t)(lk + j) * ld + lrow) * ES);
         } else {
-            lrow = tid / TPR;
-            lk = (tid % TPR) * EPT;
+            lrow = tid / CPR;
+            lk = (tid % CPR) * 4;
             const long long nr = vr < ROWS ? vr : ROWS;
-            r = make_rsrc(base + (size_t)row0 * ld * ES, (uint32_t)((size_t)nr * ld * ES));
-            toff = (uint32_t)(((size_t)lrow * ld + kb + lk) * ES);
-            kmax0 = ke - kb - lk;
-            kstep = 0;
+            sbase = base + ((size_t)row0 * ld + kb) * ES;
+            ext = (uint32_t)(((size_t)nr * ld - kb) * ES);
+            sstep = (uint32_t)(BK * ES);
+#pragma unroll
+            for (int i = 0; i < NI; i++) voff[i] = (uint32_t)(((size_t)(lrow + i * RPP) * ld + lk) * ES);
+            kmax0 = kspan - lk;
         }
     }
-    // load stage s (k = kb + s * BK ...)
+    // issue the loads of stage s (k = kb + s * BK ...)
     __device__ __forceinline__ void load(int s) {
-        if constexpr (KM) {
-            const uint32_t o = toff + (uint32_t)(s * BK) * kstep;
+        const uint32_t o = (uint32_t)s * sstep;
+        const rsrc_t r = make_rsrc(sbase + o, ext - o);
 #pragma unroll
-            for (int j = 0; j < 8; j++) load_run<DT, RR>(r, o + (uint32_t)j * kstep, v + j * RR);
-        } else {
-            const uint32_t o = toff + (uint32_t)(s * BK) * ES;
-#pragma unroll
-            for (int q = 0; q < EPT / 4; q++) load_run<DT, 4>(r, o + (uint32_t)(q * 4) * ES, v + q * 4);
-            const int kmax = kmax0 - s * BK;
-#pragma unroll
-            for (int e = 0; e < EPT; e++) v[e] = e < kmax ? v[e] : 0.0f;
-        }
+        for (int i = 0; i < NL; i++) run[i].load(r, voff[i]);
+        tail = (s + 1) * BK > kspan;
+        if constexpr (!KM) kmax = kmax0 - s * BK;
     }
+    // convert the loaded stage and store it to the LDS tile buf
     __device__ __forceinline__ void store(typename P::T *buf) const {
         if constexpr (KM) {
+            float v[8][RR];
+#pragma unroll
+            for (int j = 0; j < 8; j++) run[j].get(v[j]);
 #pragma unroll
             for (int rr = 0; rr < RR; rr++) {
                 float c[8];
 #pragma unroll
-                for (int j = 0; j < 8; j++) c[j] = v[j * RR + rr];
-                lds_store8<BF16>(buf + (size_t)(lrow + rr) * LDK + lk, c);
+                for (int j = 0; j < 8; j++) c[j] = v[j][rr];
+                lds_store8<BF16>(buf, lrow + rr, lk, c);
             }
         } else {
+            float v[NI][4];
 #pragma unroll
-            for (int q = 0; q < EPT / 8; q++) lds_store8<BF16>(buf + (size_t)lrow * LDK + lk + 8 * q, v + 8 * q);
+            for (int i = 0; i < NI; i++) run[i].get(v[i]);
+            if (tail) {
+#pragma unroll
+                for (int i = 0; i < NI; i++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) v[i][e] = e < kmax ? v[i][e] : 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < NI; i++) lds_store4<BF16>(buf, lrow + i * RPP, lk, v[i]);
         }
     }
 };
@@ -314,19 +370,8 @@ __global__ __launch_bounds__(Tile<BF16>::THREADS) void k_gemm_tiled(GemmArgs g, 
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    const int nk = (ke - kb + BK - 1) / BK;
-    sa.load(0);
-    sb.load(0);
-    sa.store(As);
-    sb.store(Bs);
-    __syncthreads();
-    for (int kt = 0; kt < nk; kt++) {
-        const int buf = kt & 1;
-        const bool more = kt + 1 < nk;
-        if (more) {
-            sa.load(kt + 1);
-            sb.load(kt + 1);
-        }
+    // multiply the stage in LDS buffer buf into the accumulators
+    auto mma = [&](int buf) {
         const T *a = As + (size_t)buf * BM * LDK;
         const T *b = Bs + (size_t)buf * BN * LDK;
         if constexpr (BF16) {
@@ -336,10 +381,10 @@ __global__ __launch_bounds__(Tile<BF16>::THREADS) void k_gemm_tiled(GemmArgs g, 
                 const int kc = kq + 8 * (lane >> 4);
 #pragma unroll
                 for (int i = 0; i < 4; i++)
-                    fa[i] = *reinterpret_cast<const bf16x8 *>(a + (wm * 64 + i * 16 + (lane & 15)) * LDK + kc);
+                    fa[i] = *reinterpret_cast<const bf16x8 *>(a + lds_at<true>(wm * 64 + i * 16 + (lane & 15), kc >> 3));
 #pragma unroll
                 for (int j = 0; j < 4; j++)
-                    fb[j] = *reinterpret_cast<const bf16x8 *>(b + (wn * 64 + j * 16 + (lane & 15)) * LDK + kc);
+                    fb[j] = *reinterpret_cast<const bf16x8 *>(b + lds_at<true>(wn * 64 + j * 16 + (lane & 15), kc >> 3));
 #pragma unroll
                 for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -352,9 +397,9 @@ __global__ __launch_bounds__(Tile<BF16>::THREADS) void k_gemm_tiled(GemmArgs g, 
                 const int kc = ks + (lane >> 4);
                 float fa[4], fb[4];
 #pragma unroll
-                for (int i = 0; i < 4; i++) fa[i] = a[(wm * 64 + i * 16 + (lane & 15)) * LDK + kc];
+                for (int i = 0; i < 4; i++) fa[i] = a[lds_at<false>(wm * 64 + i * 16 + (lane & 15), kc >> 2) + (kc & 3)];
 #pragma unroll
-                for (int j = 0; j < 4; j++) fb[j] = b[(wn * 64 + j * 16 + (lane & 15)) * LDK + kc];
+                for (int j = 0; j < 4; j++) fb[j] = b[lds_at<false>(wn * 64 + j * 16 + (lane & 15), kc >> 2) + (kc & 3)];
 #pragma unroll
                 for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -362,12 +407,31 @@ __global__ __launch_bounds__(Tile<BF16>::THREADS) void k_gemm_tiled(GemmArgs g, 
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
             }
         }
-        if (more) {
-            sa.store(As + (size_t)(buf ^ 1) * BM * LDK);
-            sb.store(Bs + (size_t)(buf ^ 1) * BN * LDK);
-        }
+    };
+
+    // The loads of stage kt + 1 are issued before stage kt is multiplied and
+    // stored to the other buffer after it, with no branch between (a load under a
+    // condition makes the compiler copy its registers, which waits for it).
+    const int nk = (ke - kb + BK - 1) / BK;
+    sa.load(0);
+    sb.load(0);
+    sa.store(As);
+    sb.store(Bs);
+    __syncthreads();
+    for (int kt = 0; kt + 1 < nk; kt++) {
+        const int buf = kt & 1;
+        sa.load(kt + 1);
+        sb.load(kt + 1);
+        // keep the scheduler from sinking the loads into the MFMA sequence or
+        // hoisting the conversions above it
+        __builtin_amdgcn_sched_barrier(0);
+        mma(buf);
+        __builtin_amdgcn_sched_barrier(0);
+        sa.store(As + (size_t)(buf ^ 1) * BM * LDK);
+        sb.store(Bs + (size_t)(buf ^ 1) * BN * LDK);
         __syncthreads();
     }
+    mma((nk - 1) & 1);
     // epilogue: lane holds rows 4 * (lane / 16) + r of column lane % 16 of each 16 x 16 block
     const bool split = total > tiles;
     float *out = split ? g.C_part + (size_t)z * g.M * g.N : g.C;
@@ -402,8 +466,8 @@ static bool tiled_ok(const GemmArgs &g, bool bf16) {
     if (!(fwd || dx || dw) || g.K <= 0) return false;
     if ((reinterpret_cast<uintptr_t>(g.A) & 15) || (reinterpret_cast<uintptr_t>(g.B) & 15)) return false;
     if (g.lda % 4 != 0 || g.ldb % 4 != 0) return false;
-    if (!g.a_kc && g.M % 4 != 0) return false;
-    if (!g.b_kc && g.N % 4 != 0) return false;
+    if (!g.a_kc && (g.M % 4 != 0 || g.lda < g.M)) return false;
+    if (!g.b_kc && (g.N % 4 != 0 || g.ldb < g.N)) return false;
     if (g.splits > 1 && (g.a_kc || g.b_kc)) return false;
     const int bk = bf16 ? Tile<true>::BK : Tile<false>::BK;
     const size_t kps = (size_t)tiled_kps(g, bk) + bk;
