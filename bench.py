@@ -17,8 +17,11 @@ timing (the loss is not part of the ALIF path).
 Printed JSON (last stdout line): whole-job neuron-steps/s (B * N * T / step
 time), the sequential GPU kernels on the same work, per-kernel HIP event
 durations, the HBM roofline of the dominant kernel, the FP64 oracle on host
-cores over the same workload, and a serving leg (p50 / p99 latency and
-throughput of a Poisson stream of uneven requests under continuous batching).
+cores over the same workload, a serving leg (p50 / p99 latency and
+throughput of a Poisson stream of uneven requests under continuous batching),
+and two spike-input training legs: the three-layer 700 -> 1024 -> 1024 -> 20
+network with BF16 GEMMs (each GEMM also timed alone against the MFMA peak) and
+the SHD-shaped 700 -> 512 -> readout step with FP32 GEMMs.
 """
 from __future__ import annotations
 
@@ -31,6 +34,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}   # MI355X dense, published
 
 
 def log(msg):
@@ -122,6 +126,131 @@ def time_steps(fn_fwd, fn_bwd, steps, warmup):
     fwd = [a.elapsed_time(b) for a, b, _ in ev]
     bwd = [b.elapsed_time(c) for _, b, c in ev]
     return wall, np.array(fwd), np.array(bwd)
+
+
+def _event_ms(fn, reps):
+    """Average duration of fn() over reps calls, HIP events on the current stream
+    (the library launches on it)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def three_layer_leg(steps, warmup, seed=4):
+    """Three-layer spike-input network 700 -> 1024 -> 1024 -> 20, B 128, T 2000,
+    DT 0.5 ms (T_R = 4), driven by a bias, BF16 GEMMs with FP32 accumulation.
+    One step = the three forward layers (Eq. 3 GEMM + block kernels) and the
+    backward chain of loss = sum of last-layer spikes (block backward, then
+    dW = gI^T x and dx = gI W per layer). Also times every GEMM of the step on
+    its own, against the BF16 MFMA peak."""
+    import torch
+
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif
+    from paper_2311_11390_amd.synth import three_layer
+    w = three_layer(seed=seed, driven=True)
+    dev = "cuda"
+    B, T = w.B, w.T
+    x = torch.as_tensor(w.inputs["x"], device=dev)
+    Ws = [torch.as_tensor(W, device=dev) for W in w.weights]
+    Ps = [alif.Params.from_numpy(lp, dev) for lp in w.layers]
+    prec = L.GEMM_BF16
+    st = {}
+
+    def step():
+        h, fs, ins = x, [], []
+        for W, P in zip(Ws, Ps):
+            f = alif.forward(h, P, w.dt, w.arp, W, gemm_precision=prec, spike_dtype=L.SPIKES_U8, save=True)
+            fs.append(f)
+            ins.append(h)
+            h = f["spikes"]
+        g = torch.ones(h.shape, dtype=torch.float32, device=dev)
+        for li in reversed(range(len(Ws))):
+            gr = alif.backward(fs[li], ins[li], Ps[li], Ws[li], grad_spikes=g, want_grad_input=li > 0,
+                               want_grad_W=True)
+            g = gr["grad_input"] if li > 0 else None
+        st["fs"], st["ins"] = fs, ins
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    neurons = sum(W.shape[0] for W in Ws)
+    spikes = [int(f["spikes"].sum().item()) for f in st["fs"]]
+    gemms = {}
+    for li, (W, h) in enumerate(zip(Ws, st["ins"])):
+        N, K = W.shape
+        M = B * T
+        flops = 2.0 * M * N * K
+        gI = torch.randn(B, T, N, device=dev)
+        calls = {f"L{li + 1} I = x W^T ({K} -> {N})": lambda: alif.input_current(h, W, None, gemm_precision=prec),
+                 f"L{li + 1} dW = gI^T x": lambda: alif.weight_grad(gI, h, gemm_precision=prec)}
+        if li > 0:
+            calls[f"L{li + 1} dx = gI W"] = lambda: alif.input_grad(gI, W, L.INPUT_SPIKES_U8, gemm_precision=prec)
+        for name, fn in calls.items():
+            t = _event_ms(fn, 5)
+            tf = flops / (t * 1e-3) / 1e12
+            gemms[name] = {"ms": t, "tflops": tf, "frac_of_peak": tf / MFMA_PEAK_TFLOPS["bf16"]}
+        del gI
+    del st["fs"], st["ins"]
+    torch.cuda.synchronize()
+    return {"workload": "three-layer 700 -> 1024 -> 1024 -> 20, B 128, T 2000, DT 0.5 ms, T_R 4, driven; "
+                        "loss = sum of last-layer spikes; BF16 GEMMs (FP32 accumulate), uint8 spikes",
+            "ms_per_step": ms, "value": B * T * neurons / (ms * 1e-3), "unit": "neuron-steps/s",
+            "steps": steps, "spikes_per_layer": spikes,
+            "gemm_peak_tflops": MFMA_PEAK_TFLOPS["bf16"], "gemms": gemms}
+
+
+def shd_like_leg(steps, warmup, seed=3):
+    """SHD-shaped training step: 700 Bernoulli channels -> 512 ALIF -> 20 leaky
+    readout, B 32, T 1000, DT 1 ms, driven by a bias, FP32 GEMMs; forward,
+    cross-entropy and backward through torch.autograd with the library's ops."""
+    import torch
+
+    from paper_2311_11390_amd import alif
+    from paper_2311_11390_amd.synth import shd_like_training
+    w = shd_like_training(seed=seed, driven=True)
+    dev = "cuda"
+    lp = w.layers[0]
+    xt = torch.as_tensor(w.inputs["x"], device=dev)
+    Wt = torch.as_tensor(w.weights[0], device=dev).requires_grad_()
+    P = {k: torch.as_tensor(getattr(lp, k), device=dev).requires_grad_()
+         for k in ("tau_mem", "tau_adapt", "d", "theta0", "bias")}
+    Wrt = torch.as_tensor(w.extra["readout_W"], device=dev).requires_grad_()
+    trt = torch.as_tensor(w.extra["readout_tau"], device=dev).requires_grad_()
+    labels = torch.as_tensor(w.inputs["labels"], device=dev)
+    cfg = {"dt": w.dt, "arp": w.arp}
+
+    def step():
+        S, _, _ = alif.BlockALIF.apply(xt, Wt, P["tau_mem"], P["tau_adapt"], P["d"], P["theta0"], P["bias"], cfg)
+        o = alif.Readout.apply(S, Wrt, trt, w.dt)
+        loss = torch.nn.functional.cross_entropy(o, labels)
+        loss.backward()
+        return S
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    return {"workload": "SHD-shaped 700 -> 512 ALIF -> 20 readout, B 32, T 1000, DT 1 ms, T_R 2, driven; "
+                        "cross-entropy; FP32 GEMMs; torch.autograd over the library's ops",
+            "ms_per_step": ms, "value": w.B * w.T * 512 / (ms * 1e-3), "unit": "neuron-steps/s",
+            "steps": steps, "spikes": int(S.sum().item())}
 
 
 def cpu_baseline(w, cpu_seconds, threads):
@@ -240,6 +369,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-sequential", action="store_true")
+    ap.add_argument("--no-layers", action="store_true",
+                    help="skip the three-layer and SHD-shaped training legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time (summed over threads) the oracle baseline runs for, in whole passes")
@@ -348,6 +479,16 @@ def main():
         seq["per_step_launch_fwd_ms"] = (time.perf_counter() - t0) * 1e3
         del car, sp
 
+    layers = None
+    if not args.no_layers:
+        log("[bench] three-layer BF16 training step")
+        layers = {"three_layer": three_layer_leg(max(3, args.steps // 4), 2)}
+        log(f"[bench] three-layer: {layers['three_layer']['ms_per_step']:.3f} ms/step")
+        log("[bench] SHD-shaped training step")
+        layers["shd_like"] = shd_like_leg(max(5, args.steps // 2), 2)
+        log(f"[bench] SHD-shaped: {layers['shd_like']['ms_per_step']:.3f} ms/step")
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = len(os.sched_getaffinity(0))
@@ -396,6 +537,7 @@ def main():
         "sequential": seq,
         "speedup_vs_sequential": (value / seq["value"]) if seq else None,
         "cpu_baseline": cpu,
+        "layers": layers,
         "serving": serve,
     }
     print(json.dumps(res), flush=True)
