@@ -265,16 +265,22 @@ struct Stage {
     static_assert(EPT % 8 == 0 && (!KM || P::THREADS / RG == BK / 8) && (KM || NI * 4 == EPT),
                   "stage shape");
 
+    static constexpr int REG_WORDS = NL * Run<DT, KM ? RR : 4>::DW;  // registers of one stage in flight
+
+    // one stage in flight: its raw loaded words and where it ends
+    struct Regs {
+        Run<DT, KM ? RR : 4> run[NL];
+        int kmax;   // k-contiguous: valid k of this thread in the stage
+        bool tail;  // the stage runs past ke
+    };
+
     const char *sbase;  // the operand at stage 0 of this split and tile
     uint32_t ext;       // bytes of valid data from sbase
     uint32_t sstep;     // bytes between stages
     int kspan;          // K steps in this split
     uint32_t voff[NL];  // byte offsets of this thread's loads within a stage
     int kmax0;          // k-contiguous: valid k of this thread at stage 0
-    int kmax;           // k-contiguous: valid k of this thread in the loaded stage
-    bool tail;          // the loaded stage runs past ke
     int lrow, lk;       // LDS row and first k of this thread
-    Run<DT, KM ? RR : 4> run[NL];
 
     __device__ __forceinline__ void init(const void *ptr, long long ld, long long rows, long long row0, int kb,
                                          int ke, int tid) {
@@ -302,21 +308,28 @@ struct Stage {
             kmax0 = kspan - lk;
         }
     }
-    // issue the loads of stage s (k = kb + s * BK ...)
-    __device__ __forceinline__ void load(int s) {
-        const uint32_t o = (uint32_t)s * sstep;
-        const rsrc_t r = make_rsrc(sbase + o, ext - o);
+    // issue the loads of stage s (k = kb + s * BK ...) into g; a stage past the
+    // split gets an empty descriptor and reads zeros
+    __device__ __forceinline__ void load(int s, Regs &g) const {
+        // the descriptor is uniform; readfirstlane keeps the compiler from
+        // treating it as divergent (which wraps every load in a waterfall loop)
+        const uint32_t o = (uint32_t)__builtin_amdgcn_readfirstlane(s) * sstep;
+        const uint64_t bp = reinterpret_cast<uint64_t>(sbase + o);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)bp);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(bp >> 32));
+        const uint32_t nrec = __builtin_amdgcn_readfirstlane(o < ext ? ext - o : 0u);
+        const rsrc_t r = make_rsrc(reinterpret_cast<const void *>(((uint64_t)hi << 32) | lo), nrec);
 #pragma unroll
-        for (int i = 0; i < NL; i++) run[i].load(r, voff[i]);
-        tail = (s + 1) * BK > kspan;
-        if constexpr (!KM) kmax = kmax0 - s * BK;
+        for (int i = 0; i < NL; i++) g.run[i].load(r, voff[i]);
+        g.tail = (s + 1) * BK > kspan;
+        if constexpr (!KM) g.kmax = kmax0 - s * BK;
     }
-    // convert the loaded stage and store it to the LDS tile buf
-    __device__ __forceinline__ void store(typename P::T *buf) const {
+    // convert a loaded stage and store it to the LDS tile buf
+    __device__ __forceinline__ void store(const Regs &g, typename P::T *buf) const {
         if constexpr (KM) {
             float v[8][RR];
 #pragma unroll
-            for (int j = 0; j < 8; j++) run[j].get(v[j]);
+            for (int j = 0; j < 8; j++) g.run[j].get(v[j]);
 #pragma unroll
             for (int rr = 0; rr < RR; rr++) {
                 float c[8];
@@ -327,12 +340,12 @@ struct Stage {
         } else {
             float v[NI][4];
 #pragma unroll
-            for (int i = 0; i < NI; i++) run[i].get(v[i]);
-            if (tail) {
+            for (int i = 0; i < NI; i++) g.run[i].get(v[i]);
+            if (g.tail) {
 #pragma unroll
                 for (int i = 0; i < NI; i++)
 #pragma unroll
-                    for (int e = 0; e < 4; e++) v[i][e] = e < kmax ? v[i][e] : 0.0f;
+                    for (int e = 0; e < 4; e++) v[i][e] = e < g.kmax ? v[i][e] : 0.0f;
             }
 #pragma unroll
             for (int i = 0; i < NI; i++) lds_store4<BF16>(buf, lrow + i * RPP, lk, v[i]);
@@ -409,29 +422,74 @@ __global__ __launch_bounds__(Tile<BF16>::THREADS) void k_gemm_tiled(GemmArgs g, 
         }
     };
 
-    // The loads of stage kt + 1 are issued before stage kt is multiplied and
-    // stored to the other buffer after it, with no branch between (a load under a
-    // condition makes the compiler copy its registers, which waits for it).
+    // Loads are issued unconditionally (past the split they read zeros): a load
+    // under a condition makes the compiler copy its registers, which waits for
+    // it. sched_barrier keeps the compiler from moving instructions across it.
+    using SA = Stage<ADT, AKM, BM, BF16>;
+    using SB = Stage<BDT, BKM, BN, BF16>;
+    T *const L0a = As, *const L1a = As + (size_t)BM * LDK;
+    T *const L0b = Bs, *const L1b = Bs + (size_t)BN * LDK;
     const int nk = (ke - kb + BK - 1) / BK;
-    sa.load(0);
-    sb.load(0);
-    sa.store(As);
-    sb.store(Bs);
-    __syncthreads();
-    for (int kt = 0; kt + 1 < nk; kt++) {
-        const int buf = kt & 1;
-        sa.load(kt + 1);
-        sb.load(kt + 1);
-        // keep the scheduler from sinking the loads into the MFMA sequence or
-        // hoisting the conversions above it
-        __builtin_amdgcn_sched_barrier(0);
-        mma(buf);
-        __builtin_amdgcn_sched_barrier(0);
-        sa.store(As + (size_t)(buf ^ 1) * BM * LDK);
-        sb.store(Bs + (size_t)(buf ^ 1) * BN * LDK);
+    if constexpr (BF16 && SA::REG_WORDS + SB::REG_WORDS <= 32) {
+        // Two stages in flight. While stage kt is multiplied from one LDS
+        // buffer, stage kt + 1, loaded a whole stage earlier, is converted and
+        // stored to the other, interleaved with the MFMAs; then the loads of
+        // stage kt + 3 go out. Stages alternate between two register sets; the
+        // loop body covers an even and an odd stage so that both are addressed
+        // statically. Stages past the split are stored to the buffer nobody reads.
+        typename SA::Regs ra0, ra1;
+        typename SB::Regs rb0, rb1;
+        sa.load(0, ra0);
+        sb.load(0, rb0);
+        sa.load(1, ra1);
+        sb.load(1, rb1);
+        sa.store(ra0, L0a);
+        sb.store(rb0, L0b);
         __syncthreads();
+        sa.load(2, ra0);
+        sb.load(2, rb0);
+        int kt = 0;
+        for (; kt + 2 <= nk; kt += 2) {
+            __builtin_amdgcn_sched_barrier(0);
+            mma(0);
+            sa.store(ra1, L1a);
+            sb.store(rb1, L1b);
+            __syncthreads();
+            sa.load(kt + 3, ra1);
+            sb.load(kt + 3, rb1);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(1);
+            sa.store(ra0, L0a);
+            sb.store(rb0, L0b);
+            __syncthreads();
+            sa.load(kt + 4, ra0);
+            sb.load(kt + 4, rb0);
+        }
+        if (kt < nk) mma(0);
+    } else {
+        // One stage in flight (wide operands would not fit two in registers):
+        // the loads of stage kt + 1 are issued before stage kt is multiplied and
+        // converted and stored after it.
+        typename SA::Regs ra;
+        typename SB::Regs rb;
+        sa.load(0, ra);
+        sb.load(0, rb);
+        sa.store(ra, L0a);
+        sb.store(rb, L0b);
+        __syncthreads();
+        for (int kt = 0; kt + 1 < nk; kt++) {
+            const int buf = kt & 1;
+            sa.load(kt + 1, ra);
+            sb.load(kt + 1, rb);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(buf);
+            __builtin_amdgcn_sched_barrier(0);
+            sa.store(ra, buf ? L0a : L1a);
+            sb.store(rb, buf ? L0b : L1b);
+            __syncthreads();
+        }
+        mma((nk - 1) & 1);
     }
-    mma((nk - 1) & 1);
     // epilogue: lane holds rows 4 * (lane / 16) + r of column lane % 16 of each 16 x 16 block
     const bool split = total > tiles;
     float *out = split ? g.C_part + (size_t)z * g.M * g.N : g.C;
