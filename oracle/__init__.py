@@ -55,10 +55,12 @@ def _load():
                                         ctypes.c_double, ctypes.c_int, _i8p,
                                         _u8p, _f64p, _f64p, _f64p, _u8p]
     lib.oracle_alif_backward.argtypes = [_i64, _i64, _f64p, _f64p, _f64p, _f64p, _f64p,
-                                         ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                          _u8p, _f64p, _f64p, _f64p, _u8p,
                                          _f64p, _f64p, _f64p,
                                          _f64p, _f64p, _f64p, _f64p, _f64p]
+    lib.oracle_surrogate.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    lib.oracle_surrogate.restype = ctypes.c_double
     lib.oracle_readout_forward.argtypes = [_i64, _i64, _f64p, _f64p, ctypes.c_double,
                                            _f64p, _f64p]
     lib.oracle_readout_backward.argtypes = [_i64, _i64, _f64p, _f64p, ctypes.c_double,
@@ -142,8 +144,22 @@ def forward_rows(I, tau_m, tau_a, d, theta0, dt, TR, force=None):
     return {"S": S, "V": V, "TH": TH, "A": A, "MASK": M, "I": I}
 
 
+# surrogate kinds (supplementary "Surrogate gradient"); the library's enum uses the same numbers
+SURROGATES = {"fast_sigmoid": 0, "boxcar": 1, "multi_gaussian": 2}
+
+
+def _sg_kind(surrogate) -> int:
+    return SURROGATES[surrogate] if isinstance(surrogate, str) else int(surrogate)
+
+
+def surrogate(kind, u: float, slope: float = 10.0) -> float:
+    """Surrogate derivative dS/du at u = V - th: fast sigmoid (slope |u| + 1)^-2,
+    boxcar 0.5 on |u| <= 0.5, or the multi-Gaussian mixture as printed."""
+    return float(_load().oracle_surrogate(_sg_kind(kind), float(u), float(slope)))
+
+
 def backward_rows(fw, tau_m, tau_a, d, theta0, dt, slope=10.0, gS=None, gV=None, gTH=None,
-                  want_gI=True):
+                  want_gI=True, surrogate="fast_sigmoid"):
     """Sequential surrogate-gradient adjoint of ``forward_rows`` (detached policy).
 
     Returns dict with gI [R][T] (or None) and g_tau_m, g_tau_a, g_d, g_theta0 [R].
@@ -157,7 +173,7 @@ def backward_rows(fw, tau_m, tau_a, d, theta0, dt, slope=10.0, gS=None, gV=None,
     gI = np.empty((R, T)) if want_gI else None
     outs = [np.empty(R) for _ in range(4)]
     _load().oracle_alif_backward(R, T, _p(I, ctypes.c_double), *[_p(q, ctypes.c_double) for q in pr],
-                                 float(dt), float(slope),
+                                 float(dt), _sg_kind(surrogate), float(slope),
                                  _p(fw["S"], ctypes.c_uint8), _p(fw["V"], ctypes.c_double),
                                  _p(fw["TH"], ctypes.c_double), _p(fw["A"], ctypes.c_double),
                                  _p(fw["MASK"], ctypes.c_uint8),
@@ -208,7 +224,8 @@ def alif_forward(I, tau_m, tau_a, d, theta0, dt, arp, force=None):
     return out
 
 
-def alif_backward(fwd, dt, slope=10.0, gS=None, gV=None, gTH=None, want_gI=True):
+def alif_backward(fwd, dt, slope=10.0, gS=None, gV=None, gTH=None, want_gI=True,
+                  surrogate="fast_sigmoid"):
     """Adjoint for ``alif_forward`` output; gradients summed over the batch.
 
     gS, gV, gTH are [B][T][N] (or None). Returns gI [B][T][N] (or None) and
@@ -217,7 +234,7 @@ def alif_backward(fwd, dt, slope=10.0, gS=None, gV=None, gTH=None, want_gI=True)
     B, T, N = fwd["S"].shape
     conv = lambda g: None if g is None else _to_rows(np.asarray(g, np.float64))
     bw = backward_rows(fwd["rows"], *fwd["params"], dt, slope, conv(gS), conv(gV), conv(gTH),
-                       want_gI=want_gI)
+                       want_gI=want_gI, surrogate=surrogate)
     out = {"gI": None if bw["gI"] is None else _from_rows(bw["gI"], B, N)}
     for k in ("g_tau_m", "g_tau_a", "g_d", "g_theta0"):
         out[k] = bw[k].reshape(B, N).sum(axis=0)

@@ -21,8 +21,8 @@
  *
  * The adjoint (oracle_alif_backward) is the sequential surrogate gradient of the
  * same recurrence under the paper's "detached" policy (supplementary "Detaching
- * gradients"): the spike enters the loss and the next layer through the surrogate
- * (fast sigmoid, supplementary "Surrogate gradient"), while its uses in the reset
+ * gradients"): the spike enters the loss and the next layer through a surrogate
+ * derivative (supplementary "Surrogate gradient"), while its uses in the reset
  * factor (1 - S[t-1]), in the adaptation increment and in the refractory mask are
  * constants. The leak path beta*V and the threshold path stay attached.
  *
@@ -138,16 +138,35 @@ void oracle_alif_forward(int64_t R, int64_t T, const double *I,
     }
 }
 
-/* Fast-sigmoid surrogate derivative (k|u| + 1)^-2, u = V - th. */
-static double fast_sigmoid_grad(double u, double k)
+/* Normal density N(u | m, s^2). */
+static double normal_pdf(double u, double m, double s)
 {
-    double q = k * fabs(u) + 1.0;
+    const double z = (u - m) / s;
+    const double pi = 3.14159265358979323846;
+    return exp(-0.5 * z * z) / (s * sqrt(2.0 * pi));
+}
+
+/*
+ * The three surrogate derivatives dS/du the supplementary ("Surrogate gradient")
+ * compares, with u = V - th for all of them:
+ *   kind 0, fast sigmoid:   (k |u| + 1)^-2
+ *   kind 1, boxcar:         0.5 where |u| <= 0.5, else 0
+ *   kind 2, multi-Gaussian: 1.15 N(u | 0, 0.5^2) - 0.15 N(u | 3, 3^2) - 0.15 N(u | -3, 3^2)
+ * The multi-Gaussian constants are the ones printed there.
+ */
+double oracle_surrogate(int kind, double u, double k)
+{
+    if (kind == 1) return fabs(u) <= 0.5 ? 0.5 : 0.0;
+    if (kind == 2)
+        return 1.15 * normal_pdf(u, 0.0, 0.5) - 0.15 * normal_pdf(u, 3.0, 3.0) -
+               0.15 * normal_pdf(u, -3.0, 3.0);
+    const double q = k * fabs(u) + 1.0;
     return 1.0 / (q * q);
 }
 
 /*
  * Adjoint of oracle_alif_forward under the detached policy, reverse over t with
- * lambda_V[T+1] = lambda_a[T+1] = 0:
+ * lambda_V[T+1] = lambda_a[T+1] = 0 (sigma' is oracle_surrogate of `surrogate`):
  *   s        = sigma'(V[t] - th[t])
  *   lamV[t]  = gV[t] + gS[t] s + beta (1 - S[t]) lamV[t+1]
  *   lamTh[t] = gTh[t] - gS[t] s
@@ -162,7 +181,7 @@ static double fast_sigmoid_grad(double u, double k)
 void oracle_alif_backward(int64_t R, int64_t T, const double *I,
                           const double *tau_m, const double *tau_a,
                           const double *d, const double *theta0,
-                          double dt, double slope,
+                          double dt, int surrogate, double slope,
                           const uint8_t *S, const double *V, const double *TH,
                           const double *A, const uint8_t *MASK,
                           const double *gS, const double *gV, const double *gTH,
@@ -178,7 +197,7 @@ void oracle_alif_backward(int64_t R, int64_t T, const double *I,
         double lamV_next = 0.0, lamA_next = 0.0;
         double gbeta = 0.0, gp = 0.0, gd = 0.0, gth0 = 0.0;
         for (int64_t t = T - 1; t >= 0; t--) {
-            double sg = fast_sigmoid_grad(V[o + t] - TH[o + t], slope);
+            double sg = oracle_surrogate(surrogate, V[o + t] - TH[o + t], slope);
             double gs = gS ? gS[o + t] : 0.0;
             double lamV = (gV ? gV[o + t] : 0.0) + gs * sg
                         + beta * (1.0 - (double)S[o + t]) * lamV_next;

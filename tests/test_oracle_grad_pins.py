@@ -3,10 +3,12 @@
 * Central finite differences of smooth losses sum(wV V) + sum(wTh th), which do
   not go through the spike function, at points where no spike flips.
 * float64 torch autograd through a plain transcription of Eqs. 1-5 in which the
-  spike has the fast-sigmoid surrogate derivative and its uses in reset,
+  spike has one of the three surrogate derivatives and its uses in reset,
   adaptation and refractory gate are detached (the supplementary "Detaching
   gradients" policy). Autograd derives the adjoint mechanically, so a dropped
   term or a wrong index in the hand-written adjoint shows up as a mismatch.
+* The surrogate derivatives themselves against closed-form integrals over u,
+  evenness and their special values.
 """
 import math
 
@@ -77,22 +79,34 @@ def test_adjoint_matches_finite_differences(seed):
     assert checked >= 14
 
 
+def _torch_surrogate(u, kind, k):
+    """The three surrogate derivatives in torch (an implementation separate from
+    the oracle's C code): fast sigmoid, boxcar, multi-Gaussian."""
+    if kind == "boxcar":
+        return 0.5 * (u.abs() <= 0.5).to(u.dtype)
+    if kind == "multi_gaussian":
+        nd = lambda m, sd: torch.exp(-0.5 * ((u - m) / sd) ** 2) / (sd * math.sqrt(2 * math.pi))
+        return 1.15 * nd(0.0, 0.5) - 0.15 * nd(3.0, 3.0) - 0.15 * nd(-3.0, 3.0)
+    return 1.0 / (k * u.abs() + 1.0) ** 2
+
+
 class _ForcedSpike(torch.autograd.Function):
-    """Spike with given forward decisions and fast-sigmoid surrogate derivative."""
+    """Spike with given forward decisions and a surrogate derivative."""
 
     @staticmethod
-    def forward(ctx, u, s, k):
+    def forward(ctx, u, s, k, kind="fast_sigmoid"):
         ctx.save_for_backward(u)
         ctx.k = k
+        ctx.kind = kind
         return s.clone()
 
     @staticmethod
     def backward(ctx, g):
         (u,) = ctx.saved_tensors
-        return g / (ctx.k * u.abs() + 1.0) ** 2, None, None
+        return g * _torch_surrogate(u, ctx.kind, ctx.k), None, None, None
 
 
-def _torch_standard(I, prm, dt, TR, S_forced, slope):
+def _torch_standard(I, prm, dt, TR, S_forced, slope, kind="fast_sigmoid"):
     """Eqs. 1-5 in torch float64 with detached spike uses (reset, adaptation, gate)."""
     R, T = I.shape
     I = torch.tensor(I, dtype=torch.float64, requires_grad=True)
@@ -110,7 +124,7 @@ def _torch_standard(I, prm, dt, TR, S_forced, slope):
         v = (beta * v + (1 - beta) * I[:, t] * gate) * (1 - s_prev.detach())
         a = p * a + s_prev.detach()
         th = P["theta0"] + P["d"] * a
-        s = _ForcedSpike.apply(v - th, Sf[:, t], slope)
+        s = _ForcedSpike.apply(v - th, Sf[:, t], slope, kind)
         last = np.where(S_forced[:, t] > 0, t, last)
         Vs.append(v)
         THs.append(th)
@@ -119,24 +133,53 @@ def _torch_standard(I, prm, dt, TR, S_forced, slope):
     return I, P, torch.stack(Vs, 1), torch.stack(THs, 1), torch.stack(Ss, 1)
 
 
+@pytest.mark.parametrize("kind", ["fast_sigmoid", "boxcar", "multi_gaussian"])
 @pytest.mark.parametrize("seed,TR", [(3, 2), (4, 4), (5, 9)])
-def test_adjoint_matches_torch_autograd(seed, TR):
+def test_adjoint_matches_torch_autograd(seed, TR, kind):
     g, I, prm, dt, _ = _setup(seed, R=4, T=150, TR=TR)
     R, T = I.shape
     f = _fw(I, prm, dt, TR)
     assert f["S"].sum() > 5
     wS, wV, wT = (g.standard_normal((R, T)) for _ in range(3))
     slope = 10.0
-    It, P, V, TH, S = _torch_standard(I, prm, dt, TR, f["S"], slope)
+    It, P, V, TH, S = _torch_standard(I, prm, dt, TR, f["S"], slope, kind)
     np.testing.assert_allclose(V.detach().numpy(), f["V"], rtol=0, atol=1e-12)
     np.testing.assert_allclose(TH.detach().numpy(), f["TH"], rtol=0, atol=1e-12)
     loss = (torch.tensor(wS) * S).sum() + (torch.tensor(wV) * V).sum() + (torch.tensor(wT) * TH).sum()
     loss.backward()
     bw = oracle.backward_rows(f, prm["tau_m"], prm["tau_a"], prm["d"], prm["theta0"], dt,
-                              slope=slope, gS=wS, gV=wV, gTH=wT)
+                              slope=slope, gS=wS, gV=wV, gTH=wT, surrogate=kind)
+    if kind == "boxcar":   # some steps must sit inside the window for the pin to bite
+        assert (np.abs(f["V"] - f["TH"]) <= 0.5).sum() > 20
     np.testing.assert_allclose(bw["gI"], It.grad.numpy(), rtol=1e-10, atol=1e-12)
     for name, key in [("tau_m", "g_tau_m"), ("tau_a", "g_tau_a"), ("d", "g_d"), ("theta0", "g_theta0")]:
         np.testing.assert_allclose(bw[key], P[name].grad.numpy(), rtol=1e-10, atol=1e-12)
+
+
+def test_surrogate_integrals_and_special_values():
+    """The surrogate derivatives against closed forms: the integral over u of the
+    fast sigmoid on [-X, X] is (2/k)(1 - 1/(kX + 1)), of the boxcar 0.5, and of
+    the multi-Gaussian 1.15 - 0.15 - 0.15 = 0.85 (unit-mass Gaussians, tails beyond
+    |u| = 60 negligible); all are even in u; the boxcar window is closed."""
+    X, n = 60.0, 240001
+    u = np.linspace(-X, X, n)
+    h = u[1] - u[0]
+    k = 10.0
+    for kind, ref in [("fast_sigmoid", 2.0 / k * (1.0 - 1.0 / (k * X + 1.0))), ("boxcar", 0.5),
+                      ("multi_gaussian", 0.85)]:
+        v = np.array([oracle.surrogate(kind, x, k) for x in u])
+        integral = h * (v.sum() - 0.5 * (v[0] + v[-1]))
+        tol = 2 * h * 0.5 if kind == "boxcar" else 1e-6   # the boxcar jumps at the grid edges
+        assert abs(integral - ref) <= tol, (kind, integral, ref)
+        w = np.array([oracle.surrogate(kind, -x, k) for x in u])
+        np.testing.assert_allclose(v, w, rtol=1e-13, atol=1e-16)   # even (up to summation order)
+    assert oracle.surrogate("fast_sigmoid", 0.0, k) == 1.0
+    assert oracle.surrogate("fast_sigmoid", 0.1, k) == 0.25
+    assert oracle.surrogate("boxcar", 0.5) == 0.5 and oracle.surrogate("boxcar", -0.5) == 0.5
+    assert oracle.surrogate("boxcar", 0.5 + 1e-12) == 0.0 and oracle.surrogate("boxcar", 0.0) == 0.5
+    # the multi-Gaussian peaks at 0 and dips below zero in its tails
+    assert oracle.surrogate("multi_gaussian", 0.0) > oracle.surrogate("multi_gaussian", 0.3) > 0
+    assert oracle.surrogate("multi_gaussian", 2.0) < 0
 
 
 def test_readout_adjoint_finite_differences():
