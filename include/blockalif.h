@@ -94,7 +94,13 @@ enum alif_algo {
     ALIF_ALGO_SEQUENTIAL      = 1, /* baseline: one thread per (b, neuron), fused loop over t */
     ALIF_ALGO_SEQUENTIAL_STEP = 2  /* baseline: one kernel launch per time step */
 };
-enum alif_surrogate { ALIF_SG_FAST_SIGMOID = 0 }; /* dS/du = (k|u| + 1)^-2, u = V - th */
+/* Surrogate derivative dS/du of the backward, u = V - th (supplementary
+ * "Surrogate gradient"; the multi-Gaussian constants as printed there). */
+enum alif_surrogate {
+    ALIF_SG_FAST_SIGMOID   = 0, /* (k|u| + 1)^-2, k = sg_slope */
+    ALIF_SG_BOXCAR         = 1, /* 0.5 where |u| <= 0.5, else 0 */
+    ALIF_SG_MULTI_GAUSSIAN = 2  /* 1.15 N(u|0, 0.5^2) - 0.15 N(u|3, 3^2) - 0.15 N(u|-3, 3^2) */
+};
 
 /* ---- problem descriptor ------------------------------------------------------ */
 typedef struct alif_desc {
@@ -109,7 +115,7 @@ typedef struct alif_desc {
     int32_t spike_dtype;    /* enum alif_spike_dtype of the spike output */
     int32_t algo;           /* enum alif_algo */
     int32_t surrogate;      /* enum alif_surrogate */
-    float   sg_slope;       /* surrogate slope k (supplementary uses 10) */
+    float   sg_slope;       /* fast-sigmoid slope k (supplementary uses 10); >= 0 */
 } alif_desc;
 
 /* Per-neuron parameters, device float [N] each (Eqs. 2-5). bias may be NULL (= 0). */
@@ -221,7 +227,7 @@ int alif_forward(const alif_desc *desc, const alif_params *prm,
 
 /*
  * Surrogate-gradient backward pass of alif_forward under the paper's "detached"
- * policy (supplementary "Detaching gradients"; fast-sigmoid surrogate,
+ * policy (supplementary "Detaching gradients"; surrogate desc->surrogate,
  * supplementary "Surrogate gradient"): spikes pass gradient to the loss and to
  * downstream layers; their uses in reset, adaptation and refractory gate are
  * constants. Each block is recomputed from the input and its saved carry, then

@@ -28,7 +28,7 @@ INPUT_CURRENT_F32, INPUT_SPIKES_U8, INPUT_SPIKES_BF16, INPUT_SPIKES_F32 = 0, 1, 
 GEMM_FP32, GEMM_BF16 = 0, 1
 SPIKES_U8, SPIKES_BF16, SPIKES_F32 = 0, 1, 2
 ALGO_BLOCKS, ALGO_SEQUENTIAL, ALGO_SEQUENTIAL_STEP = 0, 1, 2
-SG_FAST_SIGMOID = 0
+SG_FAST_SIGMOID, SG_BOXCAR, SG_MULTI_GAUSSIAN = 0, 1, 2
 REQ_HOST_CURRENT, REQ_OU = 0, 1
 
 

@@ -57,9 +57,10 @@ def refractory_steps(dt_ms: float, arp_ms: float) -> int:
 
 
 def make_desc(B, T, N, dt, arp, n_in=0, input_kind=L.INPUT_CURRENT_F32, gemm_precision=L.GEMM_FP32,
-              spike_dtype=L.SPIKES_U8, algo=L.ALGO_BLOCKS, slope=10.0) -> L.AlifDesc:
+              spike_dtype=L.SPIKES_U8, algo=L.ALGO_BLOCKS, slope=10.0,
+              surrogate=L.SG_FAST_SIGMOID) -> L.AlifDesc:
     return L.AlifDesc(int(B), int(n_in), int(N), int(T), float(dt), float(arp), int(input_kind),
-                      int(gemm_precision), int(spike_dtype), int(algo), L.SG_FAST_SIGMOID, float(slope))
+                      int(gemm_precision), int(spike_dtype), int(algo), int(surrogate), float(slope))
 
 
 def carry_bytes(desc) -> int:
@@ -87,13 +88,15 @@ def _cstate(s):
 def forward(inp: torch.Tensor, params: Params, dt: float, arp: float, W: torch.Tensor | None = None, *,
             gemm_precision=L.GEMM_FP32, spike_dtype=L.SPIKES_U8, algo=L.ALGO_BLOCKS,
             want_v=False, want_theta=False, save=False, init=None, want_final=False,
-            slope=10.0, out=None) -> dict:
+            slope=10.0, surrogate=L.SG_FAST_SIGMOID, out=None) -> dict:
     """One ALIF layer over T steps (alif_forward).
 
     ``inp`` is the current float32 [B][T][N] when ``W`` is None, else presynaptic
     spikes [B][T][n_in] (uint8, bfloat16 or float32 0/1). Returns a dict with
     ``spikes`` (dtype from ``spike_dtype``), optional ``v``/``theta``, and what the
-    backward needs (``current``, ``carries``, ``desc``) when ``save``."""
+    backward needs (``current``, ``carries``, ``desc``) when ``save``. ``surrogate``
+    (SG_FAST_SIGMOID with ``slope``, SG_BOXCAR, SG_MULTI_GAUSSIAN) selects the
+    surrogate derivative the backward of this forward uses."""
     assert inp.is_cuda and inp.is_contiguous()
     B, T = inp.shape[0], inp.shape[1]
     dev = inp.device
@@ -105,7 +108,7 @@ def forward(inp: torch.Tensor, params: Params, dt: float, arp: float, W: torch.T
         N, n_in = W.shape
         assert inp.shape[2] == n_in
         kind = _INPUT_KIND[inp.dtype]
-    desc = make_desc(B, T, N, dt, arp, n_in, kind, gemm_precision, spike_dtype, algo, slope)
+    desc = make_desc(B, T, N, dt, arp, n_in, kind, gemm_precision, spike_dtype, algo, slope, surrogate)
     o = out or {}
     spikes = o.get("spikes")
     if spikes is None:
@@ -271,7 +274,8 @@ class BlockALIF(torch.autograd.Function):
         traces = cfg.get("traces", False)
         f = forward(inp.contiguous(), prm, cfg["dt"], cfg["arp"], W, gemm_precision=cfg.get("gemm", L.GEMM_FP32),
                     spike_dtype=cfg.get("spike_dtype", L.SPIKES_F32), algo=cfg.get("algo", L.ALGO_BLOCKS),
-                    want_v=traces, want_theta=traces, save=True, slope=cfg.get("slope", 10.0))
+                    want_v=traces, want_theta=traces, save=True, slope=cfg.get("slope", 10.0),
+                    surrogate=cfg.get("surrogate", L.SG_FAST_SIGMOID))
         ctx.cfg = cfg
         ctx.fwd = {k: f[k] for k in ("current", "carries", "desc")}
         ctx.prm = prm

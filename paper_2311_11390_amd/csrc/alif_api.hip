@@ -86,7 +86,9 @@ int check_desc(const alif_desc *d, Prob *p) {
         return fail(ALIF_EINVAL, "unknown spike_dtype %d", d->spike_dtype);
     if (d->algo < ALIF_ALGO_BLOCKS || d->algo > ALIF_ALGO_SEQUENTIAL_STEP)
         return fail(ALIF_EINVAL, "unknown algo %d", d->algo);
-    if (d->surrogate != ALIF_SG_FAST_SIGMOID) return fail(ALIF_EINVAL, "unknown surrogate %d", d->surrogate);
+    if (d->surrogate != ALIF_SG_FAST_SIGMOID && d->surrogate != ALIF_SG_BOXCAR &&
+        d->surrogate != ALIF_SG_MULTI_GAUSSIAN)
+        return fail(ALIF_EINVAL, "unknown surrogate %d", d->surrogate);
     if (!(d->sg_slope >= 0.0f) || !std::isfinite(d->sg_slope)) return fail(ALIF_EINVAL, "bad sg_slope");
     const bool sp = d->input_kind != ALIF_INPUT_CURRENT_F32;
     if (sp) {
@@ -318,6 +320,7 @@ int alif_forward(const alif_desc *desc, const alif_params *prm, const void *inpu
     a.B = p.B; a.T = p.T; a.N = p.N; a.TR = p.TR; a.NB = p.NB;
     a.dt = desc->dt_ms;
     a.slope = desc->sg_slope;
+    a.surrogate = desc->surrogate;
     a.I = I;
     a.bias_k = bias_k;
     a.tau_m = prm->tau_mem_ms; a.tau_a = prm->tau_adapt_ms; a.d = prm->d; a.theta0 = prm->theta0;
@@ -394,6 +397,7 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
         a.n_groups = (p.N + nwg - 1) / nwg;
         a.dt = desc->dt_ms;
         a.slope = desc->sg_slope;
+        a.surrogate = desc->surrogate;
         a.I = I;
         a.bias_k = bias_k;
         a.tau_m = prm->tau_mem_ms; a.tau_a = prm->tau_adapt_ms; a.d = prm->d; a.theta0 = prm->theta0;
@@ -408,6 +412,7 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
         a.B = p.B; a.T = p.T; a.N = p.N; a.TR = p.TR; a.NB = p.NB;
         a.dt = desc->dt_ms;
         a.slope = desc->sg_slope;
+        a.surrogate = desc->surrogate;
         a.I = I;
         a.bias_k = bias_k;
         a.tau_m = prm->tau_mem_ms; a.tau_a = prm->tau_adapt_ms; a.d = prm->d; a.theta0 = prm->theta0;

@@ -529,7 +529,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_fwd(FwdArgs a) {
 // affine map (lam_start = R + M lam_in) in LDS, and every wave composes the
 // maps from the block end (Horner) to get its own incoming lambda and the
 // block's lambda at step 1 (the carry to the previous block).
-template <int SEG, int L, bool EVEN, int DEPTH, bool GVT, bool GI>
+template <int SEG, int L, bool EVEN, int DEPTH, bool GVT, bool GI, int SG>
 __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     constexpr int NWG = Geo<SEG>::NWG;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -666,7 +666,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
         if (quiet) {
 #pragma unroll
             for (int k = L - 1; k >= 0; k--) {
-                const float gsk = cur.gs[k] * fast_sigmoid_grad(vt[k] - th[k], a.slope);
+                const float gsk = cur.gs[k] * surrogate_grad<SG>(vt[k] - th[k], a.slope);
                 float src;
                 if constexpr (GVT) {
                     src = cur.gv[k] + gsk;
@@ -691,7 +691,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
                 ak[k] = after ? fmaf(c.pt[k], a1, pa) : c.pt[k] * a1;
                 const float thk = after ? fmaf(c.dd, pa, th[k]) : th[k];
                 gate[k] = (t > mpre) && !after;
-                const float gsk = cur.gs[k] * fast_sigmoid_grad(Vk[k] - thk, a.slope);
+                const float gsk = cur.gs[k] * surrogate_grad<SG>(Vk[k] - thk, a.slope);
                 float src;
                 if constexpr (GVT) {
                     src = cur.gv[k] + gsk;
@@ -916,18 +916,25 @@ hipError_t blocks_bwd_launch(const BwdArgs &a, hipStream_t st) {
     const size_t sm = bwd_smem_bytes<SEG, L>(a.TR);
     constexpr int TH = Geo<SEG>::THREADS;
     const bool gvt = a.gV || a.gTH, gi = a.gI != nullptr;
-#define ALIF_LB(G1, G2)                                                                           \
+#define ALIF_LB3(G1, G2, SG)                                                                      \
     do {                                                                                          \
         if (a.TR == SEG * L)                                                                      \
-            hipLaunchKernelGGL((k_blocks_bwd<SEG, L, true, bwd_depth<SEG, L>(), G1, G2>), dim3(grid),  \
+            hipLaunchKernelGGL((k_blocks_bwd<SEG, L, true, bwd_depth<SEG, L>(), G1, G2, SG>), dim3(grid), \
                                dim3(TH), sm, st, a);                                              \
         else                                                                                      \
-            hipLaunchKernelGGL((k_blocks_bwd<SEG, L, false, bwd_depth<SEG, L>(), G1, G2>), dim3(grid), \
+            hipLaunchKernelGGL((k_blocks_bwd<SEG, L, false, bwd_depth<SEG, L>(), G1, G2, SG>), dim3(grid),\
                                dim3(TH), sm, st, a);                                              \
+    } while (0)
+#define ALIF_LB(G1, G2)                                                                           \
+    do {                                                                                          \
+        if (a.surrogate == 1) ALIF_LB3(G1, G2, 1);                                                \
+        else if (a.surrogate == 2) ALIF_LB3(G1, G2, 2);                                           \
+        else ALIF_LB3(G1, G2, 0);                                                                 \
     } while (0)
     if (gvt) { if (gi) ALIF_LB(true, true); else ALIF_LB(true, false); }
     else { if (gi) ALIF_LB(false, true); else ALIF_LB(false, false); }
 #undef ALIF_LB
+#undef ALIF_LB3
     return hipGetLastError();
 }
 

@@ -189,6 +189,29 @@ __device__ __forceinline__ float fast_sigmoid_grad(float u, float k) {
     return r * r;
 }
 
+// The surrogate derivatives dS/du at u = V - th (Supplementary, "Surrogate
+// gradient"), selected at compile time:
+//   SG 0  fast sigmoid    (k|u| + 1)^-2
+//   SG 1  boxcar          0.5 where |u| <= 0.5, else 0
+//   SG 2  multi-Gaussian  1.15 N(u | 0, 0.5^2) - 0.15 N(u | 3, 3^2) - 0.15 N(u | -3, 3^2),
+//                         with the constants as the supplementary prints them
+// The exponentials are the hardware ones (v_exp_f32, a few ulp): the values only
+// scale gradients.
+template <int SG>
+__device__ __forceinline__ float surrogate_grad(float u, float k) {
+    if constexpr (SG == 1) {
+        return fabsf(u) <= 0.5f ? 0.5f : 0.0f;
+    } else if constexpr (SG == 2) {
+        constexpr float rs2pi = 0.3989422804014327f;            // 1 / sqrt(2 pi)
+        constexpr float c0 = 1.15f * rs2pi / 0.5f, c1 = 0.15f * rs2pi / 3.0f;
+        const float um = u - 3.0f, up = u + 3.0f;
+        return c0 * __expf(-2.0f * u * u) - c1 * (__expf(um * um * (-1.0f / 18.0f)) +
+                                                   __expf(up * up * (-1.0f / 18.0f)));
+    } else {
+        return fast_sigmoid_grad(u, k);
+    }
+}
+
 // parameter sanity for the block method (positive threshold during refractory)
 __device__ __forceinline__ bool params_ok(float tm, float ta, float d, float th0) {
     return tm > 0.f && ta > 0.f && d >= 0.f && th0 > 0.f && isfinite(tm) && isfinite(ta) &&

@@ -44,6 +44,7 @@ struct FwdArgs {
 struct BwdArgs {
     int B, T, N, TR, NB, n_groups;
     double dt;
+    int surrogate;  // enum alif_surrogate
     float slope;
     const float *I;
     const float *bias_k;
@@ -57,6 +58,7 @@ struct BwdArgs {
 struct SeqArgs {
     int B, T, N, TR, NB;
     double dt;
+    int surrogate;  // enum alif_surrogate (backward)
     float slope;
     const float *I;
     const float *bias_k;

@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_seq_step(SeqArgs a) {
 
 // Sequential backward. Shared memory per lane and step of the current interval:
 // V, theta, a, x, gS (+ gV, gTheta) as float and a flag byte.
-template <bool GVT>
+template <bool GVT, int SG>
 __global__ __launch_bounds__(64) void k_seq_bwd(SeqArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     int b, n;
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(64) void k_seq_bwd(SeqArgs a) {
             const uint8_t f = sF[q];
             const bool s = f & 1, pass = f & 2, sp = f & 4;
             const float V = sV[q], th = sTh[q], av_k = sA[q], x = sX[q];
-            const float sg = fast_sigmoid_grad(V - th, a.slope);
+            const float sg = surrogate_grad<SG>(V - th, a.slope);
             const float gsk = sGS[q] * sg;
             const float cV = (GVT ? sGV[q] : 0.0f) + gsk;
             const float lt = (GVT ? sGT[q] : 0.0f) - gsk;
@@ -311,8 +311,15 @@ hipError_t launch_seq_bwd(const SeqArgs &a, hipStream_t st) {
     if (grid == 0) return hipSuccess;
     const bool gvt = a.gV || a.gTH;
     const size_t smem = (size_t)a.TR * 64 * ((gvt ? 7 : 5) * sizeof(float) + 1);
-    if (gvt) hipLaunchKernelGGL(k_seq_bwd<true>, dim3(grid), dim3(64), smem, st, a);
-    else hipLaunchKernelGGL(k_seq_bwd<false>, dim3(grid), dim3(64), smem, st, a);
+#define ALIF_SB(G)                                                                                \
+    do {                                                                                          \
+        if (a.surrogate == 1) hipLaunchKernelGGL((k_seq_bwd<G, 1>), dim3(grid), dim3(64), smem, st, a); \
+        else if (a.surrogate == 2) hipLaunchKernelGGL((k_seq_bwd<G, 2>), dim3(grid), dim3(64), smem, st, a); \
+        else hipLaunchKernelGGL((k_seq_bwd<G, 0>), dim3(grid), dim3(64), smem, st, a);           \
+    } while (0)
+    if (gvt) ALIF_SB(true);
+    else ALIF_SB(false);
+#undef ALIF_SB
     return hipGetLastError();
 }
 
