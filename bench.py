@@ -253,6 +253,87 @@ def shd_like_leg(steps, warmup, seed=3):
             "steps": steps, "spikes": int(S.sum().item())}
 
 
+def speedup_sweep(steps=5, warmup=2):
+    """Training-step speedup of the block kernels over the fused sequential kernels
+    in the shapes of the paper's speed benchmarks: the synthetic Poisson spike
+    dataset (rate per batch element ~ U[0, 200] Hz, one step = 1 ms), 200 inputs,
+    ALIF layers with loss = total last-layer spike count, forward and backward
+    (FP32 GEMMs, dW for every layer, dx between layers), B 64.
+      * T in {512, 2048} x T_R in {2, 5, 10, 20, 40, 64} (the sequential backward
+        takes T_R <= 64), one layer of 256;
+      * T = 1024, T_R = 40: 1-3 layers of 128, 256 or 512 units.
+    Both algorithms run the same GEMMs; only the ALIF kernels differ. Each row also
+    times the forward alone against the per-step-launch forward (one kernel launch
+    per time step, the cost structure of a step-by-step framework loop)."""
+    import torch
+
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif
+    from paper_2311_11390_amd.synth import speed_benchmark
+    dev = "cuda"
+    configs = [(T, TR, (256,)) for T in (512, 2048) for TR in (2, 5, 10, 20, 40, 64)]
+    configs += [(1024, 40, (h,) * n) for n in (1, 2, 3) for h in (128, 256, 512)]
+    rows = []
+    for T, TR, hidden in configs:
+        w = speed_benchmark(seed=T + TR + len(hidden) * hidden[0], B=64, T=T, hidden=hidden, TR=TR)
+        x = torch.as_tensor(w.inputs["x"], device=dev)
+        Ws = [torch.as_tensor(W, device=dev) for W in w.weights]
+        Ps = [alif.Params.from_numpy(lp, dev) for lp in w.layers]
+        res = {}
+        for name, algo in (("block", L.ALGO_BLOCKS), ("sequential", L.ALGO_SEQUENTIAL)):
+            def step():
+                h, fs, ins = x, [], []
+                for W, P in zip(Ws, Ps):
+                    f = alif.forward(h, P, w.dt, w.arp, W, algo=algo, spike_dtype=L.SPIKES_U8, save=True)
+                    fs.append(f)
+                    ins.append(h)
+                    h = f["spikes"]
+                g = torch.ones(h.shape, dtype=torch.float32, device=dev)
+                for li in reversed(range(len(Ws))):
+                    gr = alif.backward(fs[li], ins[li], Ps[li], Ws[li], grad_spikes=g, want_grad_input=li > 0,
+                                       want_grad_W=True)
+                    g = gr["grad_input"] if li > 0 else None
+                return fs
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fs = step()
+            torch.cuda.synchronize()
+            res[name] = (time.perf_counter() - t0) / steps * 1e3
+            if name == "block":
+                res["spikes_last_layer"] = int(fs[-1]["spikes"].sum().item())
+        for name, algo in (("block_fwd", L.ALGO_BLOCKS), ("per_step_fwd", L.ALGO_SEQUENTIAL_STEP)):
+            def fwd():
+                h = x
+                for W, P in zip(Ws, Ps):
+                    h = alif.forward(h, P, w.dt, w.arp, W, algo=algo, spike_dtype=L.SPIKES_U8)["spikes"]
+            fwd()
+            torch.cuda.synchronize()
+            reps = 1 if algo == L.ALGO_SEQUENTIAL_STEP else steps
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fwd()
+            torch.cuda.synchronize()
+            res[name] = (time.perf_counter() - t0) / reps * 1e3
+        rows.append({"T": T, "T_R": TR, "layers": len(hidden), "hidden": hidden[0], "batch": 64,
+                     "block_ms": res["block"], "sequential_ms": res["sequential"],
+                     "speedup": res["sequential"] / res["block"],
+                     "block_fwd_ms": res["block_fwd"], "per_step_fwd_ms": res["per_step_fwd"],
+                     "fwd_speedup_vs_per_step": res["per_step_fwd"] / res["block_fwd"],
+                     "spikes_last_layer": res["spikes_last_layer"]})
+        log(f"[bench] speedup T={T} T_R={TR} layers={len(hidden)}x{hidden[0]}: block {res['block']:.3f} ms, "
+            f"sequential {res['sequential']:.3f} ms, x{rows[-1]['speedup']:.1f}; forward {res['block_fwd']:.3f} "
+            f"ms vs per-step {res['per_step_fwd']:.2f} ms, x{rows[-1]['fwd_speedup_vs_per_step']:.0f}")
+        del x, Ws, Ps
+    return {"workload": "synthetic Poisson spikes (rate per batch element ~ U[0, 200] Hz), 200 inputs -> ALIF "
+                        "layers, B 64, DT 1 ms, ARP = T_R ms, driven; loss = last-layer spike count; forward + "
+                        "backward with FP32 GEMMs",
+            "comparator": "fused sequential kernels (one thread per (batch, neuron), loop over t)",
+            "steps": steps, "rows": rows}
+
+
 def cpu_baseline(w, cpu_seconds, threads):
     """FP64 oracle fwd + bwd over the whole workload (every (batch, neuron) row, all
     T steps), repeated in whole passes until `cpu_seconds` of CPU time (summed
@@ -371,6 +452,8 @@ def main():
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--no-layers", action="store_true",
                     help="skip the three-layer and SHD-shaped training legs")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the block-vs-sequential speedup sweep over T, T_R, layers and width")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time (summed over threads) the oracle baseline runs for, in whole passes")
@@ -489,6 +572,12 @@ def main():
         log(f"[bench] SHD-shaped: {layers['shd_like']['ms_per_step']:.3f} ms/step")
         torch.cuda.empty_cache()
 
+    sweep = None
+    if not args.no_sweep:
+        log("[bench] block-vs-sequential speedup sweep")
+        sweep = speedup_sweep()
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = len(os.sched_getaffinity(0))
@@ -538,6 +627,7 @@ def main():
         "speedup_vs_sequential": (value / seq["value"]) if seq else None,
         "cpu_baseline": cpu,
         "layers": layers,
+        "speedup_sweep": sweep,
         "serving": serve,
     }
     print(json.dumps(res), flush=True)

@@ -160,6 +160,29 @@ def three_layer(seed=0, driven=False, B=128, T=2000) -> Workload:
                     2.0, sizes, {"x": x}, lps, Ws)
 
 
+def speed_benchmark(seed=0, B=64, T=1024, n_in=200, hidden=(256,), TR=40, driven=True) -> Workload:
+    """The speed-benchmark network: a synthetic spike dataset in which each batch
+    element b fires at r_b ~ U[0, 200] Hz on every input channel (homogeneous
+    Poisson, one step = 1 ms), feeding ALIF layers of the given widths with
+    W ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)), tau_mem 20 ms, tau_adapt 150 ms,
+    d 1.8 (supplementary "Speed benchmarks" and "Weight initialisation");
+    loss = total last-layer spike count. DT = 1 ms and ARP = T_R ms, so the
+    refractory period spans T_R steps. ``driven`` adds a bias b ~ U[1, 2] so that
+    every layer fires (with zero bias the deeper layers fall silent)."""
+    g = rng(seed)
+    rates = g.uniform(0.0, 200.0, B).astype(np.float32)
+    x = bernoulli_spikes(g, (B, T, n_in), (rates * 1e-3)[:, None, None])
+    sizes = [n_in, *hidden]
+    Ws, lps = [], []
+    for i in range(len(hidden)):
+        lim = 1.0 / np.sqrt(sizes[i])
+        Ws.append(g.uniform(-lim, lim, (sizes[i + 1], sizes[i])).astype(np.float32))
+        lps.append(layer_params(g, sizes[i + 1], tau_mem=(20.0, 20.0), tau_adapt=(150.0, 150.0),
+                                bias=(1.0, 2.0) if driven else None))
+    return Workload(f"speed_{n_in}x{'x'.join(map(str, hidden))}_B{B}_T{T}_TR{TR}", B, T, 1.0, float(TR),
+                    sizes, {"x": x}, lps, Ws)
+
+
 @dataclass
 class Request:
     """One serving request: a single ALIF layer of N neurons over T steps fed by
