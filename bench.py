@@ -261,7 +261,8 @@ def speedup_sweep(steps=5, warmup=2):
     (FP32 GEMMs, dW for every layer, dx between layers), B 64.
       * T in {512, 2048} x T_R in {2, 5, 10, 20, 40, 64} (the sequential backward
         takes T_R <= 64), one layer of 256;
-      * T = 1024, T_R = 40: 1-3 layers of 128, 256 or 512 units.
+      * T = 1024, T_R = 40: 1-3 layers of 128, 256 or 512 units;
+      * the supplementary's single-layer forward shape: 200 -> 100, T 1000, B 128, T_R 50.
     Both algorithms run the same GEMMs; only the ALIF kernels differ. Each row also
     times the forward alone against the per-step-launch forward (one kernel launch
     per time step, the cost structure of a step-by-step framework loop)."""
@@ -271,11 +272,12 @@ def speedup_sweep(steps=5, warmup=2):
     from paper_2311_11390_amd import alif
     from paper_2311_11390_amd.synth import speed_benchmark
     dev = "cuda"
-    configs = [(T, TR, (256,)) for T in (512, 2048) for TR in (2, 5, 10, 20, 40, 64)]
-    configs += [(1024, 40, (h,) * n) for n in (1, 2, 3) for h in (128, 256, 512)]
+    configs = [(T, TR, (256,), 64) for T in (512, 2048) for TR in (2, 5, 10, 20, 40, 64)]
+    configs += [(1024, 40, (h,) * n, 64) for n in (1, 2, 3) for h in (128, 256, 512)]
+    configs += [(1000, 50, (100,), 128)]   # the single-layer forward timing shape of the supplementary
     rows = []
-    for T, TR, hidden in configs:
-        w = speed_benchmark(seed=T + TR + len(hidden) * hidden[0], B=64, T=T, hidden=hidden, TR=TR)
+    for T, TR, hidden, B in configs:
+        w = speed_benchmark(seed=T + TR + len(hidden) * hidden[0], B=B, T=T, hidden=hidden, TR=TR)
         x = torch.as_tensor(w.inputs["x"], device=dev)
         Ws = [torch.as_tensor(W, device=dev) for W in w.weights]
         Ps = [alif.Params.from_numpy(lp, dev) for lp in w.layers]
@@ -317,13 +319,13 @@ def speedup_sweep(steps=5, warmup=2):
                 fwd()
             torch.cuda.synchronize()
             res[name] = (time.perf_counter() - t0) / reps * 1e3
-        rows.append({"T": T, "T_R": TR, "layers": len(hidden), "hidden": hidden[0], "batch": 64,
+        rows.append({"T": T, "T_R": TR, "layers": len(hidden), "hidden": hidden[0], "batch": B,
                      "block_ms": res["block"], "sequential_ms": res["sequential"],
                      "speedup": res["sequential"] / res["block"],
                      "block_fwd_ms": res["block_fwd"], "per_step_fwd_ms": res["per_step_fwd"],
                      "fwd_speedup_vs_per_step": res["per_step_fwd"] / res["block_fwd"],
                      "spikes_last_layer": res["spikes_last_layer"]})
-        log(f"[bench] speedup T={T} T_R={TR} layers={len(hidden)}x{hidden[0]}: block {res['block']:.3f} ms, "
+        log(f"[bench] speedup B={B} T={T} T_R={TR} layers={len(hidden)}x{hidden[0]}: block {res['block']:.3f} ms, "
             f"sequential {res['sequential']:.3f} ms, x{rows[-1]['speedup']:.1f}; forward {res['block_fwd']:.3f} "
             f"ms vs per-step {res['per_step_fwd']:.2f} ms, x{rows[-1]['fwd_speedup_vs_per_step']:.0f}")
         del x, Ws, Ps

@@ -195,6 +195,35 @@ def test_blocks_differ_from_standard_model_at_TR1():
     assert mism > 0
 
 
+@pytest.mark.parametrize("n_in,T,weights,bias", [
+    (1, 12, [(1.2,), (2.5,), (6.0,)], 0.0),
+    (2, 5, [(1.5, -0.6), (2.0, 2.0), (0.7, 4.0)], 0.2)])
+def test_brute_force_all_input_patterns(n_in, T, weights, bias):
+    """Every binary input pattern of a tiny spike-input layer (Eq. 3 feeding
+    Eqs. 1-5), over a grid of weights and T_R in {2, 3}: the oracle (its C input
+    current and standard-model recurrence) equals the Blocks model of Props. 1-5
+    on the current b + W x computed here, spike for spike, traces to rounding."""
+    patterns = np.array([[(k >> i) & 1 for i in range(n_in * T)] for k in range(2 ** (n_in * T))],
+                        np.uint8).reshape(-1, T, n_in)
+    tau_m, tau_a, d, theta0, dt = 2.0, 20.0, 0.5, 1.0, 1.0
+    beta, p = math.exp(-dt / tau_m), math.exp(-dt / tau_a)
+    fired = 0
+    for wv in weights:
+        W = np.array([wv], np.float64)
+        I_here = patterns.astype(np.float64) @ W[0] + bias              # [P][T]
+        I_orc = oracle.input_current(patterns, W, np.array([bias]))[..., 0]
+        np.testing.assert_allclose(I_orc, I_here, rtol=0, atol=1e-15)
+        for TR in (2, 3):
+            f = _run(I_orc, tau_m=tau_m, tau_a=tau_a, d=d, theta0=theta0, dt=dt, TR=TR)
+            for r in range(len(patterns)):
+                S, V, TH = blocks(I_here[r], beta, p, d, theta0, TR)
+                assert np.array_equal(S, f["S"][r]), (wv, TR, r)
+                np.testing.assert_allclose(V, f["V"][r], rtol=0, atol=1e-11)
+                np.testing.assert_allclose(TH, f["TH"][r], rtol=0, atol=1e-11)
+            fired += int(f["S"].any(axis=1).sum())
+    assert fired > len(patterns)          # the grid reaches the spiking regime
+
+
 def test_input_current_matches_matmul():
     g = np.random.default_rng(6)
     x = (g.random((3, 50, 37)) < 0.2).astype(np.uint8)
