@@ -7,14 +7,34 @@
 namespace alif {
 
 // Sum the per-(b, n) FP64 partials over the batch in a fixed order and convert
-// d/dbeta, d/dp to d/dtau (dbeta/dtau = beta DT / tau^2).
-__global__ void k_finalize(FinalizeArgs a) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= a.N) return;
+// d/dbeta, d/dp to d/dtau (dbeta/dtau = beta DT / tau^2). A workgroup owns 64
+// neurons; its FIN_PH phases each sum the batch rows b = ph, ph + FIN_PH, ... in
+// increasing order (loads of consecutive neurons coalesce, and the phases keep
+// many loads in flight), then phase 0 adds the phase sums in order 0..FIN_PH-1.
+constexpr int FIN_PH = 16;
+
+__global__ __launch_bounds__(64 * FIN_PH) void k_finalize(FinalizeArgs a) {
+    __shared__ double red[FIN_PH][5][64];
+    const int nl = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + nl;
     const size_t BN = (size_t)a.B * a.N;
     double s[5] = {0, 0, 0, 0, 0};
-    for (int b = 0; b < a.B; b++)
-        for (int q = 0; q < 5; q++) s[q] += a.part[q * BN + (size_t)b * a.N + n];
+    if (n < a.N) {
+#pragma unroll 4
+        for (int b = ph; b < a.B; b += FIN_PH)
+#pragma unroll
+            for (int q = 0; q < 5; q++) s[q] += a.part[q * BN + (size_t)b * a.N + n];
+    }
+#pragma unroll
+    for (int q = 0; q < 5; q++) red[ph][q][nl] = s[q];
+    __syncthreads();
+    if (ph != 0 || n >= a.N) return;
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+        double t = 0.0;
+        for (int k = 0; k < FIN_PH; k++) t += red[k][q][nl];
+        s[q] = t;
+    }
     const double tm = a.tau_m[n], ta = a.tau_a[n];
     const double beta = exp(-a.dt / tm), p = exp(-a.dt / ta);
     if (a.g_tau_m) a.g_tau_m[n] = (float)(s[0] * beta * a.dt / (tm * tm));
@@ -82,7 +102,7 @@ hipError_t launch_blocks_bwd(const BwdArgs &a, hipStream_t st) {
 
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st) {
     if (a.N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize, dim3((a.N + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_finalize, dim3((a.N + 63) / 64), dim3(64 * FIN_PH), 0, st, a);
     return hipGetLastError();
 }
 
