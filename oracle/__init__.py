@@ -59,6 +59,9 @@ def _load():
                                          _u8p, _f64p, _f64p, _f64p, _u8p,
                                          _f64p, _f64p, _f64p,
                                          _f64p, _f64p, _f64p, _f64p, _f64p]
+    lib.oracle_alif_forward_recurrent.argtypes = [_i64, _i64, _i64, _f64p, _f64p, _f64p, _f64p, _f64p,
+                                                  _f64p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                                  _i8p, _u8p, _f64p, _f64p, _f64p, _u8p, _f64p]
     lib.oracle_surrogate.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
     lib.oracle_surrogate.restype = ctypes.c_double
     lib.oracle_readout_forward.argtypes = [_i64, _i64, _f64p, _f64p, ctypes.c_double,
@@ -222,6 +225,45 @@ def alif_forward(I, tau_m, tau_a, d, theta0, dt, arp, force=None):
     out["TR"] = TR
     out["params"] = prm
     return out
+
+
+def alif_forward_recurrent(Iff, W_rec, tau_m, tau_a, d, theta0, dt, arp, force=None, D=None):
+    """The recurrent network (Eq. 3 with W_rec S[t - D], D = T_R unless given) on
+    Iff [B][T][N] = bias + feedforward current. Returns S, V, TH, A, MASK and
+    Itot (the whole current) in [B][T][N], plus ``ff``: the row-wise forward of
+    the same neurons driven by Itot with the recurrent run's decisions imposed,
+    which is what ``alif_backward`` differentiates (under the detached policy the
+    recurrent input is a constant of the spike path)."""
+    Iff = np.ascontiguousarray(Iff, np.float64)
+    B, T, N = Iff.shape
+    TR = refractory_steps(dt, arp)
+    if TR < 1:
+        raise ValueError("ARP is not a whole number of steps")
+    D = TR if D is None else int(D)
+    W_rec = _c64(W_rec)
+    prm = [_c64(np.broadcast_to(np.asarray(q, np.float64), (N,))) for q in (tau_m, tau_a, d, theta0)]
+    fc = None if force is None else np.ascontiguousarray(force, np.int8)
+    S = np.empty((B, T, N), np.uint8)
+    M = np.empty((B, T, N), np.uint8)
+    V, TH, A, It = (np.empty((B, T, N)) for _ in range(4))
+    _load().oracle_alif_forward_recurrent(B, T, N, _p(Iff, ctypes.c_double), _p(W_rec, ctypes.c_double),
+                                          *[_p(q, ctypes.c_double) for q in prm], float(dt), TR, D,
+                                          _p(fc, ctypes.c_int8), _p(S, ctypes.c_uint8), _p(V, ctypes.c_double),
+                                          _p(TH, ctypes.c_double), _p(A, ctypes.c_double),
+                                          _p(M, ctypes.c_uint8), _p(It, ctypes.c_double))
+    ff = alif_forward(It, prm[0], prm[1], prm[2], prm[3], dt, arp, force=S.astype(np.int8))
+    return {"S": S, "V": V, "TH": TH, "A": A, "MASK": M, "Itot": It, "ff": ff}
+
+
+def recurrent_weight_grad(gI, S, D):
+    """Gradient with respect to W_rec of the recurrent term of Eq. 3, with the
+    spikes held constant (detached policy): dL/dW_rec[i][j] = sum over (b, t) of
+    gI[b][t][i] S[b][t - D][j] (one FP64 matrix product over the shifted spikes)."""
+    gI = np.asarray(gI, np.float64)
+    S = np.asarray(S, np.float64)
+    Ssh = np.zeros_like(S)
+    Ssh[:, D:, :] = S[:, :S.shape[1] - D, :]
+    return gI.reshape(-1, gI.shape[-1]).T @ Ssh.reshape(-1, S.shape[-1])
 
 
 def alif_backward(fwd, dt, slope=10.0, gS=None, gV=None, gTH=None, want_gI=True,

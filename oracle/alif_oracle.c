@@ -138,6 +138,65 @@ void oracle_alif_forward(int64_t R, int64_t T, const double *I,
     }
 }
 
+/*
+ * The recurrent network of Eqs. 1-5: Eq. 3's input current gains the recurrent
+ * term sum_j W_rec[i][j] S_j[t - D] with transmission delay D (the paper takes
+ * D = T_R; no spikes before t = 1, so the term is 0 for t <= D). All N neurons
+ * of one batch element advance together, step by step.
+ *   Iff   [B][T][N] the rest of the current (bias + feedforward), FP64
+ *   Wrec  [N][N]    recurrent weights
+ *   force [B][T][N] or NULL: as in oracle_alif_forward
+ * Outputs [B][T][N]: S, V, TH, A, MASK and Itot (the whole Eq. 3 current).
+ */
+void oracle_alif_forward_recurrent(int64_t B, int64_t T, int64_t N, const double *Iff,
+                                   const double *Wrec, const double *tau_m, const double *tau_a,
+                                   const double *d, const double *theta0, double dt, int TR, int D,
+                                   const int8_t *force, uint8_t *S, double *V, double *TH,
+                                   double *A, uint8_t *MASK, double *Itot)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < B; b++) {
+        double *v = calloc((size_t)N, sizeof(double));
+        double *a = calloc((size_t)N, sizeof(double));
+        int *s_prev = calloc((size_t)N, sizeof(int));
+        int *spiked = calloc((size_t)N, sizeof(int));
+        int64_t *t_last = calloc((size_t)N, sizeof(int64_t));
+        for (int64_t t = 0; t < T; t++) {
+            const int64_t o = (b * T + t) * N;
+            const int64_t od = (b * T + t - D) * N;   /* step t - D of the same batch element */
+            for (int64_t i = 0; i < N; i++) {
+                const double beta = exp(-dt / tau_m[i]);
+                const double p = exp(-dt / tau_a[i]);
+                /* Eq. 3 with the recurrent current */
+                double cur = Iff[o + i];
+                if (t - D >= 0)
+                    for (int64_t j = 0; j < N; j++)
+                        if (S[od + j]) cur += Wrec[i * N + j];
+                Itot[o + i] = cur;
+                /* Eq. 4 */
+                const int pass = !spiked[i] || (t - t_last[i]) >= (int64_t)TR;
+                const double in = pass ? cur : 0.0;
+                /* Eq. 2 */
+                v[i] = (beta * v[i] + (1.0 - beta) * in) * (1.0 - (double)s_prev[i]);
+                /* Eq. 5 */
+                a[i] = p * a[i] + (double)s_prev[i];
+                const double th = theta0[i] + d[i] * a[i];
+                /* Eq. 1 */
+                int s1 = v[i] > th;
+                if (force && force[o + i] >= 0) s1 = force[o + i];
+                if (s1) { spiked[i] = 1; t_last[i] = t; }
+                S[o + i] = (uint8_t)s1;
+                V[o + i] = v[i];
+                TH[o + i] = th;
+                A[o + i] = a[i];
+                MASK[o + i] = (uint8_t)pass;
+            }
+            for (int64_t i = 0; i < N; i++) s_prev[i] = S[o + i];
+        }
+        free(v); free(a); free(s_prev); free(spiked); free(t_last);
+    }
+}
+
 /* Normal density N(u | m, s^2). */
 static double normal_pdf(double u, double m, double s)
 {

@@ -47,25 +47,21 @@ def block(I_blk, V0, a0, beta, p, d, theta0):
     return V_t, th, a_t, z, S
 
 
-def blocks(I, beta, p, d, theta0, TR):
-    """Chain ceil(T / T_R) Blocks (Props. 3-5) over one neuron's current I[T].
+class _Chain:
+    """One neuron's state between Blocks: V0 and a0 (Props. 4-5) and the latent
+    spike timing z and spikes S of the previous block (for Prop. 3's mask)."""
 
-    Returns S, V, TH (corrected traces, truncated to T)."""
-    T = len(I)
-    NB = -(-T // TR)
-    Ipad = np.zeros(NB * TR)
-    Ipad[:T] = I                                   # zero padding (footnote to "Blocks")
-    V0, a0 = 0.0, 0.0
-    z_prev = None
-    S_prev = None
-    S_all, V_all, TH_all = [], [], []
-    for n in range(NB):
-        I_blk = Ipad[n * TR:(n + 1) * TR]
-        if z_prev is None:
+    def __init__(self):
+        self.V0, self.a0, self.z_prev, self.S_prev = 0.0, 0.0, None, None
+
+    def step(self, I_blk, beta, p, d, theta0):
+        """Block n + 1 of this neuron on its (unmasked) input current I_blk."""
+        TR = len(I_blk)
+        if self.z_prev is None:
             mask = np.ones(TR)
         else:
-            mask = (z_prev >= S_prev.max()).astype(np.float64)    # Prop. 3
-        V_t, th, a_t, z, S = block(I_blk * mask, V0, a0, beta, p, d, theta0)
+            mask = (self.z_prev >= self.S_prev.max()).astype(np.float64)    # Prop. 3
+        V_t, th, a_t, z, S = block(I_blk * mask, self.V0, self.a0, beta, p, d, theta0)
         V = V_t.copy()
         TH = th.copy()
         if S.max() > 0:
@@ -75,12 +71,27 @@ def blocks(I, beta, p, d, theta0, TR):
             k = np.arange(ts + 1, TR)
             TH[ts + 1:] = theta0 + d * (p ** (k - ts - 1) * (p * a_s + 1.0))   # Eq. 5
             m = int((z > 1).sum())
-            V0 = 0.0                                # Prop. 4
-            a0 = p ** m * (a_s + 1.0 / p)           # Prop. 5
+            self.V0 = 0.0                           # Prop. 4
+            self.a0 = p ** m * (a_s + 1.0 / p)      # Prop. 5
         else:
-            V0 = V_t[-1]                            # Prop. 4
-            a0 = a_t[-1]                            # Prop. 5 (a_n[T_R])
-        z_prev, S_prev = z, S
+            self.V0 = V_t[-1]                       # Prop. 4
+            self.a0 = a_t[-1]                       # Prop. 5 (a_n[T_R])
+        self.z_prev, self.S_prev = z, S
+        return S, V, TH
+
+
+def blocks(I, beta, p, d, theta0, TR):
+    """Chain ceil(T / T_R) Blocks (Props. 3-5) over one neuron's current I[T].
+
+    Returns S, V, TH (corrected traces, truncated to T)."""
+    T = len(I)
+    NB = -(-T // TR)
+    Ipad = np.zeros(NB * TR)
+    Ipad[:T] = I                                   # zero padding (footnote to "Blocks")
+    ch = _Chain()
+    S_all, V_all, TH_all = [], [], []
+    for n in range(NB):
+        S, V, TH = ch.step(Ipad[n * TR:(n + 1) * TR], beta, p, d, theta0)
         S_all.append(S)
         V_all.append(V)
         TH_all.append(TH)
@@ -88,3 +99,30 @@ def blocks(I, beta, p, d, theta0, TR):
     V = np.concatenate(V_all)[:T]
     TH = np.concatenate(TH_all)[:T]
     return S.astype(np.uint8), V, TH
+
+
+def blocks_recurrent(I_ff, W_rec, beta, p, d, theta0, TR):
+    """The recurrent network as Blocks: Prop. 3's input current of block n + 1 is
+    the bias and feedforward current plus sum_j W_rec[i][j] S_{j,n}[t], the
+    spikes of every neuron in block n at the same position t of the block (the
+    recurrent delay equals the block length). I_ff [T][N]; per-neuron beta, p, d,
+    theta0 [N]. Returns S, V, TH [T][N]."""
+    T, N = I_ff.shape
+    NB = -(-T // TR)
+    Ipad = np.zeros((NB * TR, N))
+    Ipad[:T] = I_ff
+    chains = [_Chain() for _ in range(N)]
+    S_out = np.zeros((NB * TR, N), np.uint8)
+    V_out = np.zeros((NB * TR, N))
+    TH_out = np.zeros((NB * TR, N))
+    S_prev_blk = np.zeros((TR, N))
+    for n in range(NB):
+        sl = slice(n * TR, (n + 1) * TR)
+        I_blk = Ipad[sl] + S_prev_blk @ np.asarray(W_rec, np.float64).T
+        for i in range(N):
+            S, V, TH = chains[i].step(I_blk[:, i], beta[i], p[i], d[i], theta0[i])
+            S_out[sl, i] = S
+            V_out[sl, i] = V
+            TH_out[sl, i] = TH
+        S_prev_blk = S_out[sl].astype(np.float64)
+    return S_out[:T], V_out[:T], TH_out[:T]
