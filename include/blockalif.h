@@ -258,6 +258,41 @@ int alif_backward(const alif_desc *desc, const alif_params *prm,
                   void *workspace, void *stream);
 
 /*
+ * Recurrent layer: Eq. 3's input current with the recurrent term
+ * sum_j W_rec[i][j] S_j[t - D] and transmission delay D = T_R (Section 2), which
+ * Prop. 3 turns into block n + 1 receiving W_rec times the spikes of block n.
+ * The blocks run one after another: per block one MFMA GEMM adds the recurrent
+ * current of the block to `current`, then the block kernel runs that block from
+ * the previous block's FP64 carry. No initial or final state: the run starts
+ * from rest with no earlier spike.
+ *   desc, prm   as alif_forward; desc->algo must be ALIF_ALGO_BLOCKS;
+ *               desc->gemm_precision applies to both GEMMs
+ *   input, W    as alif_forward (current input: float [B][T][N]; spike input:
+ *               spikes [B][T][n_in] and W [N][n_in])
+ *   W_rec       device float [N][N]
+ *   current     device float [B][T][N], required: receives the whole current,
+ *               b + W x + W_rec S[t - T_R] for spike input, input + W_rec S[t - T_R]
+ *               for current input (the bias then added in-kernel, as
+ *               alif_forward does). Pass it to alif_backward as `current` (spike
+ *               input) or as `input` (current input): under the detached policy
+ *               the recurrent current is a constant of the spike path, so the
+ *               ordinary backward applies.
+ *   spikes, v, theta, carries   as alif_forward
+ *   workspace   device scratch of alif_recurrent_workspace_bytes() bytes
+ * alif_recurrent_weight_grad: grad_W_rec[i][j] = sum over b, t >= T_R of
+ * grad_current[b][t][i] S[b][t - T_R][j] (device float [N][N]), from the spikes
+ * alif_forward_recurrent wrote (desc->spike_dtype) and the same workspace size.
+ */
+int alif_recurrent_workspace_bytes(const alif_desc *desc, size_t *bytes);
+int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm,
+                           const void *input, const float *W, const float *W_rec,
+                           float *current, void *spikes, float *v, float *theta,
+                           void *carries, void *workspace, void *stream);
+int alif_recurrent_weight_grad(const alif_desc *desc, const float *grad_current,
+                               const void *spikes, float *grad_W_rec,
+                               void *workspace, void *stream);
+
+/*
  * Leaky non-spiking readout (supplementary "Readout neurons"): the membrane of
  * Eq. 2 without spike, reset or refractory gate, driven by I_r = W_r S, with
  * output o[b][c] = sum_t V_r[b][t][c].

@@ -165,6 +165,70 @@ def backward(fwd: dict, inp: torch.Tensor, params: Params, W: torch.Tensor | Non
     return out
 
 
+def forward_recurrent(inp: torch.Tensor, params: Params, dt: float, arp: float, W_rec: torch.Tensor,
+                      W: torch.Tensor | None = None, *, gemm_precision=L.GEMM_FP32, spike_dtype=L.SPIKES_U8,
+                      want_v=False, want_theta=False, save=True, slope=10.0, surrogate=L.SG_FAST_SIGMOID,
+                      workspace=None) -> dict:
+    """One recurrent ALIF layer (alif_forward_recurrent): Eq. 3 with the recurrent
+    current W_rec S[t - T_R]. ``inp`` as in ``forward``. Returns ``spikes``,
+    optional ``v``/``theta``, ``current`` (the whole current, which the backward
+    differentiates), ``carries``, ``desc`` and the ``workspace`` (reusable by
+    ``recurrent_weight_grad``)."""
+    assert inp.is_cuda and inp.is_contiguous() and W_rec.dtype == torch.float32 and W_rec.is_contiguous()
+    B, T = inp.shape[0], inp.shape[1]
+    dev = inp.device
+    if W is None:
+        assert inp.dtype == torch.float32
+        N, n_in, kind = inp.shape[2], 0, L.INPUT_CURRENT_F32
+    else:
+        assert W.dtype == torch.float32 and W.is_contiguous()
+        N, n_in = W.shape
+        kind = _INPUT_KIND[inp.dtype]
+    assert W_rec.shape == (N, N)
+    desc = make_desc(B, T, N, dt, arp, n_in, kind, gemm_precision, spike_dtype, L.ALGO_BLOCKS, slope, surrogate)
+    spikes = torch.empty(B, T, N, dtype=_SPIKE_TORCH[spike_dtype], device=dev)
+    v = torch.empty(B, T, N, dtype=torch.float32, device=dev) if want_v else None
+    th = torch.empty(B, T, N, dtype=torch.float32, device=dev) if want_theta else None
+    current = torch.empty(B, T, N, dtype=torch.float32, device=dev)
+    carries = torch.empty(max(1, carry_bytes(desc)), dtype=torch.uint8, device=dev) if save else None
+    if workspace is None:
+        n = ctypes.c_size_t()
+        L.check(L.load().alif_recurrent_workspace_bytes(ctypes.byref(desc), ctypes.byref(n)))
+        workspace = torch.empty(max(1, n.value), dtype=torch.uint8, device=dev)
+    cp = params.c()
+    L.check(L.load().alif_forward_recurrent(ctypes.byref(desc), ctypes.byref(cp), _p(inp), _p(W), _p(W_rec),
+                                            _p(current), _p(spikes), _p(v), _p(th), _p(carries), _p(workspace),
+                                            _stream(dev)))
+    return {"spikes": spikes, "v": v, "theta": th, "current": current, "carries": carries, "desc": desc,
+            "workspace": workspace, "recurrent": True, "current_input": W is None}
+
+
+def recurrent_weight_grad(fwd: dict, grad_current: torch.Tensor) -> torch.Tensor:
+    """grad_W_rec [N][N] = sum_{b,t} grad_current[b][t]^T S[b][t - T_R] (alif_recurrent_weight_grad)."""
+    desc = fwd["desc"]
+    N = desc.n_neurons
+    out = torch.empty(N, N, dtype=torch.float32, device=grad_current.device)
+    L.check(L.load().alif_recurrent_weight_grad(ctypes.byref(desc), _p(grad_current.contiguous()),
+                                                _p(fwd["spikes"]), _p(out), _p(fwd["workspace"]),
+                                                _stream(grad_current.device)))
+    return out
+
+
+def backward_recurrent(fwd: dict, inp: torch.Tensor, params: Params, W: torch.Tensor | None = None, **kw) -> dict:
+    """Backward of ``forward_recurrent`` under the detached policy: the ordinary
+    layer backward on the whole current (the recurrent input is a constant of the
+    spike path), plus ``grad_W_rec``. Keyword arguments as ``backward``."""
+    kw = dict(kw)
+    kw["want_grad_current"] = True
+    if fwd["current_input"]:
+        f = dict(fwd, current=None)
+        out = backward(f, fwd["current"], params, None, **kw)
+    else:
+        out = backward(fwd, inp, params, W, **kw)
+    out["grad_W_rec"] = recurrent_weight_grad(fwd, out["grad_current"])
+    return out
+
+
 def decay_tables(params: Params, N, dt, arp):
     desc = make_desc(1, 1, N, dt, arp)
     TR = refractory_steps(dt, arp)

@@ -451,6 +451,149 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
     return ALIF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// recurrent layer (Eq. 3's recurrent current with delay D = T_R; Prop. 3)
+// ---------------------------------------------------------------------------
+namespace {
+
+int spike_elem_bytes(int sdt) { return sdt == ALIF_SPIKES_U8 ? 1 : (sdt == ALIF_SPIKES_BF16 ? 2 : 4); }
+int spike_gemm_kind(int sdt) {
+    return sdt == ALIF_SPIKES_U8 ? ALIF_INPUT_SPIKES_U8
+                                 : (sdt == ALIF_SPIKES_BF16 ? ALIF_INPUT_SPIKES_BF16 : ALIF_INPUT_SPIKES_F32);
+}
+
+// Forward scratch: the spikes of every block, block-major [NB][B][T_R][N] (each
+// block 256-byte aligned, the A operand of the next block's recurrent GEMM),
+// then two FP64 carry states [B][N] (v, a) and their int32 spike steps.
+struct RecLayout {
+    size_t blk, spikes, state, total;
+};
+RecLayout rec_layout(const alif_desc *d, const Prob &p) {
+    RecLayout L{};
+    const size_t sb = (size_t)spike_elem_bytes(d->spike_dtype);
+    L.blk = align256((size_t)p.B * p.TR * p.N * sb);
+    L.spikes = L.blk * p.NB;
+    L.state = align256((size_t)p.B * p.N * 8) * 4 + align256((size_t)p.B * p.N * 4) * 2;
+    const size_t fwd = L.spikes + L.state;
+    // weight gradient: the spikes shifted by T_R steps, then the GEMM's partial sums
+    const size_t wg = align256((size_t)p.B * p.T * p.N * sb) + gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.N);
+    L.total = fwd > wg ? fwd : wg;
+    return L;
+}
+
+}  // namespace
+
+int alif_recurrent_workspace_bytes(const alif_desc *desc, size_t *bytes) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    if (!bytes) return fail(ALIF_EINVAL, "bytes is NULL");
+    *bytes = rec_layout(desc, p).total;
+    return ALIF_OK;
+}
+
+int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm, const void *input, const float *W,
+                           const float *W_rec, float *current, void *spikes, float *v, float *theta,
+                           void *carries, void *workspace, void *stream) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    if ((rc = check_params(prm))) return rc;
+    if (desc->algo != ALIF_ALGO_BLOCKS) return fail(ALIF_EUNSUPPORTED, "the recurrent layer runs the blocks algorithm");
+    const size_t BTN = (size_t)p.B * p.T * p.N;
+    if (BTN == 0) return ALIF_OK;
+    if (!input || !W_rec || !current || !spikes || !workspace)
+        return fail(ALIF_EINVAL, "input, W_rec, current, spikes and workspace are required");
+    if (p.spikes_in && !W) return fail(ALIF_EINVAL, "spike input needs W");
+    unsigned *status = nullptr;
+    if ((rc = status_word(&status))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const bool bf16 = desc->gemm_precision == ALIF_GEMM_BF16;
+    const float *bias_k = prm->bias;
+    hipError_t e;
+    // the current without its recurrent part: b + W x (spike input) or the input
+    // itself (current input; the bias is then added in-kernel, as alif_forward does)
+    if (p.spikes_in) {
+        GemmIn in;
+        in.kind = desc->input_kind;
+        in.ptr = input;
+        e = gemm_input_current((size_t)p.B * p.T, p.N, p.n_in, in, W, prm->bias, current, bf16, st);
+        if (e != hipSuccess) return hip_fail(e, "input-current GEMM");
+        bias_k = nullptr;
+    } else {
+        e = hipMemcpyAsync(current, input, BTN * sizeof(float), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "current copy");
+    }
+    const RecLayout L = rec_layout(desc, p);
+    char *ws = (char *)workspace;
+    char *sblk = ws;
+    char *stb = ws + L.spikes;
+    const size_t s8 = align256((size_t)p.B * p.N * 8), s4 = align256((size_t)p.B * p.N * 4);
+    double *sv[2] = {(double *)stb, (double *)(stb + s8)};
+    double *sa[2] = {(double *)(stb + 2 * s8), (double *)(stb + 3 * s8)};
+    int32_t *sts[2] = {(int32_t *)(stb + 4 * s8), (int32_t *)(stb + 4 * s8 + s4)};
+    const int nwg = block_neurons_per_wg(block_config(p.TR).seg);
+    const size_t TN = (size_t)p.T * p.N, TRN = (size_t)p.TR * p.N;
+    const int sb = spike_elem_bytes(desc->spike_dtype);
+    for (int n = 0; n < p.NB; n++) {
+        const int rows = p.T - n * p.TR < p.TR ? p.T - n * p.TR : p.TR;
+        float *cur_n = current + n * TRN;
+        if (n > 0) {   // block n's recurrent current from the spikes of block n - 1
+            GemmIn s;
+            s.kind = spike_gemm_kind(desc->spike_dtype);
+            s.ptr = sblk + (size_t)(n - 1) * L.blk;
+            e = gemm_recurrent_block(p.B, p.TR, rows, p.N, (long long)TN, s, W_rec, cur_n, cur_n, bf16, st);
+            if (e != hipSuccess) return hip_fail(e, "recurrent-current GEMM");
+        }
+        FwdArgs a{};
+        a.B = p.B; a.T = rows; a.N = p.N; a.TR = p.TR; a.NB = 1;
+        a.n_groups = (p.N + nwg - 1) / nwg;
+        a.dt = desc->dt_ms;
+        a.I = cur_n;
+        a.bias_k = bias_k;
+        a.tau_m = prm->tau_mem_ms; a.tau_a = prm->tau_adapt_ms; a.d = prm->d; a.theta0 = prm->theta0;
+        if (n > 0) { a.init_v = sv[(n - 1) & 1]; a.init_a = sa[(n - 1) & 1]; a.init_ts = sts[(n - 1) & 1]; }
+        a.fin_v = sv[n & 1]; a.fin_a = sa[n & 1]; a.fin_ts = sts[n & 1];
+        a.spikes = sblk + (size_t)n * L.blk;
+        a.spike_dtype = desc->spike_dtype;
+        a.V = v ? v + n * TRN : nullptr;
+        a.TH = theta ? theta + n * TRN : nullptr;
+        if (carries) a.ck = carry_view(carries, p);
+        a.status = status;
+        a.bs_i = TN;
+        a.bs_s = TRN;
+        a.ck_nb = p.NB;
+        a.ck_off = n;
+        e = launch_blocks_fwd(a, st);
+        if (e != hipSuccess) return hip_fail(e, "block forward launch");
+    }
+    e = launch_blocks_to_bt(p.B, p.T, p.N, p.TR, sb, sblk, L.blk, spikes, st);
+    if (e != hipSuccess) return hip_fail(e, "spike layout launch");
+    return ALIF_OK;
+}
+
+int alif_recurrent_weight_grad(const alif_desc *desc, const float *grad_current, const void *spikes,
+                               float *grad_W_rec, void *workspace, void *stream) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    if (!grad_current || !spikes || !grad_W_rec || !workspace)
+        return fail(ALIF_EINVAL, "grad_current, spikes, grad_W_rec and workspace are required");
+    hipStream_t st = (hipStream_t)stream;
+    const int sb = spike_elem_bytes(desc->spike_dtype);
+    const size_t shb = align256((size_t)p.B * p.T * p.N * sb);
+    char *shifted = (char *)workspace;
+    hipError_t e = launch_shift_time(p.B, p.T, p.N, p.TR, sb, spikes, shifted, st);
+    if (e != hipSuccess) return hip_fail(e, "spike shift launch");
+    GemmIn x;
+    x.kind = spike_gemm_kind(desc->spike_dtype);
+    x.ptr = shifted;
+    e = gemm_weight_grad((size_t)p.B * p.T, p.N, p.N, grad_current, x, grad_W_rec,
+                         desc->gemm_precision == ALIF_GEMM_BF16, shifted + shb, st);
+    if (e != hipSuccess) return hip_fail(e, "recurrent weight-gradient GEMM");
+    return ALIF_OK;
+}
+
 int alif_device_status(uint32_t *bits, void *stream) {
     if (!bits) return fail(ALIF_EINVAL, "bits is NULL");
     unsigned *s = nullptr;

@@ -100,6 +100,68 @@ hipError_t launch_blocks_bwd(const BwdArgs &a, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// layout moves of the recurrent layer (grid-stride loops over the output)
+// ---------------------------------------------------------------------------
+template <typename E>
+__global__ void k_blocks_to_bt(size_t total, int T, int N, int TR, const char *blocks, size_t blk_bytes,
+                               E *out) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t bt = e / N;
+        const int i = (int)(e - bt * N);
+        const int t = (int)(bt % T);
+        const size_t b = bt / T;
+        const int n = t / TR, k = t - n * TR;
+        const E *src = reinterpret_cast<const E *>(blocks + (size_t)n * blk_bytes);
+        out[e] = src[(b * TR + k) * N + i];
+    }
+}
+
+template <typename E>
+__global__ void k_shift_time(size_t total, int T, int N, int D, const E *in, E *out) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int t = (int)((e / N) % T);
+        out[e] = t >= D ? in[e - (size_t)D * N] : E(0);
+    }
+}
+
+static unsigned grid_for(size_t total) {
+    const size_t g = (total + 255) / 256;
+    return (unsigned)(g < ((size_t)1 << 20) ? (g ? g : 1) : ((size_t)1 << 20));
+}
+
+hipError_t launch_blocks_to_bt(int B, int T, int N, int TR, int elem, const void *blocks, size_t blk_bytes,
+                               void *spikes, hipStream_t st) {
+    const size_t total = (size_t)B * T * N;
+    if (total == 0) return hipSuccess;
+    const char *bl = static_cast<const char *>(blocks);
+    if (elem == 1)
+        hipLaunchKernelGGL(k_blocks_to_bt<uint8_t>, dim3(grid_for(total)), dim3(256), 0, st, total, T, N, TR, bl,
+                           blk_bytes, static_cast<uint8_t *>(spikes));
+    else if (elem == 2)
+        hipLaunchKernelGGL(k_blocks_to_bt<uint16_t>, dim3(grid_for(total)), dim3(256), 0, st, total, T, N, TR, bl,
+                           blk_bytes, static_cast<uint16_t *>(spikes));
+    else
+        hipLaunchKernelGGL(k_blocks_to_bt<uint32_t>, dim3(grid_for(total)), dim3(256), 0, st, total, T, N, TR, bl,
+                           blk_bytes, static_cast<uint32_t *>(spikes));
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_time(int B, int T, int N, int D, int elem, const void *in, void *out, hipStream_t st) {
+    const size_t total = (size_t)B * T * N;
+    if (total == 0) return hipSuccess;
+    if (elem == 1)
+        hipLaunchKernelGGL(k_shift_time<uint8_t>, dim3(grid_for(total)), dim3(256), 0, st, total, T, N, D,
+                           static_cast<const uint8_t *>(in), static_cast<uint8_t *>(out));
+    else if (elem == 2)
+        hipLaunchKernelGGL(k_shift_time<uint16_t>, dim3(grid_for(total)), dim3(256), 0, st, total, T, N, D,
+                           static_cast<const uint16_t *>(in), static_cast<uint16_t *>(out));
+    else
+        hipLaunchKernelGGL(k_shift_time<uint32_t>, dim3(grid_for(total)), dim3(256), 0, st, total, T, N, D,
+                           static_cast<const uint32_t *>(in), static_cast<uint32_t *>(out));
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st) {
     if (a.N == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3((a.N + 63) / 64), dim3(64 * FIN_PH), 0, st, a);

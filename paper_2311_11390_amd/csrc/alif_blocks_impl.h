@@ -323,15 +323,19 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_fwd(FwdArgs a) {
     const int pfrow = c.nl * RL + TR + c.t0;
 
     const size_t TN = (size_t)T * N;
-    const rsrc_t rI = make_rsrc(a.I + b * TN, (uint32_t)(TN * 4));
-    const rsrc_t rS = make_rsrc((const char *)a.spikes + b * TN * SB, (uint32_t)(TN * SB));
-    const rsrc_t rV = make_rsrc(a.V ? a.V + b * TN : nullptr, a.V ? (uint32_t)(TN * 4) : 0u);
-    const rsrc_t rT = make_rsrc(a.TH ? a.TH + b * TN : nullptr, a.TH ? (uint32_t)(TN * 4) : 0u);
-    const size_t CN = (size_t)(a.NB + 1) * N;   // carry-in of every block, then the final carry
+    const size_t bsi = a.bs_i ? a.bs_i : TN, bss = a.bs_s ? a.bs_s : TN;
+    const rsrc_t rI = make_rsrc(a.I + b * bsi, (uint32_t)(TN * 4));
+    const rsrc_t rS = make_rsrc((const char *)a.spikes + b * bss * SB, (uint32_t)(TN * SB));
+    const rsrc_t rV = make_rsrc(a.V ? a.V + b * bsi : nullptr, a.V ? (uint32_t)(TN * 4) : 0u);
+    const rsrc_t rT = make_rsrc(a.TH ? a.TH + b * bsi : nullptr, a.TH ? (uint32_t)(TN * 4) : 0u);
+    // carry-in of every block, then the final carry; a sub-range run writes its
+    // entries at block ck_off of arrays with ck_nb blocks
+    const size_t CN = (size_t)((a.ck_nb ? a.ck_nb : a.NB) + 1) * N, CE = (size_t)(a.NB + 1) * N;
+    const size_t CO = b * CN + (size_t)a.ck_off * N;
     const bool ck = a.ck.v != nullptr;
-    const rsrc_t rCv = make_rsrc(ck ? a.ck.v + b * CN : nullptr, ck ? (uint32_t)(CN * 4) : 0u);
-    const rsrc_t rCa = make_rsrc(ck ? a.ck.a + b * CN : nullptr, ck ? (uint32_t)(CN * 4) : 0u);
-    const rsrc_t rCt = make_rsrc(ck ? a.ck.ts + b * CN : nullptr, ck ? (uint32_t)CN : 0u);
+    const rsrc_t rCv = make_rsrc(ck ? a.ck.v + CO : nullptr, ck ? (uint32_t)(CE * 4) : 0u);
+    const rsrc_t rCa = make_rsrc(ck ? a.ck.a + CO : nullptr, ck ? (uint32_t)(CE * 4) : 0u);
+    const rsrc_t rCt = make_rsrc(ck ? a.ck.ts + CO : nullptr, ck ? (uint32_t)CE : 0u);
     // checkpoint offsets (bytes); only the segment-0 wave stores
     const uint32_t ck4 = (c.valid && c.w == 0) ? (uint32_t)c.n * 4u : ALIF_OOB;
     const uint32_t ck1 = (c.valid && c.w == 0) ? (uint32_t)c.n : ALIF_OOB;

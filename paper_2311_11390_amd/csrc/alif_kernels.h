@@ -39,6 +39,12 @@ struct FwdArgs {
     float *V, *TH;
     CarryView ck;
     unsigned *status;
+    // Sub-range runs (0 = the defaults of a whole-tensor run): elements between
+    // consecutive batch elements of I, V, TH (bs_i) and of spikes (bs_s), the
+    // block dimension of the carry arrays (ck_nb) and the block index of this
+    // run's first carry in them (ck_off).
+    size_t bs_i, bs_s;
+    int ck_nb, ck_off;
 };
 
 struct BwdArgs {
@@ -97,6 +103,11 @@ BlockConfig block_config(int TR);
 int block_neurons_per_wg(int seg);
 
 hipError_t launch_blocks_fwd(const FwdArgs &a, hipStream_t st);
+// spikes[b][n T_R + k][i] = blocks[n][b][k][i] (block n at byte offset n * blk_bytes), for n T_R + k < T
+hipError_t launch_blocks_to_bt(int B, int T, int N, int TR, int elem, const void *blocks, size_t blk_bytes,
+                               void *spikes, hipStream_t st);
+// out[b][t][i] = in[b][t - D][i] for t >= D, else 0 (elements of `elem` bytes)
+hipError_t launch_shift_time(int B, int T, int N, int D, int elem, const void *in, void *out, hipStream_t st);
 hipError_t launch_blocks_bwd(const BwdArgs &a, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st);
 hipError_t launch_decay_tables(int N, int TR, double dt, const float *tau_m, const float *tau_a,

@@ -51,6 +51,36 @@ def teacher_forced_forward(gpu_S, I, tau_m, tau_a, d, theta0, dt, arp, max_iter=
     raise ParityError("teacher forcing did not converge")
 
 
+def teacher_forced_recurrent(gpu_S, Iff, W_rec, tau_m, tau_a, d, theta0, dt, arp, max_iter=200):
+    """The recurrent oracle on Iff[B][T][N] (bias + feedforward current), with the
+    GPU's decisions imposed where they differ from the oracle's within MARGIN of
+    threshold. Neurons of one batch element are coupled through W_rec, so each
+    round imposes the mismatches at the earliest differing step of every batch
+    element and re-runs; a mismatch there with a larger margin fails.
+
+    Returns (oracle result dict, number of excused flips)."""
+    gpu_S = np.asarray(gpu_S).astype(np.uint8)
+    B, T, N = gpu_S.shape
+    force = np.full((B, T, N), -1, np.int8)
+    excused = 0
+    for _ in range(max_iter):
+        orc = oracle.alif_forward_recurrent(Iff, W_rec, tau_m, tau_a, d, theta0, dt, arp, force=force)
+        mism = gpu_S != orc["S"]
+        if not mism.any():
+            return orc, excused
+        for b in np.flatnonzero(mism.any(axis=(1, 2))):
+            t = int(np.argmax(mism[b].any(axis=1)))
+            ns = np.flatnonzero(mism[b, t])
+            margin = orc["V"][b, t, ns] - orc["TH"][b, t, ns]
+            if (np.abs(margin) >= MARGIN).any():
+                k = int(ns[np.argmax(np.abs(margin) >= MARGIN)])
+                raise ParityError(f"recurrent spike mismatch at b={b} t={t} n={k}: gpu={gpu_S[b, t, k]} "
+                                  f"oracle={orc['S'][b, t, k]} margin={orc['V'][b, t, k] - orc['TH'][b, t, k]:.3e}")
+            force[b, t, ns] = gpu_S[b, t, ns]
+            excused += len(ns)
+    raise ParityError("teacher forcing did not converge")
+
+
 def check_forward(gpu, I, prm, dt, arp, v_gpu=None, th_gpu=None):
     """Full forward parity. ``prm`` has numpy tau_mem, tau_adapt, d, theta0 (and bias)
     [N]; I is the current before bias. Returns a report dict."""

@@ -1,0 +1,108 @@
+"""GPU parity of the recurrent layer (Eq. 3 with W_rec S[t - T_R]; Prop. 3):
+alif_forward_recurrent against the oracle's recurrent network (teacher-forced at
+near-threshold crossings), and the detached-policy backward with the recurrent
+weight gradient against the oracle's adjoint, all through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import driven_current, log, np_, random_params, to_dev
+
+driven_input = lambda seed, B, T, N: driven_current(seed, B, T, N).astype(np.float64)
+from parity import TRACE_TOL, check_grad, teacher_forced_recurrent
+from paper_2311_11390_amd.synth import bernoulli_spikes, normal_weights, rng
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_round(a):
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _case(seed, B, T, N, TR, dt, spike_input=False, n_in=90, prec=0, gain=1.0):
+    import torch
+
+    from paper_2311_11390_amd import alif
+    g = rng(seed)
+    prm = random_params(seed, N, tm=(3.0, 30.0), bias=(0.8, 1.6) if spike_input else (-0.2, 0.3))
+    W_rec = (g.standard_normal((N, N)) * gain / np.sqrt(N)).astype(np.float32)
+    if spike_input:
+        x = bernoulli_spikes(g, (B, T, n_in), 0.1)
+        W = (normal_weights(g, N, n_in) * 3.0).astype(np.float32)
+        Wt = torch.as_tensor(W, device="cuda")
+        inp = torch.as_tensor(x, device="cuda")
+        Iff = oracle.input_current(x, _bf16_round(W) if prec else W, prm.bias)
+    else:
+        I = driven_current(seed, B, T, N)
+        inp = torch.as_tensor(I, device="cuda")
+        Wt = None
+        Iff = I.astype(np.float64) + prm.bias[None, None, :]
+    log(f"[rec] seed={seed} B={B} T={T} N={N} T_R={TR} spike_input={spike_input} prec={prec}")
+    P = to_dev(prm)
+    f = alif.forward_recurrent(inp, P, dt, 2.0, torch.as_tensor(W_rec, device="cuda"), Wt, gemm_precision=prec,
+                               want_v=True, want_theta=True)
+    torch.cuda.synchronize()
+    Wr = _bf16_round(W_rec) if prec else W_rec.astype(np.float64)
+    orc, excused = teacher_forced_recurrent(np_(f["spikes"]), Iff, Wr, prm.tau_mem, prm.tau_adapt, prm.d,
+                                            prm.theta0, dt, 2.0)
+    return f, orc, excused, prm, P, inp, Wt
+
+
+@pytest.mark.parametrize("TR,dt", [(2, 1.0), (5, 0.4), (20, 0.1), (40, 0.05)])
+def test_recurrent_forward_current_input(TR, dt):
+    B, N = 2, 67
+    T = 12 * TR + TR // 2 + 1          # a ragged last block
+    f, orc, excused, prm, *_ = _case(900 + TR, B, T, N, TR, dt)
+    S = np_(f["spikes"])
+    # the recurrent term must matter: some neuron fires in a block after another's spike
+    assert S.sum() > 50
+    dV = np.abs(np_(f["v"]) - orc["V"]).max()
+    dTH = np.abs(np_(f["theta"]) - orc["TH"]).max()
+    # the whole current, bias excluded on the current-input path (added in-kernel)
+    dI = np.abs(np_(f["current"]) + prm.bias[None, None, :] - orc["Itot"]).max()
+    log(f"    spikes {int(S.sum())}, excused {excused}, max|dV| {dV:.1e}, max|dTH| {dTH:.1e}, max|dI| {dI:.1e}")
+    assert dV <= TRACE_TOL and dTH <= TRACE_TOL and dI <= 1e-4
+    # the recurrent term contributes (the whole current differs from input + bias)
+    assert np.abs(orc["Itot"] - (driven_input(900 + TR, B, T, N) + prm.bias)).max() > 0.1
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_recurrent_forward_spike_input(prec):
+    B, N, TR, dt = 3, 130, 4, 0.5
+    T = 30 * TR
+    f, orc, excused, prm, *_ = _case(950 + prec, B, T, N, TR, dt, spike_input=True, prec=prec)
+    dV = np.abs(np_(f["v"]) - orc["V"]).max()
+    dI = np.abs(np_(f["current"]) - orc["Itot"]).max()
+    log(f"    spikes {int(np_(f['spikes']).sum())}, excused {excused}, max|dV| {dV:.1e}, max|dI| {dI:.1e}")
+    assert np_(f["spikes"]).sum() > 50
+    assert dV <= TRACE_TOL and dI <= 1e-4
+
+
+@pytest.mark.parametrize("TR,dt,spike_input", [(2, 1.0, False), (20, 0.1, False), (4, 0.5, True)])
+def test_recurrent_backward(TR, dt, spike_input):
+    """Detached policy: the layer backward on the whole current plus
+    grad_W_rec = sum gI^T S[t - T_R], against the oracle's adjoint of the
+    teacher-forced run."""
+    import torch
+
+    from paper_2311_11390_amd import alif
+    B, N = 2, 67
+    T = 10 * TR + 1
+    f, orc, excused, prm, P, inp, Wt = _case(970 + TR, B, T, N, TR, dt, spike_input=spike_input, n_in=50)
+    g = rng(971 + TR)
+    gS = g.standard_normal((B, T, N)).astype(np.float32)
+    out = alif.backward_recurrent(f, inp, P, Wt, grad_spikes=torch.as_tensor(gS, device="cuda"),
+                                  want_grad_W=spike_input)
+    torch.cuda.synchronize()
+    ob = oracle.alif_backward(orc["ff"], dt, 10.0, gS=gS)
+    check_grad("grad_current", np_(out["grad_current"]), ob["gI"])
+    check_grad("grad_W_rec", np_(out["grad_W_rec"]), oracle.recurrent_weight_grad(ob["gI"], orc["S"], TR))
+    for k, ko in [("grad_tau_mem", "g_tau_m"), ("grad_tau_adapt", "g_tau_a"), ("grad_d", "g_d"),
+                  ("grad_theta0", "g_theta0")]:
+        check_grad(k, np_(out[k]), ob[ko])
+    if spike_input:
+        x = np_(inp).astype(np.float64)
+        check_grad("grad_W", np_(out["grad_W"]), oracle.weight_grad(ob["gI"], x))
+    log(f"    excused {excused}")
