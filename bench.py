@@ -336,6 +336,70 @@ def speedup_sweep(steps=5, warmup=2):
             "steps": steps, "rows": rows}
 
 
+def recurrent_leg(w, I, P, gS, steps=3):
+    """The fine-DT workload as a recurrent network: the OU current plus
+    W_rec S[t - T_R] (W_rec ~ N(0, 0.5^2 / N)), T_R = 40, so 500 blocks run one
+    after another, each a recurrent GEMM and a one-block kernel launch. Times the
+    forward eagerly and as a captured HIP graph replay (torch.cuda.CUDAGraph on
+    the library's launches), and the detached backward with dW_rec, next to the
+    feedforward forward of the same shape."""
+    import torch
+
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif
+    B, T, N = I.shape
+    g = np.random.default_rng(11)
+    W_rec = torch.as_tensor((g.standard_normal((N, N)) * 0.5 / np.sqrt(N)).astype(np.float32), device="cuda")
+    f = alif.forward_recurrent(I, P, w.dt, w.arp, W_rec)
+    ws = f["workspace"]
+    torch.cuda.synchronize()
+
+    def fwd():
+        return alif.forward_recurrent(I, P, w.dt, w.arp, W_rec, workspace=ws)
+
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f = fwd()
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) / steps * 1e3
+    spikes = int(f["spikes"].sum().item())
+    graph_ms = None
+    try:
+        cg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(cg):
+            fg = fwd()
+        cg.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            cg.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) / steps * 1e3
+        assert torch.equal(fg["spikes"], f["spikes"]), "graph replay differs from the eager run"
+        del cg, fg
+    except Exception as e:   # report, keep the eager numbers
+        log(f"[bench] recurrent graph capture failed: {e}")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = alif.backward_recurrent(f, I, P, grad_spikes=gS)
+    torch.cuda.synchronize()
+    bwd = (time.perf_counter() - t0) / steps * 1e3
+    del out
+    ff = alif.forward(I, P, w.dt, w.arp, save=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ff = alif.forward(I, P, w.dt, w.arp, save=True)
+    torch.cuda.synchronize()
+    ff_ms = (time.perf_counter() - t0) / steps * 1e3
+    NB = (T + 39) // 40
+    return {"workload": f"fine-DT shape as a recurrent network: {B} x {N} neurons, T {T}, T_R 40 ({NB} blocks in "
+                        "sequence), OU current + W_rec S[t - T_R], W_rec ~ N(0, 0.25 / N), FP32 GEMMs",
+            "forward_eager_ms": eager, "forward_graph_ms": graph_ms, "backward_ms": bwd,
+            "feedforward_forward_ms": ff_ms, "spikes": spikes,
+            "value": B * N * T / ((graph_ms or eager) + bwd) * 1e3, "unit": "neuron-steps/s (fwd + bwd)"}
+
+
 def cpu_baseline(w, cpu_seconds, threads):
     """FP64 oracle fwd + bwd over the whole workload (every (batch, neuron) row, all
     T steps), repeated in whole passes until `cpu_seconds` of CPU time (summed
@@ -454,6 +518,7 @@ def main():
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--no-layers", action="store_true",
                     help="skip the three-layer and SHD-shaped training legs")
+    ap.add_argument("--no-recurrent", action="store_true", help="skip the recurrent-network leg")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the block-vs-sequential speedup sweep over T, T_R, layers and width")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -564,6 +629,14 @@ def main():
         seq["per_step_launch_fwd_ms"] = (time.perf_counter() - t0) * 1e3
         del car, sp
 
+    recurrent = None
+    if not args.no_recurrent:
+        log("[bench] recurrent network on the fine-DT shape")
+        recurrent = recurrent_leg(w, I, P, gS)
+        log(f"[bench] recurrent: forward {recurrent['forward_eager_ms']:.2f} ms eager, "
+            f"{recurrent['forward_graph_ms']} ms graph; backward {recurrent['backward_ms']:.2f} ms")
+        torch.cuda.empty_cache()
+
     layers = None
     if not args.no_layers:
         log("[bench] three-layer BF16 training step")
@@ -629,6 +702,7 @@ def main():
         "speedup_vs_sequential": (value / seq["value"]) if seq else None,
         "cpu_baseline": cpu,
         "layers": layers,
+        "recurrent": recurrent,
         "speedup_sweep": sweep,
         "serving": serve,
     }

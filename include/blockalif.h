@@ -261,12 +261,13 @@ int alif_backward(const alif_desc *desc, const alif_params *prm,
  * Recurrent layer: Eq. 3's input current with the recurrent term
  * sum_j W_rec[i][j] S_j[t - D] and transmission delay D = T_R (Section 2), which
  * Prop. 3 turns into block n + 1 receiving W_rec times the spikes of block n.
- * The blocks run one after another: per block one MFMA GEMM adds the recurrent
- * current of the block to `current`, then the block kernel runs that block from
- * the previous block's FP64 carry. No initial or final state: the run starts
- * from rest with no earlier spike.
+ * The blocks run one after another: per block, an event-driven kernel adds the
+ * recurrent current (the columns of W_rec of the neurons that spiked in the
+ * previous block, summed in FP32 in increasing neuron order) to `current`,
+ * then the block kernel runs that block from the previous block's FP64 carry.
+ * No initial or final state: the run starts from rest with no earlier spike.
  *   desc, prm   as alif_forward; desc->algo must be ALIF_ALGO_BLOCKS;
- *               desc->gemm_precision applies to both GEMMs
+ *               desc->gemm_precision applies to the feedforward GEMM
  *   input, W    as alif_forward (current input: float [B][T][N]; spike input:
  *               spikes [B][T][n_in] and W [N][n_in])
  *   W_rec       device float [N][N]

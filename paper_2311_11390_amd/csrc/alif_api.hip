@@ -463,10 +463,11 @@ int spike_gemm_kind(int sdt) {
 }
 
 // Forward scratch: the spikes of every block, block-major [NB][B][T_R][N] (each
-// block 256-byte aligned, the A operand of the next block's recurrent GEMM),
-// then two FP64 carry states [B][N] (v, a) and their int32 spike steps.
+// block 256-byte aligned; the next block's recurrent current reads them), then
+// two FP64 carry states [B][N] (v, a) and their int32 spike steps, then W_rec
+// transposed.
 struct RecLayout {
-    size_t blk, spikes, state, total;
+    size_t blk, spikes, state, wt, total;
 };
 RecLayout rec_layout(const alif_desc *d, const Prob &p) {
     RecLayout L{};
@@ -474,7 +475,8 @@ RecLayout rec_layout(const alif_desc *d, const Prob &p) {
     L.blk = align256((size_t)p.B * p.TR * p.N * sb);
     L.spikes = L.blk * p.NB;
     L.state = align256((size_t)p.B * p.N * 8) * 4 + align256((size_t)p.B * p.N * 4) * 2;
-    const size_t fwd = L.spikes + L.state;
+    L.wt = align256((size_t)p.N * p.N * 4);
+    const size_t fwd = L.spikes + L.state + L.wt;
     // weight gradient: the spikes shifted by T_R steps, then the GEMM's partial sums
     const size_t wg = align256((size_t)p.B * p.T * p.N * sb) + gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.N);
     L.total = fwd > wg ? fwd : wg;
@@ -532,6 +534,9 @@ int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm, const 
     double *sv[2] = {(double *)stb, (double *)(stb + s8)};
     double *sa[2] = {(double *)(stb + 2 * s8), (double *)(stb + 3 * s8)};
     int32_t *sts[2] = {(int32_t *)(stb + 4 * s8), (int32_t *)(stb + 4 * s8 + s4)};
+    float *wrt = (float *)(stb + L.state);
+    e = launch_transpose(p.N, W_rec, wrt, st);
+    if (e != hipSuccess) return hip_fail(e, "W_rec transpose launch");
     const int nwg = block_neurons_per_wg(block_config(p.TR).seg);
     const size_t TN = (size_t)p.T * p.N, TRN = (size_t)p.TR * p.N;
     const int sb = spike_elem_bytes(desc->spike_dtype);
@@ -539,11 +544,9 @@ int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm, const 
         const int rows = p.T - n * p.TR < p.TR ? p.T - n * p.TR : p.TR;
         float *cur_n = current + n * TRN;
         if (n > 0) {   // block n's recurrent current from the spikes of block n - 1
-            GemmIn s;
-            s.kind = spike_gemm_kind(desc->spike_dtype);
-            s.ptr = sblk + (size_t)(n - 1) * L.blk;
-            e = gemm_recurrent_block(p.B, p.TR, rows, p.N, (long long)TN, s, W_rec, cur_n, cur_n, bf16, st);
-            if (e != hipSuccess) return hip_fail(e, "recurrent-current GEMM");
+            e = launch_recurrent_events(p.B, p.TR, rows, p.N, (long long)TN, sb, sblk + (size_t)(n - 1) * L.blk,
+                                        wrt, cur_n, st);
+            if (e != hipSuccess) return hip_fail(e, "recurrent current launch");
         }
         FwdArgs a{};
         a.B = p.B; a.T = rows; a.N = p.N; a.TR = p.TR; a.NB = 1;

@@ -125,6 +125,76 @@ __global__ void k_shift_time(size_t total, int T, int N, int D, const E *in, E *
     }
 }
 
+// Recurrent current of one block from the previous block's spikes, event-driven
+// (a neuron spikes at most once per block, so the spike rows are sparse):
+//   C[b][k][i] += sum over j with S[b][k][j] != 0 of W_recT[j][i]
+// for b < B, k < rows. One workgroup per (b, k) row: the active j are compacted
+// in increasing order (wave ballots and their prefix counts), then every thread
+// sums its outputs i over them in that order, in FP32, reading W_recT rows
+// (coalesced over i). S: [B][TR][N] of element type E; C: rows of a [B][T][N]
+// tensor starting at the block (batch stride bstride).
+template <typename E>
+__global__ __launch_bounds__(256) void k_recurrent_events(int TR, int rows, int N, long long bstride,
+                                                          const E *S, const float *WrecT, float *C) {
+    extern __shared__ int act[];              // [N] active presynaptic indices
+    __shared__ int wave_cnt[4];
+    const int row = blockIdx.x, b = row / rows, k = row - b * rows;
+    const E *srow = S + ((size_t)b * TR + k) * N;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int base = 0;
+    for (int j0 = 0; j0 < N; j0 += 256) {
+        const int j = j0 + tid;
+        const bool on = j < N && srow[j] != E(0);
+        const unsigned long long m = __ballot(on);
+        if (lane == 0) wave_cnt[wave] = __popcll(m);
+        __syncthreads();
+        int off = base;
+        for (int w = 0; w < wave; w++) off += wave_cnt[w];
+        if (on) act[off + __popcll(m & ((1ull << lane) - 1ull))] = j;
+        base += wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
+        __syncthreads();
+    }
+    if (base == 0) return;
+    float *crow = C + (size_t)b * bstride + (size_t)k * N;
+    for (int i = tid; i < N; i += 256) {
+        float s = 0.0f;
+        for (int e = 0; e < base; e++) s += WrecT[(size_t)act[e] * N + i];
+        crow[i] += s;
+    }
+}
+
+// out[j][i] = in[i][j] for an N x N matrix
+__global__ void k_transpose(int N, const float *in, float *out) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)N * N) return;
+    const int j = (int)(e / N), i = (int)(e - (size_t)j * N);
+    out[e] = in[(size_t)i * N + j];
+}
+
+hipError_t launch_recurrent_events(int B, int TR, int rows, int N, long long bstride, int elem, const void *S,
+                                   const float *WrecT, float *C, hipStream_t st) {
+    if (B == 0 || rows == 0 || N == 0) return hipSuccess;
+    const dim3 grid((unsigned)(B * rows)), blk(256);
+    const size_t sm = (size_t)N * sizeof(int);
+    if (elem == 1)
+        hipLaunchKernelGGL(k_recurrent_events<uint8_t>, grid, blk, sm, st, TR, rows, N, bstride,
+                           static_cast<const uint8_t *>(S), WrecT, C);
+    else if (elem == 2)
+        hipLaunchKernelGGL(k_recurrent_events<uint16_t>, grid, blk, sm, st, TR, rows, N, bstride,
+                           static_cast<const uint16_t *>(S), WrecT, C);
+    else
+        hipLaunchKernelGGL(k_recurrent_events<uint32_t>, grid, blk, sm, st, TR, rows, N, bstride,
+                           static_cast<const uint32_t *>(S), WrecT, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(int N, const float *in, float *out, hipStream_t st) {
+    const size_t total = (size_t)N * N;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, N, in, out);
+    return hipGetLastError();
+}
+
 static unsigned grid_for(size_t total) {
     const size_t g = (total + 255) / 256;
     return (unsigned)(g < ((size_t)1 << 20) ? (g ? g : 1) : ((size_t)1 << 20));

@@ -41,19 +41,7 @@ struct GemmArgs {
     const float *bias;
     int splits;        // split of K over blockIdx.z; > 1 writes partials to C_part
     float *C_part;     // [splits][M][N]
-    // Grouped output rows (c_rpb = 0: plain): row m of C sits at
-    // (m / c_rpb) * c_bstride + (m % c_rpb) * ldc, and rows with m % c_rpb >= c_rvalid
-    // are not written. Cadd (nullable, laid out like C) is added to the result.
-    long long c_rpb, c_bstride;
-    int c_rvalid;
-    const float *Cadd;
 };
 hipError_t gemm_launch(const GemmArgs &g, bool bf16, hipStream_t st);
-
-// Recurrent current of one block: C[b][k][:] = Cadd[b][k][:] + S[b][k][:] . Wrec^T for
-// b < B, k < rows (S contiguous [B][TR][N] of spike kind s_kind; C and Cadd rows
-// of a [B][T][N] tensor starting at the block, batch stride T N).
-hipError_t gemm_recurrent_block(int B, int TR, int rows, int N, long long bstride, GemmIn S,
-                                const float *Wrec, const float *Cadd, float *C, bool bf16, hipStream_t st);
 
 }  // namespace alif

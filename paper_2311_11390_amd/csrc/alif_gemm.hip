@@ -23,13 +23,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int GBM = 128, GBN = 128;
 
-// element offset of output row m (grouped rows, see GemmArgs), or -1 if not written
-__device__ __forceinline__ long long out_row(const GemmArgs &g, long long m, long long ldc) {
-    if (g.c_rpb == 0) return m * ldc;
-    const long long grp = m / g.c_rpb, k = m - grp * g.c_rpb;
-    return k < g.c_rvalid ? grp * g.c_bstride + k * ldc : -1;
-}
-
 __device__ __forceinline__ float ld_elem(const void *p, int dt, long long i) {
     if (dt == 0) return static_cast<const float *>(p)[i];
     if (dt == 1) return (float)static_cast<const uint8_t *>(p)[i];
@@ -111,22 +104,18 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         __syncthreads();
     }
     // epilogue: lane holds rows 4 * (lane / 16) + r of column lane % 16 of each 16 x 16 block
-    const bool part = g.splits > 1;
-    float *out = part ? g.C_part + (size_t)z * g.M * g.N : g.C;
-    const long long ldc = part ? g.N : g.ldc;
+    float *out = g.splits > 1 ? g.C_part + (size_t)z * g.M * g.N : g.C;
+    const long long ldc = g.splits > 1 ? g.N : g.ldc;
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int n = n0 + wn * 64 + j * 16 + (lane & 15);
-        const float bias = (g.bias && !part && n < g.N) ? g.bias[n] : 0.0f;
+        const float bias = (g.bias && g.splits == 1 && n < g.N) ? g.bias[n] : 0.0f;
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const long long m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
-                if (m >= g.M || n >= g.N) continue;
-                if (part) { out[m * ldc + n] = acc[i][j][r]; continue; }
-                const long long o = out_row(g, m, ldc);
-                if (o >= 0) out[o + n] = acc[i][j][r] + bias + (g.Cadd ? g.Cadd[o + n] : 0.0f);
+                if (m < g.M && n < g.N) out[m * ldc + n] = acc[i][j][r] + bias;
             }
     }
 }
@@ -514,10 +503,7 @@ __global__ __launch_bounds__(Tile<BF16>::THREADS) void k_gemm_tiled(GemmArgs g, 
 #pragma unroll
             for (int rr = 0; rr < 4; rr++) {
                 const long long m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + rr;
-                if (m >= g.M || n >= g.N) continue;
-                if (split) { out[m * ldc + n] = acc[i][j][rr]; continue; }
-                const long long o = out_row(g, m, ldc);
-                if (o >= 0) out[o + n] = acc[i][j][rr] + bias + (g.Cadd ? g.Cadd[o + n] : 0.0f);
+                if (m < g.M && n < g.N) out[m * ldc + n] = acc[i][j][rr] + bias;
             }
     }
 }
@@ -594,7 +580,6 @@ __global__ void k_split_reduce(long long MN, int N, int splits, const float *P, 
 
 hipError_t gemm_launch(const GemmArgs &g, bool bf16, hipStream_t st) {
     if (g.M == 0 || g.N == 0) return hipSuccess;
-    if (g.splits > 1 && (g.c_rpb != 0 || g.Cadd)) return hipErrorInvalidValue;   // partial sums are plain
     if (tiled_ok(g, bf16)) {
         int splits = 1;
         hipError_t e = bf16 ? tiled_launch<true>(g, st, &splits) : tiled_launch<false>(g, st, &splits);
@@ -627,18 +612,6 @@ hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, 
     g.A = x.ptr; g.a_dt = dt_of(x.kind); g.lda = K; g.a_kc = 1;
     g.B = W; g.b_dt = 0; g.ldb = K; g.b_kc = 1;
     g.C = out; g.ldc = N; g.bias = bias; g.splits = 1;
-    return gemm_launch(g, bf16, st);
-}
-
-hipError_t gemm_recurrent_block(int B, int TR, int rows, int N, long long bstride, GemmIn S,
-                                const float *Wrec, const float *Cadd, float *C, bool bf16, hipStream_t st) {
-    // C[m][n] = sum_j S[m][j] Wrec[n][j], m = b TR + k over the block's rows
-    GemmArgs g{};
-    g.M = (long long)B * TR; g.N = N; g.K = N;
-    g.A = S.ptr; g.a_dt = dt_of(S.kind); g.lda = N; g.a_kc = 1;
-    g.B = Wrec; g.b_dt = 0; g.ldb = N; g.b_kc = 1;
-    g.C = C; g.ldc = N; g.bias = nullptr; g.splits = 1;
-    g.c_rpb = TR; g.c_bstride = bstride; g.c_rvalid = rows; g.Cadd = Cadd;
     return gemm_launch(g, bf16, st);
 }
 

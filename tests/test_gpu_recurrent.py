@@ -44,7 +44,7 @@ def _case(seed, B, T, N, TR, dt, spike_input=False, n_in=90, prec=0, gain=1.0):
     f = alif.forward_recurrent(inp, P, dt, 2.0, torch.as_tensor(W_rec, device="cuda"), Wt, gemm_precision=prec,
                                want_v=True, want_theta=True)
     torch.cuda.synchronize()
-    Wr = _bf16_round(W_rec) if prec else W_rec.astype(np.float64)
+    Wr = W_rec.astype(np.float64)   # the recurrent current is summed in FP32 whatever the GEMM precision
     orc, excused = teacher_forced_recurrent(np_(f["spikes"]), Iff, Wr, prm.tau_mem, prm.tau_adapt, prm.d,
                                             prm.theta0, dt, 2.0)
     return f, orc, excused, prm, P, inp, Wt
