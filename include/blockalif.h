@@ -259,8 +259,9 @@ int alif_backward(const alif_desc *desc, const alif_params *prm,
 
 /*
  * Recurrent layer: Eq. 3's input current with the recurrent term
- * sum_j W_rec[i][j] S_j[t - D] and transmission delay D = T_R (Section 2), which
- * Prop. 3 turns into block n + 1 receiving W_rec times the spikes of block n.
+ * sum_j W_rec[i][j] S_j[t - D] and transmission delay D (Section 2 takes
+ * D = T_R, which Prop. 3 turns into block n + 1 receiving W_rec times the
+ * spikes of block n; any D >= T_R keeps the source in a finished block).
  * The blocks run one after another: per block, an event-driven kernel adds the
  * recurrent current (the columns of W_rec of the neurons that spiked in the
  * previous block, summed in FP32 in increasing neuron order) to `current`,
@@ -271,6 +272,7 @@ int alif_backward(const alif_desc *desc, const alif_params *prm,
  *   input, W    as alif_forward (current input: float [B][T][N]; spike input:
  *               spikes [B][T][n_in] and W [N][n_in])
  *   W_rec       device float [N][N]
+ *   delay       D in steps; 0 means T_R; D < T_R is rejected (ALIF_EINVAL)
  *   current     device float [B][T][N], required: receives the whole current,
  *               b + W x + W_rec S[t - T_R] for spike input, input + W_rec S[t - T_R]
  *               for current input (the bias then added in-kernel, as
@@ -280,18 +282,19 @@ int alif_backward(const alif_desc *desc, const alif_params *prm,
  *               ordinary backward applies.
  *   spikes, v, theta, carries   as alif_forward
  *   workspace   device scratch of alif_recurrent_workspace_bytes() bytes
- * alif_recurrent_weight_grad: grad_W_rec[i][j] = sum over b, t >= T_R of
- * grad_current[b][t][i] S[b][t - T_R][j] (device float [N][N]), from the spikes
- * alif_forward_recurrent wrote (desc->spike_dtype) and the same workspace size.
+ * alif_recurrent_weight_grad: grad_W_rec[i][j] = sum over b, t >= D of
+ * grad_current[b][t][i] S[b][t - D][j] (device float [N][N]), from the spikes
+ * alif_forward_recurrent wrote (desc->spike_dtype), the same delay and the same
+ * workspace size.
  */
 int alif_recurrent_workspace_bytes(const alif_desc *desc, size_t *bytes);
 int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm,
                            const void *input, const float *W, const float *W_rec,
-                           float *current, void *spikes, float *v, float *theta,
-                           void *carries, void *workspace, void *stream);
-int alif_recurrent_weight_grad(const alif_desc *desc, const float *grad_current,
-                               const void *spikes, float *grad_W_rec,
-                               void *workspace, void *stream);
+                           int32_t delay, float *current, void *spikes, float *v,
+                           float *theta, void *carries, void *workspace, void *stream);
+int alif_recurrent_weight_grad(const alif_desc *desc, int32_t delay,
+                               const float *grad_current, const void *spikes,
+                               float *grad_W_rec, void *workspace, void *stream);
 
 /*
  * Leaky non-spiking readout (supplementary "Readout neurons"): the membrane of

@@ -70,9 +70,9 @@ _SIGNATURES = {
     "alif_decay_tables": (c_int, [POINTER(AlifDesc), POINTER(AlifParams), _P, _P, _P]),
     "alif_input_current": (c_int, [POINTER(AlifDesc), _P, _P, _P, _P, _P]),
     "alif_recurrent_workspace_bytes": (c_int, [POINTER(AlifDesc), POINTER(c_size_t)]),
-    "alif_forward_recurrent": (c_int, [POINTER(AlifDesc), POINTER(AlifParams), _P, _P, _P, _P, _P, _P, _P,
-                                       _P, _P, _P]),
-    "alif_recurrent_weight_grad": (c_int, [POINTER(AlifDesc), _P, _P, _P, _P, _P]),
+    "alif_forward_recurrent": (c_int, [POINTER(AlifDesc), POINTER(AlifParams), _P, _P, _P, c_int32, _P, _P, _P,
+                                       _P, _P, _P, _P]),
+    "alif_recurrent_weight_grad": (c_int, [POINTER(AlifDesc), c_int32, _P, _P, _P, _P, _P]),
     "alif_weight_grad_workspace_bytes": (c_int, [POINTER(AlifDesc), POINTER(c_size_t)]),
     "alif_weight_grad": (c_int, [POINTER(AlifDesc), _P, _P, _P, _P, _P]),
     "alif_input_grad": (c_int, [POINTER(AlifDesc), _P, _P, _P, _P]),

@@ -168,9 +168,9 @@ def backward(fwd: dict, inp: torch.Tensor, params: Params, W: torch.Tensor | Non
 def forward_recurrent(inp: torch.Tensor, params: Params, dt: float, arp: float, W_rec: torch.Tensor,
                       W: torch.Tensor | None = None, *, gemm_precision=L.GEMM_FP32, spike_dtype=L.SPIKES_U8,
                       want_v=False, want_theta=False, save=True, slope=10.0, surrogate=L.SG_FAST_SIGMOID,
-                      workspace=None) -> dict:
+                      delay=0, workspace=None) -> dict:
     """One recurrent ALIF layer (alif_forward_recurrent): Eq. 3 with the recurrent
-    current W_rec S[t - T_R]. ``inp`` as in ``forward``. Returns ``spikes``,
+    current W_rec S[t - D], D = ``delay`` steps (0: T_R). ``inp`` as in ``forward``. Returns ``spikes``,
     optional ``v``/``theta``, ``current`` (the whole current, which the backward
     differentiates), ``carries``, ``desc`` and the ``workspace`` (reusable by
     ``recurrent_weight_grad``)."""
@@ -197,18 +197,18 @@ def forward_recurrent(inp: torch.Tensor, params: Params, dt: float, arp: float, 
         workspace = torch.empty(max(1, n.value), dtype=torch.uint8, device=dev)
     cp = params.c()
     L.check(L.load().alif_forward_recurrent(ctypes.byref(desc), ctypes.byref(cp), _p(inp), _p(W), _p(W_rec),
-                                            _p(current), _p(spikes), _p(v), _p(th), _p(carries), _p(workspace),
-                                            _stream(dev)))
+                                            int(delay), _p(current), _p(spikes), _p(v), _p(th), _p(carries),
+                                            _p(workspace), _stream(dev)))
     return {"spikes": spikes, "v": v, "theta": th, "current": current, "carries": carries, "desc": desc,
-            "workspace": workspace, "recurrent": True, "current_input": W is None}
+            "workspace": workspace, "recurrent": True, "current_input": W is None, "delay": int(delay)}
 
 
 def recurrent_weight_grad(fwd: dict, grad_current: torch.Tensor) -> torch.Tensor:
-    """grad_W_rec [N][N] = sum_{b,t} grad_current[b][t]^T S[b][t - T_R] (alif_recurrent_weight_grad)."""
+    """grad_W_rec [N][N] = sum_{b,t} grad_current[b][t]^T S[b][t - D] (alif_recurrent_weight_grad)."""
     desc = fwd["desc"]
     N = desc.n_neurons
     out = torch.empty(N, N, dtype=torch.float32, device=grad_current.device)
-    L.check(L.load().alif_recurrent_weight_grad(ctypes.byref(desc), _p(grad_current.contiguous()),
+    L.check(L.load().alif_recurrent_weight_grad(ctypes.byref(desc), fwd["delay"], _p(grad_current.contiguous()),
                                                 _p(fwd["spikes"]), _p(out), _p(fwd["workspace"]),
                                                 _stream(grad_current.device)))
     return out

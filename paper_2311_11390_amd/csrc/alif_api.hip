@@ -495,13 +495,15 @@ int alif_recurrent_workspace_bytes(const alif_desc *desc, size_t *bytes) {
 }
 
 int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm, const void *input, const float *W,
-                           const float *W_rec, float *current, void *spikes, float *v, float *theta,
-                           void *carries, void *workspace, void *stream) {
+                           const float *W_rec, int32_t delay, float *current, void *spikes, float *v,
+                           float *theta, void *carries, void *workspace, void *stream) {
     Prob p;
     int rc = check_desc(desc, &p);
     if (rc) return rc;
     if ((rc = check_params(prm))) return rc;
     if (desc->algo != ALIF_ALGO_BLOCKS) return fail(ALIF_EUNSUPPORTED, "the recurrent layer runs the blocks algorithm");
+    const int D = delay == 0 ? p.TR : delay;
+    if (D < p.TR) return fail(ALIF_EINVAL, "recurrent delay %d < T_R = %d", D, p.TR);
     const size_t BTN = (size_t)p.B * p.T * p.N;
     if (BTN == 0) return ALIF_OK;
     if (!input || !W_rec || !current || !spikes || !workspace)
@@ -543,9 +545,9 @@ int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm, const 
     for (int n = 0; n < p.NB; n++) {
         const int rows = p.T - n * p.TR < p.TR ? p.T - n * p.TR : p.TR;
         float *cur_n = current + n * TRN;
-        if (n > 0) {   // block n's recurrent current from the spikes of block n - 1
-            e = launch_recurrent_events(p.B, p.TR, rows, p.N, (long long)TN, sb, sblk + (size_t)(n - 1) * L.blk,
-                                        wrt, cur_n, st);
+        if ((n + 1) * p.TR > D) {   // block n's recurrent current from spikes D steps back
+            e = launch_recurrent_events(p.B, p.TR, rows, p.N, (long long)TN, n * p.TR, D, sb, sblk, L.blk, wrt,
+                                        cur_n, st);
             if (e != hipSuccess) return hip_fail(e, "recurrent current launch");
         }
         FwdArgs a{};
@@ -575,18 +577,20 @@ int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm, const 
     return ALIF_OK;
 }
 
-int alif_recurrent_weight_grad(const alif_desc *desc, const float *grad_current, const void *spikes,
-                               float *grad_W_rec, void *workspace, void *stream) {
+int alif_recurrent_weight_grad(const alif_desc *desc, int32_t delay, const float *grad_current,
+                               const void *spikes, float *grad_W_rec, void *workspace, void *stream) {
     Prob p;
     int rc = check_desc(desc, &p);
     if (rc) return rc;
+    const int D = delay == 0 ? p.TR : delay;
+    if (D < p.TR) return fail(ALIF_EINVAL, "recurrent delay %d < T_R = %d", D, p.TR);
     if (!grad_current || !spikes || !grad_W_rec || !workspace)
         return fail(ALIF_EINVAL, "grad_current, spikes, grad_W_rec and workspace are required");
     hipStream_t st = (hipStream_t)stream;
     const int sb = spike_elem_bytes(desc->spike_dtype);
     const size_t shb = align256((size_t)p.B * p.T * p.N * sb);
     char *shifted = (char *)workspace;
-    hipError_t e = launch_shift_time(p.B, p.T, p.N, p.TR, sb, spikes, shifted, st);
+    hipError_t e = launch_shift_time(p.B, p.T, p.N, D, sb, spikes, shifted, st);
     if (e != hipSuccess) return hip_fail(e, "spike shift launch");
     GemmIn x;
     x.kind = spike_gemm_kind(desc->spike_dtype);

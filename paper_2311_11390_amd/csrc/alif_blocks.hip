@@ -125,21 +125,27 @@ __global__ void k_shift_time(size_t total, int T, int N, int D, const E *in, E *
     }
 }
 
-// Recurrent current of one block from the previous block's spikes, event-driven
-// (a neuron spikes at most once per block, so the spike rows are sparse):
-//   C[b][k][i] += sum over j with S[b][k][j] != 0 of W_recT[j][i]
-// for b < B, k < rows. One workgroup per (b, k) row: the active j are compacted
-// in increasing order (wave ballots and their prefix counts), then every thread
-// sums its outputs i over them in that order, in FP32, reading W_recT rows
-// (coalesced over i). S: [B][TR][N] of element type E; C: rows of a [B][T][N]
-// tensor starting at the block (batch stride bstride).
+// Recurrent current of one block from earlier spikes, event-driven (a neuron
+// spikes at most once per block, so the spike rows are sparse):
+//   C[b][k][i] += sum over j with S[b][t - D][j] != 0 of W_recT[j][i],  t = t0 + k,
+// for b < B, k < rows; nothing where t - D < 0. The spikes come from the
+// block-major staging copy (block m at byte offset m * blk_bytes, [B][TR][N] of
+// element type E); D >= T_R keeps the source in a finished block. One workgroup
+// per (b, k) row: the active j are compacted in increasing order (wave ballots
+// and their prefix counts), then every thread sums its outputs i over them in
+// that order, in FP32, reading W_recT rows (coalesced over i). C: rows of a
+// [B][T][N] tensor starting at the block (batch stride bstride).
 template <typename E>
-__global__ __launch_bounds__(256) void k_recurrent_events(int TR, int rows, int N, long long bstride,
-                                                          const E *S, const float *WrecT, float *C) {
+__global__ __launch_bounds__(256) void k_recurrent_events(int TR, int rows, int N, long long bstride, int t0, int D,
+                                                          const char *blocks, size_t blk_bytes, const float *WrecT,
+                                                          float *C) {
     extern __shared__ int act[];              // [N] active presynaptic indices
     __shared__ int wave_cnt[4];
     const int row = blockIdx.x, b = row / rows, k = row - b * rows;
-    const E *srow = S + ((size_t)b * TR + k) * N;
+    const int u = t0 + k - D;                 // source step
+    if (u < 0) return;                        // uniform over the workgroup
+    const E *srow = reinterpret_cast<const E *>(blocks + (size_t)(u / TR) * blk_bytes) +
+                    ((size_t)b * TR + (u % TR)) * N;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int base = 0;
     for (int j0 = 0; j0 < N; j0 += 256) {
@@ -171,20 +177,22 @@ __global__ void k_transpose(int N, const float *in, float *out) {
     out[e] = in[(size_t)i * N + j];
 }
 
-hipError_t launch_recurrent_events(int B, int TR, int rows, int N, long long bstride, int elem, const void *S,
-                                   const float *WrecT, float *C, hipStream_t st) {
+hipError_t launch_recurrent_events(int B, int TR, int rows, int N, long long bstride, int t0, int D, int elem,
+                                   const void *blocks, size_t blk_bytes, const float *WrecT, float *C,
+                                   hipStream_t st) {
     if (B == 0 || rows == 0 || N == 0) return hipSuccess;
     const dim3 grid((unsigned)(B * rows)), blk(256);
     const size_t sm = (size_t)N * sizeof(int);
+    const char *bl = static_cast<const char *>(blocks);
     if (elem == 1)
-        hipLaunchKernelGGL(k_recurrent_events<uint8_t>, grid, blk, sm, st, TR, rows, N, bstride,
-                           static_cast<const uint8_t *>(S), WrecT, C);
+        hipLaunchKernelGGL(k_recurrent_events<uint8_t>, grid, blk, sm, st, TR, rows, N, bstride, t0, D, bl,
+                           blk_bytes, WrecT, C);
     else if (elem == 2)
-        hipLaunchKernelGGL(k_recurrent_events<uint16_t>, grid, blk, sm, st, TR, rows, N, bstride,
-                           static_cast<const uint16_t *>(S), WrecT, C);
+        hipLaunchKernelGGL(k_recurrent_events<uint16_t>, grid, blk, sm, st, TR, rows, N, bstride, t0, D, bl,
+                           blk_bytes, WrecT, C);
     else
-        hipLaunchKernelGGL(k_recurrent_events<uint32_t>, grid, blk, sm, st, TR, rows, N, bstride,
-                           static_cast<const uint32_t *>(S), WrecT, C);
+        hipLaunchKernelGGL(k_recurrent_events<uint32_t>, grid, blk, sm, st, TR, rows, N, bstride, t0, D, bl,
+                           blk_bytes, WrecT, C);
     return hipGetLastError();
 }
 

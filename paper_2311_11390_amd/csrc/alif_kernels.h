@@ -106,10 +106,12 @@ hipError_t launch_blocks_fwd(const FwdArgs &a, hipStream_t st);
 // spikes[b][n T_R + k][i] = blocks[n][b][k][i] (block n at byte offset n * blk_bytes), for n T_R + k < T
 hipError_t launch_blocks_to_bt(int B, int T, int N, int TR, int elem, const void *blocks, size_t blk_bytes,
                                void *spikes, hipStream_t st);
-// C[b][k][i] += sum_{j: S[b][k][j] != 0} WrecT[j][i] (b < B, k < rows; S [B][TR][N] of
-// `elem`-byte spikes; C rows of a [B][T][N] tensor at batch stride bstride)
-hipError_t launch_recurrent_events(int B, int TR, int rows, int N, long long bstride, int elem, const void *S,
-                                   const float *WrecT, float *C, hipStream_t st);
+// C[b][k][i] += sum_{j: S[b][t0 + k - D][j] != 0} WrecT[j][i] (b < B, k < rows; spikes from
+// the block-major staging [NB][B][TR][N] of `elem`-byte elements, block m at m * blk_bytes;
+// C rows of a [B][T][N] tensor at batch stride bstride; nothing where t0 + k < D)
+hipError_t launch_recurrent_events(int B, int TR, int rows, int N, long long bstride, int t0, int D, int elem,
+                                   const void *blocks, size_t blk_bytes, const float *WrecT, float *C,
+                                   hipStream_t st);
 // out[j][i] = in[i][j], N x N float
 hipError_t launch_transpose(int N, const float *in, float *out, hipStream_t st);
 // out[b][t][i] = in[b][t - D][i] for t >= D, else 0 (elements of `elem` bytes)

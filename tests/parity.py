@@ -51,7 +51,7 @@ def teacher_forced_forward(gpu_S, I, tau_m, tau_a, d, theta0, dt, arp, max_iter=
     raise ParityError("teacher forcing did not converge")
 
 
-def teacher_forced_recurrent(gpu_S, Iff, W_rec, tau_m, tau_a, d, theta0, dt, arp, max_iter=200):
+def teacher_forced_recurrent(gpu_S, Iff, W_rec, tau_m, tau_a, d, theta0, dt, arp, max_iter=200, D=None):
     """The recurrent oracle on Iff[B][T][N] (bias + feedforward current), with the
     GPU's decisions imposed where they differ from the oracle's within MARGIN of
     threshold. Neurons of one batch element are coupled through W_rec, so each
@@ -64,7 +64,7 @@ def teacher_forced_recurrent(gpu_S, Iff, W_rec, tau_m, tau_a, d, theta0, dt, arp
     force = np.full((B, T, N), -1, np.int8)
     excused = 0
     for _ in range(max_iter):
-        orc = oracle.alif_forward_recurrent(Iff, W_rec, tau_m, tau_a, d, theta0, dt, arp, force=force)
+        orc = oracle.alif_forward_recurrent(Iff, W_rec, tau_m, tau_a, d, theta0, dt, arp, force=force, D=D)
         mism = gpu_S != orc["S"]
         if not mism.any():
             return orc, excused

@@ -21,7 +21,7 @@ def _bf16_round(a):
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def _case(seed, B, T, N, TR, dt, spike_input=False, n_in=90, prec=0, gain=1.0):
+def _case(seed, B, T, N, TR, dt, spike_input=False, n_in=90, prec=0, gain=1.0, D=0):
     import torch
 
     from paper_2311_11390_amd import alif
@@ -42,11 +42,11 @@ def _case(seed, B, T, N, TR, dt, spike_input=False, n_in=90, prec=0, gain=1.0):
     log(f"[rec] seed={seed} B={B} T={T} N={N} T_R={TR} spike_input={spike_input} prec={prec}")
     P = to_dev(prm)
     f = alif.forward_recurrent(inp, P, dt, 2.0, torch.as_tensor(W_rec, device="cuda"), Wt, gemm_precision=prec,
-                               want_v=True, want_theta=True)
+                               want_v=True, want_theta=True, delay=D)
     torch.cuda.synchronize()
     Wr = W_rec.astype(np.float64)   # the recurrent current is summed in FP32 whatever the GEMM precision
     orc, excused = teacher_forced_recurrent(np_(f["spikes"]), Iff, Wr, prm.tau_mem, prm.tau_adapt, prm.d,
-                                            prm.theta0, dt, 2.0)
+                                            prm.theta0, dt, 2.0, D=D or None)
     return f, orc, excused, prm, P, inp, Wt
 
 
@@ -106,3 +106,24 @@ def test_recurrent_backward(TR, dt, spike_input):
         x = np_(inp).astype(np.float64)
         check_grad("grad_W", np_(out["grad_W"]), oracle.weight_grad(ob["gI"], x))
     log(f"    excused {excused}")
+
+
+@pytest.mark.parametrize("TR,dt,D", [(2, 1.0, 5), (5, 0.4, 10), (20, 0.1, 27)])
+def test_recurrent_longer_delay(TR, dt, D):
+    """Delays D > T_R (the source step t - D still lies in a finished block):
+    forward and the detached backward's dW_rec."""
+    import torch
+
+    from paper_2311_11390_amd import alif
+    B, N = 2, 67
+    T = 11 * TR + 3
+    f, orc, excused, prm, P, inp, Wt = _case(990 + D, B, T, N, TR, dt, D=D)
+    dV = np.abs(np_(f["v"]) - orc["V"]).max()
+    assert np_(f["spikes"]).sum() > 50 and dV <= TRACE_TOL
+    gS = rng(991 + D).standard_normal((B, T, N)).astype(np.float32)
+    out = alif.backward_recurrent(f, inp, P, None, grad_spikes=torch.as_tensor(gS, device="cuda"))
+    torch.cuda.synchronize()
+    ob = oracle.alif_backward(orc["ff"], dt, 10.0, gS=gS)
+    check_grad("grad_current", np_(out["grad_current"]), ob["gI"])
+    check_grad("grad_W_rec", np_(out["grad_W_rec"]), oracle.recurrent_weight_grad(ob["gI"], orc["S"], D))
+    log(f"    D={D}: excused {excused}, max|dV| {dV:.1e}")

@@ -37,8 +37,8 @@ def test_zero_recurrent_weights_is_feedforward():
     np.testing.assert_array_equal(r["Itot"], Iff)
 
 
-@pytest.mark.parametrize("TR,dt", [(2, 1.0), (5, 0.4)])
-def test_driven_by_another_neuron_is_a_delayed_iir_filter(TR, dt):
+@pytest.mark.parametrize("TR,dt,D", [(2, 1.0, 2), (5, 0.4, 5), (2, 1.0, 7), (5, 0.4, 10)])
+def test_driven_by_another_neuron_is_a_delayed_iir_filter(TR, dt, D):
     """Neuron 0 fires periodically on a constant current; neuron 1 has no other
     input and W_rec[1][0] = w < theta0, so it never fires and its membrane is the
     IIR filter (1 - beta) / (1 - beta z^-1) of w S_0[t - D]."""
@@ -48,11 +48,11 @@ def test_driven_by_another_neuron_is_a_delayed_iir_filter(TR, dt):
     Iff[0, :, 0] = 2.5
     W_rec = np.array([[0.0, 0.0], [w, 0.0]])
     tm = np.array([10.0, 7.0])
-    r = oracle.alif_forward_recurrent(Iff, W_rec, tm, [100.0, 100.0], [0.0, 0.0], [1.0, 1.0], dt, TR * dt)
+    r = oracle.alif_forward_recurrent(Iff, W_rec, tm, [100.0, 100.0], [0.0, 0.0], [1.0, 1.0], dt, TR * dt, D=D)
     S0 = r["S"][0, :, 0].astype(np.float64)
     assert S0.sum() > 10 and r["S"][0, :, 1].sum() == 0
     drive = np.zeros(T)
-    drive[TR:] = w * S0[:T - TR]
+    drive[D:] = w * S0[:T - D]
     np.testing.assert_array_equal(r["Itot"][0, :, 1], drive)
     beta = math.exp(-dt / tm[1])
     np.testing.assert_allclose(r["V"][0, :, 1], lfilter([1.0 - beta], [1.0, -beta], drive), rtol=0, atol=1e-13)
