@@ -103,28 +103,6 @@ hipError_t launch_blocks_bwd(const BwdArgs &a, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // layout moves of the recurrent layer (grid-stride loops over the output)
 // ---------------------------------------------------------------------------
-template <typename E>
-__global__ void k_blocks_to_bt(size_t total, int T, int N, int TR, const char *blocks, size_t blk_bytes,
-                               E *out) {
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const size_t bt = e / N;
-        const int i = (int)(e - bt * N);
-        const int t = (int)(bt % T);
-        const size_t b = bt / T;
-        const int n = t / TR, k = t - n * TR;
-        const E *src = reinterpret_cast<const E *>(blocks + (size_t)n * blk_bytes);
-        out[e] = src[(b * TR + k) * N + i];
-    }
-}
-
-template <typename E>
-__global__ void k_shift_time(size_t total, int T, int N, int D, const E *in, E *out) {
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int t = (int)((e / N) % T);
-        out[e] = t >= D ? in[e - (size_t)D * N] : E(0);
-    }
-}
-
 // Recurrent current of one block from earlier spikes, event-driven (a neuron
 // spikes at most once per block, so the spike rows are sparse):
 //   C[b][k][i] += sum over j with S[b][t - D][j] != 0 of W_recT[j][i],  t = t0 + k,
@@ -203,40 +181,78 @@ hipError_t launch_transpose(int N, const float *in, float *out, hipStream_t st) 
     return hipGetLastError();
 }
 
+// Both move whole neuron rows (N elements, `rb` bytes) in chunks of type C (16,
+// 4 or 1 bytes, the widest that divides the row and keeps every row aligned):
+// one index computation per chunk.
+template <typename C>
+__global__ void k_blocks_to_bt(size_t chunks, int cpr, int T, int TR, const char *blocks, size_t blk_bytes,
+                               size_t rb, C *out) {
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < chunks; c += (size_t)gridDim.x * blockDim.x) {
+        const size_t row = c / cpr;                     // output row (b, t)
+        const int w = (int)(c - row * cpr);
+        const size_t b = row / T;
+        const int t = (int)(row - b * T);
+        const int n = t / TR, k = t - n * TR;
+        const C *src = reinterpret_cast<const C *>(blocks + (size_t)n * blk_bytes + (b * TR + k) * rb);
+        out[c] = src[w];
+    }
+}
+
+template <typename C>
+__global__ void k_shift_time(size_t chunks, int cpr, int T, int D, const C *in, C *out) {
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < chunks; c += (size_t)gridDim.x * blockDim.x) {
+        const size_t row = c / cpr;
+        const int t = (int)(row % T);
+        out[c] = t >= D ? in[c - (size_t)D * cpr] : C{};
+    }
+}
+
 static unsigned grid_for(size_t total) {
     const size_t g = (total + 255) / 256;
     return (unsigned)(g < ((size_t)1 << 20) ? (g ? g : 1) : ((size_t)1 << 20));
 }
 
+// widest chunk (16, 4 or 1 bytes) dividing the row bytes and every given address
+static int chunk_bytes(size_t rb, const void *a, const void *b, size_t extra_align) {
+    const uintptr_t m = reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | extra_align | rb;
+    return (m & 15) == 0 ? 16 : ((m & 3) == 0 ? 4 : 1);
+}
+
 hipError_t launch_blocks_to_bt(int B, int T, int N, int TR, int elem, const void *blocks, size_t blk_bytes,
                                void *spikes, hipStream_t st) {
-    const size_t total = (size_t)B * T * N;
-    if (total == 0) return hipSuccess;
+    const size_t rb = (size_t)N * elem, rows = (size_t)B * T;
+    if (rows == 0 || rb == 0) return hipSuccess;
     const char *bl = static_cast<const char *>(blocks);
-    if (elem == 1)
-        hipLaunchKernelGGL(k_blocks_to_bt<uint8_t>, dim3(grid_for(total)), dim3(256), 0, st, total, T, N, TR, bl,
-                           blk_bytes, static_cast<uint8_t *>(spikes));
-    else if (elem == 2)
-        hipLaunchKernelGGL(k_blocks_to_bt<uint16_t>, dim3(grid_for(total)), dim3(256), 0, st, total, T, N, TR, bl,
-                           blk_bytes, static_cast<uint16_t *>(spikes));
+    const int cb = chunk_bytes(rb, blocks, spikes, blk_bytes);
+    const int cpr = (int)(rb / cb);
+    const size_t chunks = rows * cpr;
+    if (cb == 16)
+        hipLaunchKernelGGL(k_blocks_to_bt<uint4>, dim3(grid_for(chunks)), dim3(256), 0, st, chunks, cpr, T, TR, bl,
+                           blk_bytes, rb, static_cast<uint4 *>(spikes));
+    else if (cb == 4)
+        hipLaunchKernelGGL(k_blocks_to_bt<uint32_t>, dim3(grid_for(chunks)), dim3(256), 0, st, chunks, cpr, T, TR,
+                           bl, blk_bytes, rb, static_cast<uint32_t *>(spikes));
     else
-        hipLaunchKernelGGL(k_blocks_to_bt<uint32_t>, dim3(grid_for(total)), dim3(256), 0, st, total, T, N, TR, bl,
-                           blk_bytes, static_cast<uint32_t *>(spikes));
+        hipLaunchKernelGGL(k_blocks_to_bt<uint8_t>, dim3(grid_for(chunks)), dim3(256), 0, st, chunks, cpr, T, TR,
+                           bl, blk_bytes, rb, static_cast<uint8_t *>(spikes));
     return hipGetLastError();
 }
 
 hipError_t launch_shift_time(int B, int T, int N, int D, int elem, const void *in, void *out, hipStream_t st) {
-    const size_t total = (size_t)B * T * N;
-    if (total == 0) return hipSuccess;
-    if (elem == 1)
-        hipLaunchKernelGGL(k_shift_time<uint8_t>, dim3(grid_for(total)), dim3(256), 0, st, total, T, N, D,
-                           static_cast<const uint8_t *>(in), static_cast<uint8_t *>(out));
-    else if (elem == 2)
-        hipLaunchKernelGGL(k_shift_time<uint16_t>, dim3(grid_for(total)), dim3(256), 0, st, total, T, N, D,
-                           static_cast<const uint16_t *>(in), static_cast<uint16_t *>(out));
-    else
-        hipLaunchKernelGGL(k_shift_time<uint32_t>, dim3(grid_for(total)), dim3(256), 0, st, total, T, N, D,
+    const size_t rb = (size_t)N * elem, rows = (size_t)B * T;
+    if (rows == 0 || rb == 0) return hipSuccess;
+    const int cb = chunk_bytes(rb, in, out, 0);
+    const int cpr = (int)(rb / cb);
+    const size_t chunks = rows * cpr;
+    if (cb == 16)
+        hipLaunchKernelGGL(k_shift_time<uint4>, dim3(grid_for(chunks)), dim3(256), 0, st, chunks, cpr, T, D,
+                           static_cast<const uint4 *>(in), static_cast<uint4 *>(out));
+    else if (cb == 4)
+        hipLaunchKernelGGL(k_shift_time<uint32_t>, dim3(grid_for(chunks)), dim3(256), 0, st, chunks, cpr, T, D,
                            static_cast<const uint32_t *>(in), static_cast<uint32_t *>(out));
+    else
+        hipLaunchKernelGGL(k_shift_time<uint8_t>, dim3(grid_for(chunks)), dim3(256), 0, st, chunks, cpr, T, D,
+                           static_cast<const uint8_t *>(in), static_cast<uint8_t *>(out));
     return hipGetLastError();
 }
 
