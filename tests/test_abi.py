@@ -97,6 +97,37 @@ def test_sizes_and_validation_host_side():
     assert b"required" in lib.alif_last_error()
 
 
+def test_projection_and_recurrent_validation_host_side():
+    """The dW / dx and recurrent entry points reject bad arguments before any
+    device call."""
+    lib = L.load()
+    n = ctypes.c_size_t()
+    by = ctypes.byref
+    spk = _desc(input_kind=1, n_in=16)
+    assert lib.alif_weight_grad_workspace_bytes(by(spk), by(n)) == 0
+    assert lib.alif_weight_grad(by(_desc()), None, None, None, None, None) == L.ALIF_EINVAL
+    assert b"spike input_kind" in lib.alif_last_error()
+    assert lib.alif_weight_grad(by(spk), None, None, None, None, None) == L.ALIF_EINVAL
+    assert lib.alif_input_grad(by(_desc()), None, None, None, None) == L.ALIF_EINVAL
+    assert lib.alif_input_grad(by(spk), None, None, None, None) == L.ALIF_EINVAL
+    assert b"required" in lib.alif_last_error()
+    # recurrent layer
+    assert lib.alif_recurrent_workspace_bytes(by(_desc()), by(n)) == 0 and n.value > 0
+    none_p = L.AlifParams(None, None, None, None, None)
+    fake_p = L.AlifParams(16, 16, 16, 16, None)   # never dereferenced: validation fails first
+    args = [None] * 7
+    assert lib.alif_forward_recurrent(by(_desc()), by(none_p), None, None, None, 0, *args) == L.ALIF_EINVAL
+    assert lib.alif_forward_recurrent(by(_desc()), by(fake_p), None, None, None, 0, *args) == L.ALIF_EINVAL
+    assert b"required" in lib.alif_last_error()
+    assert lib.alif_forward_recurrent(by(_desc()), by(fake_p), None, None, None, 1, *args) == L.ALIF_EINVAL
+    assert b"delay" in lib.alif_last_error()
+    assert lib.alif_forward_recurrent(by(_desc(algo=1)), by(fake_p), None, None, None, 0, *args) == \
+        L.ALIF_EUNSUPPORTED
+    assert lib.alif_recurrent_weight_grad(by(_desc()), 1, None, None, None, None, None) == L.ALIF_EINVAL
+    assert lib.alif_recurrent_weight_grad(by(_desc()), 0, None, None, None, None, None) == L.ALIF_EINVAL
+    assert b"required" in lib.alif_last_error()
+
+
 def _request(N=100, T=1000, dt=0.05, arp=2.0, **kw):
     import numpy as np
 

@@ -127,3 +127,41 @@ def test_recurrent_longer_delay(TR, dt, D):
     check_grad("grad_current", np_(out["grad_current"]), ob["gI"])
     check_grad("grad_W_rec", np_(out["grad_W_rec"]), oracle.recurrent_weight_grad(ob["gI"], orc["S"], D))
     log(f"    D={D}: excused {excused}, max|dV| {dV:.1e}")
+
+
+def test_recurrent_without_reach_equals_feedforward():
+    """D >= T (and a run shorter than one block): the recurrent term never
+    applies, so the block-by-block run must equal alif_forward on the same
+    current, spike for spike and trace for trace (this also checks the
+    one-block runs and their chained FP64 carries against the single launch)."""
+    import torch
+
+    from paper_2311_11390_amd import alif
+    g = rng(31)
+    B, N, TR, dt = 2, 67, 5, 0.4
+    for T, D in [(3 * 52 + 2, 400), (3, 5)]:
+        I = driven_current(31 + T, B, T, N)
+        prm = random_params(31, N, tm=(3.0, 30.0), bias=(-0.2, 0.3))
+        It = torch.as_tensor(I, device="cuda")
+        P = to_dev(prm)
+        W_rec = torch.as_tensor((g.standard_normal((N, N)) / np.sqrt(N)).astype(np.float32), device="cuda")
+        fr = alif.forward_recurrent(It, P, dt, 2.0, W_rec, want_v=True, want_theta=True, delay=D)
+        ff = alif.forward(It, P, dt, 2.0, want_v=True, want_theta=True)
+        torch.cuda.synchronize()
+        log(f"[rec] no reach T={T} D={D}: spikes {int(np_(ff['spikes']).sum())}")
+        np.testing.assert_array_equal(np_(fr["spikes"]), np_(ff["spikes"]))
+        assert np.abs(np_(fr["v"]) - np_(ff["v"])).max() <= 1e-6
+        assert np.abs(np_(fr["theta"]) - np_(ff["theta"])).max() <= 1e-6
+        np.testing.assert_array_equal(np_(fr["current"]), I)
+
+
+def test_recurrent_empty_shapes():
+    import torch
+
+    from paper_2311_11390_amd import alif
+    for B, T, N in [(0, 40, 8), (2, 0, 8)]:
+        I = torch.zeros(B, T, N, device="cuda")
+        prm = random_params(3, N)
+        f = alif.forward_recurrent(I, to_dev(prm), 0.5, 2.0, torch.zeros(N, N, device="cuda"))
+        torch.cuda.synchronize()
+        assert f["spikes"].shape == (B, T, N)
