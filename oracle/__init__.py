@@ -362,3 +362,56 @@ def smoothed_mse(S, S_target, kernel):
     loss = float((diff ** 2).sum() / M)
     g = smooth_time(2.0 * diff / M, kernel[::-1].copy())
     return loss, g
+
+
+# ---------------------------------------------------------------------------
+# Neural-fit loss and optimiser (supplementary "Neural fits")
+# ---------------------------------------------------------------------------
+
+def van_rossum(x, y, dt, tau, scale=1.0):
+    """Van Rossum distance of supplementary "Supervised training loss" and its gradient.
+
+    D = sqrt((1/tau) * integral over [0, T] of (k*x - k*y)^2), k(t) = H(t) exp(-t/tau),
+    put on the simulation grid: a spike (or count) at step s is an impulse of unit
+    area at step s, so (k*x)[t] = sum_{s <= t} exp(-(t - s) dt / tau) x[s] (H(0) = 1),
+    and the integral is dt times the sum over the T simulated steps.
+
+    x: model spike trains [B][T][N]; y: targets [B][T][N] or [B][R][T][N] (R repeats
+    compared with the same model train). Returns (D [B][R][N],
+    grad [B][T][N] = scale * sum_r dD[b][r][n] / dx[b][t][n]); where D = 0 the
+    gradient of that term is taken as 0 (the square root's subgradient).
+    """
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    if y.ndim == 3:
+        y = y[:, None]
+    B, T, N = x.shape
+    R = y.shape[1]
+    a = np.exp(-dt / tau)
+    e = np.zeros((B, R, T, N))              # k*x - k*y
+    run = np.zeros((B, R, N))
+    for t in range(T):
+        run = a * run + (x[:, None, t, :] - y[:, :, t, :])
+        e[:, :, t, :] = run
+    D = np.sqrt(dt / tau * (e ** 2).sum(axis=2))
+    # dD/dx[s] = (dt / (tau D)) * sum_{t >= s} exp(-(t - s) dt / tau) e[t]
+    w = np.where(D > 0, dt / (tau * np.where(D > 0, D, 1.0)), 0.0)
+    grad = np.zeros((B, T, N))
+    run = np.zeros((B, R, N))
+    for t in range(T - 1, -1, -1):
+        run = a * run + e[:, :, t, :]
+        grad[:, t, :] = (w * run).sum(axis=1)
+    return D, scale * grad
+
+
+def adam_step(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, lo=-np.inf, hi=np.inf):
+    """One Adam update (Kingma and Ba, Algorithm 1; the optimiser the neural fits use),
+    followed by a projection of the parameter onto [lo, hi] (the paper leaves how the
+    parameters are kept valid open). ``step`` counts from 1. Returns (p, m, v)."""
+    p, g, m, v = (np.asarray(a, np.float64) for a in (p, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    p = p - lr * mhat / (np.sqrt(vhat) + eps)
+    return np.clip(p, lo, hi), m, v
