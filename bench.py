@@ -336,6 +336,195 @@ def speedup_sweep(steps=5, warmup=2):
             "steps": steps, "rows": rows}
 
 
+def dt_error_sweep(reps=3, seed=21):
+    """The speed-accuracy trade-off of simulating one layer at a coarser DT (the
+    problem overview figure, panel b): 16 x 256 ALIF neurons with fixed input
+    weights driven by 200 Poisson channels for 1 s (synth.dt_sweep_layer), the
+    same input events binned at DT in {0.025, 0.05, 0.1, 0.2, 0.25, 0.5, 1} ms, ARP
+    2 ms. Per DT: forward time (FP32 input GEMM + ALIF) of the block kernels, of
+    the fused sequential kernels and of one launch per step, and the error of the
+    spike trains against the DT = 0.025 ms run (its trains summed into the coarser
+    bins): mean van Rossum distance at tau_R = 10 ms and 100 ms, and the relative
+    error of the spike count."""
+    import torch
+
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif, synth
+    dev = "cuda"
+    w = synth.dt_sweep_layer(seed)
+    x_fine = w.inputs["x"]
+    B, Tf, _ = x_fine.shape
+    W = torch.as_tensor(w.weights[0], device=dev)
+    P = alif.Params.from_numpy(w.layers[0], dev)
+    N = W.shape[0]
+    rows, ref = [], None
+    for dt in (0.025, 0.05, 0.1, 0.2, 0.25, 0.5, 1.0):
+        s = int(round(dt / w.dt))
+        x = torch.as_tensor(synth.bin_counts(x_fine, s) if s > 1 else x_fine, device=dev)
+        T = x.shape[1]
+        Wd = (W / dt).contiguous()
+        out = {"spikes": torch.empty(B, T, N, dtype=torch.uint8, device=dev),
+               "current": torch.empty(B, T, N, dtype=torch.float32, device=dev)}
+        row = {"dt_ms": dt, "T": T, "T_R": alif.refractory_steps(dt, w.arp)}
+        for name, algo, n in (("sequential", L.ALGO_SEQUENTIAL, reps), ("per_step", L.ALGO_SEQUENTIAL_STEP, 1),
+                              ("block", L.ALGO_BLOCKS, reps)):
+            o = dict(out)
+            if algo == L.ALGO_SEQUENTIAL_STEP:
+                desc = alif.make_desc(B, T, N, dt, w.arp, x.shape[2], L.INPUT_SPIKES_U8, algo=algo)
+                o["carries"] = torch.empty(alif.carry_bytes(desc), dtype=torch.uint8, device=dev)
+            row[name + "_fwd_ms"] = _event_ms(lambda: alif.forward(x, P, dt, w.arp, Wd, algo=algo, out=o), n)
+        S = out["spikes"]            # the block run's trains
+        if ref is None:
+            ref = S.clone()
+        tgt = ref.view(B, T, s, N).sum(dim=2).to(torch.uint8).contiguous()
+        for tau in (10.0, 100.0):
+            d, _, _ = alif.van_rossum(S, tgt, dt, tau, want_grad=False)
+            row[f"van_rossum_{tau:g}ms"] = float(d.mean().item())
+        n_ref = float(ref.sum().item())
+        row["spike_count_rel_err"] = abs(float(S.sum().item()) - n_ref) / n_ref
+        row["rate_hz"] = float(S.sum().item()) / (B * N * w.T * w.dt * 1e-3)
+        rows.append(row)
+        log(f"[bench] dt sweep DT={dt}: block {row['block_fwd_ms']:.3f} ms, sequential "
+            f"{row['sequential_fwd_ms']:.3f} ms, per-step {row['per_step_fwd_ms']:.1f} ms; van Rossum "
+            f"{row['van_rossum_10ms']:.3f} (10 ms) {row['van_rossum_100ms']:.3f} (100 ms), "
+            f"count err {row['spike_count_rel_err']:.3f}")
+        del x, out, S
+    return {"workload": f"{B} x {N} ALIF, 200 Poisson inputs (rate per batch element ~ U[20, 80] Hz), "
+                        f"W ~ U[0, 0.26], 1 s, ARP 2 ms; error against DT {w.dt} ms",
+            "reps": reps, "rows": rows}
+
+
+FIT_GROUPS = (  # parameter, Adam learning rate, projection bounds
+    ("tau_mem", 0.5, 1.0, 200.0), ("tau_adapt", 5.0, 5.0, 2000.0), ("d", 0.01, 0.0, 5.0),
+    ("theta0", 0.01, 0.05, 10.0), ("bias", 0.01, -5.0, 5.0))
+
+
+def fit_sweep(epochs=100, seq_epochs=5, N=2048, seed=31):
+    """Fitting ALIF neurons to recorded spike trains by minimising the van Rossum
+    distance (tau_R 100 ms) with Adam, full batch, at several DT and ARP (the
+    neural-fit figure's accuracy-versus-ARP and accuracy-versus-DT panels), on
+    synthetic recordings (synth.neuron_fit): N ground-truth neurons simulated at
+    DT 0.05 ms, ARP 2 ms, 4 fitting + 4 held-out OU stimuli of 2 s, 4 repeats each
+    with independent intrinsic noise. Every fit starts from the same initial
+    parameters; one epoch = forward on the fitting stimuli, van Rossum loss and
+    gradient against all repeats, surrogate-gradient backward, one Adam step per
+    parameter vector. Per configuration: ms per epoch, the mean distance on the
+    fitting set (last epoch) and on the held-out set before and after fitting, the
+    repeat-to-repeat distance of the recordings themselves (the floor), and the
+    relative error of the recovered tau_mem and theta0; the held-out distance and
+    the floor are also given at tau_R 10 ms, which weighs spike timing more. The DT 0.1 ms, ARP 2 ms fit
+    is also timed with the fused sequential kernels."""
+    import torch
+
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif, synth
+    dev = "cuda"
+    fs = synth.neuron_fit(seed, N=N)
+    Tg = int(round(fs.duration_ms / fs.dt_ms))
+    nb, R, ns = 2 * fs.n_stim, fs.repeats, fs.n_stim
+    stim = torch.empty(nb, Tg, N, dtype=torch.float32, device=dev)
+    for b in range(nb):
+        alif.ou_current(Tg, N, fs.dt_ms, fs.stim_tau_ms, fs.amplitudes[b], fs.stim_sd, fs.seed * 1000 + b,
+                        out=stim[b])
+    gt = torch.empty(nb, R, Tg, N, dtype=torch.uint8, device=dev)
+    Pt = alif.Params.from_numpy(fs.truth, dev)
+    cur = torch.empty(R, Tg, N, dtype=torch.float32, device=dev)
+    for b in range(nb):
+        for r in range(R):
+            alif.ou_current(Tg, N, fs.dt_ms, fs.noise_tau_ms, 0.0, fs.noise_sd, fs.seed * 1000 + 100 + b * R + r,
+                            out=cur[r])
+        cur += stim[b]
+        alif.forward(cur, Pt, fs.dt_ms, fs.arp_ms, out={"spikes": gt[b]})
+    del cur
+    torch.cuda.synchronize()
+    gt_rate = float(gt.sum().item()) / (nb * R * N * fs.duration_ms * 1e-3)
+    log(f"[bench] fit: ground truth {nb} stimuli x {R} repeats x {N} neurons, {gt_rate:.1f} Hz")
+    truth_tm = torch.as_tensor(fs.truth.tau_mem, device=dev)
+    truth_th = torch.as_tensor(fs.truth.theta0, device=dev)
+
+    def run(dt, arp, n_epochs, algo=L.ALGO_BLOCKS):
+        s = int(round(dt / fs.dt_ms))
+        Tc = Tg // s
+        I_tr = stim[:ns].view(ns, Tc, s, N).mean(dim=2).contiguous()
+        I_te = stim[ns:].view(ns, Tc, s, N).mean(dim=2).contiguous()
+        y = gt.view(nb, R, Tc, s, N).sum(dim=3).to(torch.uint8)
+        y_tr, y_te = y[:ns].contiguous(), y[ns:].contiguous()
+        del y
+        P = alif.Params.from_numpy(fs.init, dev)
+        opt = {k: (torch.zeros(N, device=dev), torch.zeros(N, device=dev)) for k, *_ in FIT_GROUPS}
+        desc = alif.make_desc(ns, Tc, N, dt, arp, algo=algo)
+        out = {"spikes": torch.empty(ns, Tc, N, dtype=torch.uint8, device=dev),
+               "carries": torch.empty(alif.carry_bytes(desc), dtype=torch.uint8, device=dev)}
+        bws = torch.empty(max(1, alif.backward_workspace_bytes(desc)), dtype=torch.uint8, device=dev)
+        vws = alif.van_rossum_workspace(ns, R, Tc, N, dev)
+        gS = torch.empty(ns, Tc, N, dtype=torch.float32, device=dev)
+        dist = torch.empty(ns, R, N, dtype=torch.float32, device=dev)
+
+        def test_distance(tau):
+            S = alif.forward(I_te, P, dt, arp, algo=algo)["spikes"]
+            d, _, _ = alif.van_rossum(S, y_te, dt, tau, want_grad=False, workspace=vws)
+            return float(d.mean().item())
+
+        def floor(tau):
+            d, _, _ = alif.van_rossum(y_te[:, 0].contiguous(), y_te[:, 1:].contiguous(), dt, tau, want_grad=False)
+            return float(d.mean().item())
+
+        row = {"dt_ms": dt, "arp_ms": arp, "T": Tc, "T_R": alif.refractory_steps(dt, arp)}
+        if algo == L.ALGO_BLOCKS:
+            row["test_distance_init"] = test_distance(100.0)
+            row["repeat_floor"] = floor(100.0)
+            row["repeat_floor_10ms"] = floor(10.0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for ep in range(1, n_epochs + 1):
+            f = alif.forward(I_tr, P, dt, arp, algo=algo, save=True, out=out)
+            alif.van_rossum(f["spikes"], y_tr, dt, 100.0, scale=1.0 / (ns * R), dist=dist, grad=gS, workspace=vws)
+            g = alif.backward(f, I_tr, P, grad_spikes=gS, workspace=bws)
+            for name, lr, lo, hi in FIT_GROUPS:
+                m, v = opt[name]
+                alif.adam_step(getattr(P, name), g["grad_" + name], m, v, ep, lr, lo=lo, hi=hi)
+            if ep == 1:
+                d_first = dist.mean()
+        e1.record()
+        torch.cuda.synchronize()
+        row["ms_per_epoch"] = e0.elapsed_time(e1) / n_epochs
+        row["epochs"] = n_epochs
+        row["train_distance_first"] = float(d_first.item())
+        row["train_distance_last"] = float(dist.mean().item())
+        if algo == L.ALGO_BLOCKS:
+            row["test_distance_fit"] = test_distance(100.0)
+            row["test_distance_fit_10ms"] = test_distance(10.0)
+            row["tau_mem_rel_err"] = float(((P.tau_mem - truth_tm).abs() / truth_tm).mean().item())
+            row["theta0_rel_err"] = float(((P.theta0 - truth_th).abs() / truth_th).mean().item())
+            row["rate_hz"] = float(out["spikes"].sum().item()) / (ns * N * fs.duration_ms * 1e-3)
+        del I_tr, I_te, y_tr, y_te, out, bws, vws, gS
+        return row
+
+    rows = []
+    for dt, arp in ((0.1, 2.0), (0.1, 4.0), (0.1, 8.0), (0.2, 2.0), (0.5, 2.0), (1.0, 2.0), (2.0, 4.0),
+                    (4.0, 8.0)):
+        row = run(dt, arp, epochs)
+        rows.append(row)
+        log(f"[bench] fit DT={dt} ARP={arp}: {row['ms_per_epoch']:.2f} ms/epoch, train D "
+            f"{row['train_distance_first']:.3f} -> {row['train_distance_last']:.3f}, test D "
+            f"{row['test_distance_init']:.3f} -> {row['test_distance_fit']:.3f} (floor {row['repeat_floor']:.3f}; "
+            f"at tau_R 10 ms {row['test_distance_fit_10ms']:.3f}, floor {row['repeat_floor_10ms']:.3f}), "
+            f"tau_mem err {row['tau_mem_rel_err']:.3f}, theta0 err {row['theta0_rel_err']:.3f}, {row['rate_hz']:.1f} Hz")
+        torch.cuda.empty_cache()
+    seq = run(0.1, 2.0, seq_epochs, algo=L.ALGO_SEQUENTIAL)
+    log(f"[bench] fit DT=0.1 ARP=2 with the sequential kernels: {seq['ms_per_epoch']:.2f} ms/epoch")
+    del stim, gt
+    torch.cuda.empty_cache()
+    return {"workload": f"{N} synthetic neurons, {ns} fitting + {ns} held-out OU stimuli of {fs.duration_ms:g} ms "
+                        f"x {R} noisy repeats, ground truth at DT {fs.dt_ms} ms, ARP {fs.arp_ms} ms "
+                        f"({gt_rate:.1f} Hz); van Rossum tau_R 100 ms; Adam, full batch",
+            "adam_groups": [{"param": k, "lr": lr, "lo": lo, "hi": hi} for k, lr, lo, hi in FIT_GROUPS],
+            "rows": rows,
+            "sequential_dt0.1_arp2": {"ms_per_epoch": seq["ms_per_epoch"], "epochs": seq_epochs,
+                                      "speedup_block": seq["ms_per_epoch"] / rows[0]["ms_per_epoch"]}}
+
+
 def recurrent_leg(w, I, P, gS, steps=3):
     """The fine-DT workload as a recurrent network: the OU current plus
     W_rec S[t - T_R] (W_rec ~ N(0, 0.5^2 / N)), T_R = 40, so 500 blocks run one
@@ -521,6 +710,9 @@ def main():
     ap.add_argument("--no-recurrent", action="store_true", help="skip the recurrent-network leg")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the block-vs-sequential speedup sweep over T, T_R, layers and width")
+    ap.add_argument("--no-fit", action="store_true",
+                    help="skip the DT error sweep and the neural-fit sweep over DT and ARP")
+    ap.add_argument("--fit-epochs", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time (summed over threads) the oracle baseline runs for, in whole passes")
@@ -653,6 +845,15 @@ def main():
         sweep = speedup_sweep()
         torch.cuda.empty_cache()
 
+    fits = None
+    if not args.no_fit:
+        log("[bench] simulation error versus DT")
+        fits = {"dt_error": dt_error_sweep()}
+        torch.cuda.empty_cache()
+        log("[bench] neural fits versus DT and ARP")
+        fits["neuron_fit"] = fit_sweep(args.fit_epochs)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = len(os.sched_getaffinity(0))
@@ -704,6 +905,7 @@ def main():
         "layers": layers,
         "recurrent": recurrent,
         "speedup_sweep": sweep,
+        "fits": fits,
         "serving": serve,
     }
     print(json.dumps(res), flush=True)

@@ -319,6 +319,46 @@ int alif_readout_backward(int32_t B, int32_t T, int32_t n_hidden, int32_t C, dou
                           const float *tau_r, const float *go, float *grad_spikes,
                           float *grad_W_r, float *grad_tau_r, void *workspace, void *stream);
 
+/* ---- neural fits: van Rossum loss and Adam (supplementary "Neural fits") ------ */
+
+/*
+ * Van Rossum distance (supplementary "Supervised training loss") between model
+ * spike trains and recorded ones, with its gradient for alif_backward's
+ * grad_spikes. On the simulation grid a spike (or a count) at step s is an
+ * impulse of unit area, the exponential kernel is H(t) exp(-t / tau_R) with
+ * H(0) = 1, and the integral over the T steps is DT times a sum:
+ *   e[t] = sum_{s <= t} a^(t - s) (x[s] - y[s]),  a = exp(-dt_ms / tau_ms),
+ *   D    = sqrt((dt_ms / tau_ms) sum_{t < T} e[t]^2).
+ *   B, R, T, N  batch, repeats per model train (1..8), steps, neurons; any may be 0
+ *   spikes      device uint8 [B][T][N]: the model's trains (0/1 or counts)
+ *   targets     device uint8 [B][R][T][N]: R recorded trains per model train
+ *               (repeats of the same stimulus), spike counts per step
+ *   dist        device float [B][R][N]: D of each (model train, repeat, neuron),
+ *               or NULL
+ *   grad        device float [B][T][N] = scale * sum_r dD[b][r][n] / dx[b][t][n],
+ *               or NULL; where D = 0 that term's gradient is 0 (subgradient)
+ *   workspace   device scratch of alif_van_rossum_workspace_bytes(B, R, T, N)
+ * With N % 4 == 0, spikes and targets must be 4-byte and grad 16-byte aligned.
+ * Sums run in FP64 per time chunk, the gradient recurrence in FP32.
+ * ALIF_EINVAL for bad sizes, dt_ms or tau_ms <= 0, or NULL buffers;
+ * ALIF_EUNSUPPORTED for R > 8. Errors are reported before any work is queued.
+ */
+int alif_van_rossum_workspace_bytes(int32_t B, int32_t R, int32_t T, int32_t N, size_t *bytes);
+int alif_van_rossum(int32_t B, int32_t R, int32_t T, int32_t N, double dt_ms, double tau_ms,
+                    const uint8_t *spikes, const uint8_t *targets, float scale,
+                    float *dist, float *grad, void *workspace, void *stream);
+
+/*
+ * One Adam step (Kingma and Ba, Algorithm 1; the neural fits' optimiser) over n
+ * device floats, in place, then the parameter is clamped to [lo, hi] (keeps time
+ * constants and thresholds valid). step counts from 1; m and v start at 0 and
+ * are kept by the caller between steps. The update runs in FP32; 1 - beta and
+ * the bias corrections are formed in FP64 from the given values and rounded once.
+ * ALIF_EINVAL for step < 1, beta outside [0, 1), eps <= 0, lo > hi or NULL buffers.
+ */
+int alif_adam_step(int32_t n, float *param, const float *grad, float *m, float *v, int32_t step,
+                   double lr, double beta1, double beta2, double eps, float lo, float hi, void *stream);
+
 /* Copies the device status word (ALIF_STATUS_* bits OR-ed by kernels on the
  * current device since the last call) to *bits and clears it. Synchronises
  * `stream`. */

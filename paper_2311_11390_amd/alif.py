@@ -399,3 +399,47 @@ def ou_current(T: int, N: int, dt: float, tau: float, mean: float, sd: float, se
     L.check(lib.alif_ou_current(T, N, dt, tau, mean, sd, seed, _p(out), _p(ws), ws_b.value,
                                 _stream(out.device)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# neural fits: van Rossum loss and Adam
+# ---------------------------------------------------------------------------
+
+def van_rossum_workspace(B, R, T, N, device):
+    n = ctypes.c_size_t()
+    L.check(L.load().alif_van_rossum_workspace_bytes(B, R, T, N, ctypes.byref(n)))
+    return torch.empty(max(1, n.value), dtype=torch.uint8, device=device)
+
+
+def van_rossum(spikes: torch.Tensor, targets: torch.Tensor, dt: float, tau: float = 100.0, *,
+               scale: float = 1.0, want_dist: bool = True, want_grad: bool = True,
+               dist=None, grad=None, workspace=None):
+    """Van Rossum distance of uint8 spikes [B][T][N] against uint8 targets [B][R][T][N]
+    (or [B][T][N] for R = 1). Returns (dist [B][R][N] or None,
+    grad [B][T][N] = scale * sum_r dD/dspikes or None, workspace)."""
+    if targets.dim() == 3:
+        targets = targets.unsqueeze(1)
+    B, T, N = spikes.shape
+    R = targets.shape[1]
+    assert spikes.dtype == torch.uint8 and targets.dtype == torch.uint8
+    assert targets.shape == (B, R, T, N) and spikes.is_contiguous() and targets.is_contiguous()
+    dev = spikes.device
+    ws = workspace if workspace is not None else van_rossum_workspace(B, R, T, N, dev)
+    if want_dist and dist is None:
+        dist = torch.empty(B, R, N, dtype=torch.float32, device=dev)
+    if want_grad and grad is None:
+        grad = torch.empty(B, T, N, dtype=torch.float32, device=dev)
+    L.check(L.load().alif_van_rossum(B, R, T, N, float(dt), float(tau), _p(spikes), _p(targets), float(scale),
+                                     _p(dist) if want_dist else None, _p(grad) if want_grad else None,
+                                     _p(ws), _stream(dev)))
+    return (dist if want_dist else None), (grad if want_grad else None), ws
+
+
+def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
+              beta1=0.9, beta2=0.999, eps=1e-8, lo=float("-inf"), hi=float("inf")):
+    """One in-place Adam step on float32 ``param`` (Kingma and Ba), clamped to [lo, hi]."""
+    for t in (param, grad, m, v):
+        assert t.dtype == torch.float32 and t.is_contiguous() and t.numel() == param.numel()
+    L.check(L.load().alif_adam_step(param.numel(), _p(param), _p(grad), _p(m), _p(v), int(step), float(lr),
+                                    float(beta1), float(beta2), float(eps), float(lo), float(hi),
+                                    _stream(param.device)))

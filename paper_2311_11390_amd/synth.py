@@ -183,6 +183,75 @@ def speed_benchmark(seed=0, B=64, T=1024, n_in=200, hidden=(256,), TR=40, driven
                     sizes, {"x": x}, lps, Ws)
 
 
+def bin_counts(x: np.ndarray, s: int) -> np.ndarray:
+    """Sum [B][T][n] uint8 counts over consecutive groups of s steps: the same events
+    on a grid s times coarser (T must be a multiple of s)."""
+    B, T, n = x.shape
+    return x.reshape(B, T // s, s, n).sum(axis=2, dtype=np.uint16).astype(np.uint8)
+
+
+def dt_sweep_layer(seed=21, B=16, N=256, n_in=200, duration_ms=1000.0, dt_ms=0.025) -> Workload:
+    """One ALIF layer with fixed input weights driven by Poisson spikes, for the
+    simulation-error-versus-DT trade-off (the problem overview figure, panel b).
+    Input channel spikes are drawn on the finest grid (dt_ms; Bernoulli per step
+    with p = rate dt, rate per batch element ~ U[20, 80] Hz) and summed into
+    coarser bins for every coarser DT, so all DTs see the same events. The
+    synaptic current is I[t] = b + sum_j W_ij counts_j[t] / DT (each input spike
+    delivers the same charge at every DT); W_ij ~ U[0, 0.26] gives a mean drive
+    of about 0.5 to 2 against theta0 = 1. tau_mem ~ U[10, 30] ms, tau_adapt ~
+    U[100, 300] ms, d ~ U[0.05, 0.5], bias ~ U[-0.1, 0.1]. ARP 2 ms at every DT."""
+    g = rng(seed)
+    T = int(round(duration_ms / dt_ms))
+    rates = g.uniform(20.0, 80.0, B).astype(np.float32)
+    x = bernoulli_spikes(g, (B, T, n_in), (rates * dt_ms * 1e-3)[:, None, None])
+    W = g.uniform(0.0, 0.26, (N, n_in)).astype(np.float32)
+    lp = LayerParams(uniform(g, 10.0, 30.0, N), uniform(g, 100.0, 300.0, N), uniform(g, 0.05, 0.5, N),
+                     const(1.0, N), uniform(g, -0.1, 0.1, N))
+    return Workload(f"dt_sweep_{n_in}x{N}_B{B}_{duration_ms:g}ms", B, T, dt_ms, 2.0, [n_in, N], {"x": x},
+                    [lp], [W], {"rates_hz": rates})
+
+
+@dataclass
+class FitSetup:
+    """Synthetic stand-in for the neural-fit experiments (supplementary "Neural fits"):
+    ground-truth ALIF neurons with their own parameters, each injected with
+    Ornstein-Uhlenbeck currents at several amplitudes (stimuli; the first half for
+    fitting, the second half held out), each stimulus repeated ``repeats`` times
+    with independent intrinsic noise (a second, weaker OU current) so that the
+    recorded trains vary from repeat to repeat. The ground truth runs at dt_ms and
+    ARP 2 ms; models start from the paper's initialisation."""
+    N: int
+    n_stim: int
+    repeats: int
+    duration_ms: float
+    dt_ms: float
+    arp_ms: float
+    amplitudes: list          # OU mean of each stimulus (fit stimuli, then held-out ones)
+    stim_tau_ms: float
+    stim_sd: float
+    noise_tau_ms: float
+    noise_sd: float
+    truth: LayerParams
+    init: LayerParams
+    seed: int
+
+
+def neuron_fit(seed=31, N=2048, n_stim=4, repeats=4, duration_ms=2000.0, dt_ms=0.05) -> FitSetup:
+    """Ground truth tau_mem ~ U[8, 40] ms, tau_adapt ~ U[50, 400] ms, d ~ U[0.02, 0.4],
+    theta0 ~ U[0.8, 1.2], bias ~ U[-0.1, 0.1]; stimuli OU (tau 5 ms, sd 0.5) with
+    means 1.0, 1.2, 1.4, 1.6 (then the same means for the held-out set); intrinsic
+    noise OU (tau 2 ms, sd 0.05). Initial model: tau_mem 20 ms, tau_adapt 100 ms,
+    d 0.1, theta0 1, bias 0 (the supplementary's initial time constants; d and
+    theta0 in this model's units)."""
+    g = rng(seed)
+    truth = LayerParams(uniform(g, 8.0, 40.0, N), uniform(g, 50.0, 400.0, N), uniform(g, 0.02, 0.4, N),
+                        uniform(g, 0.8, 1.2, N), uniform(g, -0.1, 0.1, N))
+    init = LayerParams(const(20.0, N), const(100.0, N), const(0.1, N), const(1.0, N), const(0.0, N))
+    amps = [1.0 + 0.2 * (i % 4) for i in range(n_stim)]
+    return FitSetup(N, n_stim, repeats, duration_ms, dt_ms, 2.0, amps + amps, 5.0, 0.5, 2.0, 0.05,
+                    truth, init, seed)
+
+
 @dataclass
 class Request:
     """One serving request: a single ALIF layer of N neurons over T steps fed by

@@ -201,3 +201,34 @@ def test_ou_current_sizes_and_validation_host_side():
     assert lib.alif_ou_current(10, 10, 0.0, 5.0, 0.8, 0.5, 1, None, None, 0, None) == L.ALIF_EINVAL
     assert lib.alif_ou_current(10, 10, 0.05, 5.0, 0.8, 0.5, 1, None, None, 0, None) == L.ALIF_EINVAL
     assert lib.alif_ou_current(0, 10, 0.05, 5.0, 0.8, 0.5, 1, None, None, 0, None) == L.ALIF_OK
+
+
+def test_van_rossum_and_adam_validation_host_side():
+    lib = L.load()
+    n = ctypes.c_size_t()
+    assert lib.alif_van_rossum_workspace_bytes(4, 4, 20000, 2048, ctypes.byref(n)) == L.ALIF_OK
+    assert n.value > 0
+    assert lib.alif_van_rossum_workspace_bytes(4, 9, 100, 8, ctypes.byref(n)) == L.ALIF_EUNSUPPORTED
+    assert lib.alif_van_rossum_workspace_bytes(4, 0, 100, 8, ctypes.byref(n)) == L.ALIF_EINVAL
+    assert lib.alif_van_rossum_workspace_bytes(-1, 1, 100, 8, ctypes.byref(n)) == L.ALIF_EINVAL
+    vr = lib.alif_van_rossum
+    dummy = ctypes.c_void_p(256)
+    assert vr(2, 1, 10, 8, 0.0, 100.0, dummy, dummy, 1.0, dummy, dummy, dummy, None) == L.ALIF_EINVAL
+    assert vr(2, 1, 10, 8, 0.1, -1.0, dummy, dummy, 1.0, dummy, dummy, dummy, None) == L.ALIF_EINVAL
+    assert vr(2, 1, 10, 8, 0.1, float("inf"), dummy, dummy, 1.0, dummy, dummy, dummy, None) == L.ALIF_EINVAL
+    assert vr(2, 1, 10, 8, 0.1, 100.0, dummy, dummy, float("nan"), dummy, dummy, dummy, None) == L.ALIF_EINVAL
+    assert vr(2, 9, 10, 8, 0.1, 100.0, dummy, dummy, 1.0, dummy, dummy, dummy, None) == L.ALIF_EUNSUPPORTED
+    assert vr(2, 1, 10, 8, 0.1, 100.0, None, dummy, 1.0, dummy, dummy, dummy, None) == L.ALIF_EINVAL
+    assert vr(2, 1, 10, 8, 0.1, 100.0, dummy, dummy, 1.0, dummy, dummy, None, None) == L.ALIF_EINVAL
+    odd = ctypes.c_void_p(258)
+    assert vr(2, 1, 10, 8, 0.1, 100.0, odd, dummy, 1.0, dummy, dummy, dummy, None) == L.ALIF_EINVAL
+    assert vr(2, 1, 10, 8, 0.1, 100.0, dummy, dummy, 1.0, dummy, ctypes.c_void_p(264), dummy, None) == L.ALIF_EINVAL
+    # neither output requested: nothing to do
+    assert vr(2, 1, 10, 8, 0.1, 100.0, None, None, 1.0, None, None, None, None) == L.ALIF_OK
+    adam = lib.alif_adam_step
+    assert adam(10, dummy, dummy, dummy, dummy, 0, 0.1, 0.9, 0.999, 1e-8, 0.0, 1.0, None) == L.ALIF_EINVAL
+    assert adam(10, dummy, dummy, dummy, dummy, 1, 0.1, 1.0, 0.999, 1e-8, 0.0, 1.0, None) == L.ALIF_EINVAL
+    assert adam(10, dummy, dummy, dummy, dummy, 1, 0.1, 0.9, 0.999, 0.0, 0.0, 1.0, None) == L.ALIF_EINVAL
+    assert adam(10, dummy, dummy, dummy, dummy, 1, 0.1, 0.9, 0.999, 1e-8, 2.0, 1.0, None) == L.ALIF_EINVAL
+    assert adam(10, None, dummy, dummy, dummy, 1, 0.1, 0.9, 0.999, 1e-8, 0.0, 1.0, None) == L.ALIF_EINVAL
+    assert adam(0, None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, 0.0, 1.0, None) == L.ALIF_OK
