@@ -399,7 +399,10 @@ FIT_GROUPS = (  # parameter, Adam learning rate, projection bounds
     ("theta0", 0.01, 0.05, 10.0), ("bias", 0.01, -5.0, 5.0))
 
 
-def fit_sweep(epochs=100, seq_epochs=5, N=2048, seed=31):
+FIT_CONFIGS = ((0.1, 2.0), (0.1, 4.0), (0.1, 8.0), (0.2, 2.0), (0.5, 2.0), (1.0, 2.0), (2.0, 4.0), (4.0, 8.0))
+
+
+def fit_sweep(epochs=100, seq_epochs=5, N=2048, seed=31, configs=FIT_CONFIGS):
     """Fitting ALIF neurons to recorded spike trains by minimising the van Rossum
     distance (tau_R 100 ms) with Adam, full batch, at several DT and ARP (the
     neural-fit figure's accuracy-versus-ARP and accuracy-versus-DT panels), on
@@ -490,6 +493,16 @@ def fit_sweep(epochs=100, seq_epochs=5, N=2048, seed=31):
         torch.cuda.synchronize()
         row["ms_per_epoch"] = e0.elapsed_time(e1) / n_epochs
         row["epochs"] = n_epochs
+        if algo == L.ALGO_BLOCKS:
+            # the loss alone (three kernels, one launch each), against the bytes it must
+            # move: the model spikes and every target once (1 + R bytes) and the gradient
+            # (4 bytes) per element
+            S = out["spikes"]
+            ms = _event_ms(lambda: alif.van_rossum(S, y_tr, dt, 100.0, scale=1.0 / (ns * R), dist=dist, grad=gS,
+                                                   workspace=vws), 5)
+            nbytes = float(ns) * Tc * N * (1 + R + 4)
+            row["loss"] = {"avg_ms": ms, "bytes_per_launch": nbytes, "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
+                           "frac_of_peak": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         row["train_distance_first"] = float(d_first.item())
         row["train_distance_last"] = float(dist.mean().item())
         if algo == L.ALGO_BLOCKS:
@@ -502,18 +515,20 @@ def fit_sweep(epochs=100, seq_epochs=5, N=2048, seed=31):
         return row
 
     rows = []
-    for dt, arp in ((0.1, 2.0), (0.1, 4.0), (0.1, 8.0), (0.2, 2.0), (0.5, 2.0), (1.0, 2.0), (2.0, 4.0),
-                    (4.0, 8.0)):
+    for dt, arp in configs:
         row = run(dt, arp, epochs)
         rows.append(row)
         log(f"[bench] fit DT={dt} ARP={arp}: {row['ms_per_epoch']:.2f} ms/epoch, train D "
             f"{row['train_distance_first']:.3f} -> {row['train_distance_last']:.3f}, test D "
             f"{row['test_distance_init']:.3f} -> {row['test_distance_fit']:.3f} (floor {row['repeat_floor']:.3f}; "
             f"at tau_R 10 ms {row['test_distance_fit_10ms']:.3f}, floor {row['repeat_floor_10ms']:.3f}), "
-            f"tau_mem err {row['tau_mem_rel_err']:.3f}, theta0 err {row['theta0_rel_err']:.3f}, {row['rate_hz']:.1f} Hz")
+            f"tau_mem err {row['tau_mem_rel_err']:.3f}, theta0 err {row['theta0_rel_err']:.3f}, {row['rate_hz']:.1f} Hz; "
+            f"loss {row['loss']['avg_ms']:.3f} ms = {row['loss']['frac_of_peak']:.2f} of HBM peak")
         torch.cuda.empty_cache()
-    seq = run(0.1, 2.0, seq_epochs, algo=L.ALGO_SEQUENTIAL)
-    log(f"[bench] fit DT=0.1 ARP=2 with the sequential kernels: {seq['ms_per_epoch']:.2f} ms/epoch")
+    dt0, arp0 = configs[0]
+    seq = run(dt0, arp0, seq_epochs, algo=L.ALGO_SEQUENTIAL) if seq_epochs > 0 else None
+    if seq:
+        log(f"[bench] fit DT={dt0} ARP={arp0} with the sequential kernels: {seq['ms_per_epoch']:.2f} ms/epoch")
     del stim, gt
     torch.cuda.empty_cache()
     return {"workload": f"{N} synthetic neurons, {ns} fitting + {ns} held-out OU stimuli of {fs.duration_ms:g} ms "
@@ -521,8 +536,9 @@ def fit_sweep(epochs=100, seq_epochs=5, N=2048, seed=31):
                         f"({gt_rate:.1f} Hz); van Rossum tau_R 100 ms; Adam, full batch",
             "adam_groups": [{"param": k, "lr": lr, "lo": lo, "hi": hi} for k, lr, lo, hi in FIT_GROUPS],
             "rows": rows,
-            "sequential_dt0.1_arp2": {"ms_per_epoch": seq["ms_per_epoch"], "epochs": seq_epochs,
-                                      "speedup_block": seq["ms_per_epoch"] / rows[0]["ms_per_epoch"]}}
+            "sequential": None if seq is None else {
+                "dt_ms": dt0, "arp_ms": arp0, "ms_per_epoch": seq["ms_per_epoch"], "epochs": seq_epochs,
+                "speedup_block": seq["ms_per_epoch"] / rows[0]["ms_per_epoch"]}}
 
 
 def recurrent_leg(w, I, P, gS, steps=3):
@@ -713,6 +729,11 @@ def main():
     ap.add_argument("--no-fit", action="store_true",
                     help="skip the DT error sweep and the neural-fit sweep over DT and ARP")
     ap.add_argument("--fit-epochs", type=int, default=100)
+    ap.add_argument("--fit-configs", default=",".join(f"{d:g}:{a:g}" for d, a in FIT_CONFIGS),
+                    help="DT:ARP pairs (ms) of the neural-fit sweep; the first is also fitted with the "
+                         "sequential kernels")
+    ap.add_argument("--fit-seq-epochs", type=int, default=5)
+    ap.add_argument("--no-dt-sweep", action="store_true", help="skip the simulation-error-versus-DT sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time (summed over threads) the oracle baseline runs for, in whole passes")
@@ -847,11 +868,14 @@ def main():
 
     fits = None
     if not args.no_fit:
-        log("[bench] simulation error versus DT")
-        fits = {"dt_error": dt_error_sweep()}
-        torch.cuda.empty_cache()
+        fits = {}
+        if not args.no_dt_sweep:
+            log("[bench] simulation error versus DT")
+            fits["dt_error"] = dt_error_sweep()
+            torch.cuda.empty_cache()
         log("[bench] neural fits versus DT and ARP")
-        fits["neuron_fit"] = fit_sweep(args.fit_epochs)
+        cfgs = tuple(tuple(float(v) for v in c.split(":")) for c in args.fit_configs.split(","))
+        fits["neuron_fit"] = fit_sweep(args.fit_epochs, args.fit_seq_epochs, configs=cfgs)
         torch.cuda.empty_cache()
 
     cpu = None

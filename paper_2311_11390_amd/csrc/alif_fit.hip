@@ -13,13 +13,15 @@
 //                plus e_loc every 16 steps (checkpoints). With the true carry C
 //                into the chunk, e = e_loc + a^(j+1) C, so the chunk adds
 //                P + 2 C Q + C^2 G to sum e^2, G = sum_{j=1..L} a^(2j).
-//   k_vr_combine one thread per (b, neuron): walks the chunks left to right for
-//                the carries and D, then right to left for the carry of the
-//                reverse recurrence g[s] = c[s] + a g[s + 1], where
-//                c = sum_r w_r e_r, w_r = scale DT / (tau_R D_r).
-//   k_vr_grad    one thread per (b, chunk, 1 or 4 neurons): walks its chunk's
-//                16-step pieces last to first; each piece rebuilds c forward from
-//                its checkpoint into registers, then runs g backward and stores it.
+//   k_vr_combine one thread per (b, repeat, neuron): walks the chunks left to
+//                right for the carries of e and for D, then right to left for
+//                the carries of the reverse recurrence g[s] = e[s] + a g[s + 1].
+//   k_vr_grad    one thread per (b, chunk, 1 or 4 neurons): the gradient is the
+//                reverse recurrence of c = sum_r w_r e_r, w_r = scale DT /
+//                (tau_R D_r), so the carries combine with the same weights. It
+//                walks its chunk's 16-step pieces last to first; each piece
+//                rebuilds c forward from its checkpoint into registers, then runs
+//                g backward and stores it.
 // Data read: the spike bytes twice (x once per group of up to four repeats in
 // the first pass), the gradient written once; checkpoints and chunk sums add
 // about 4 R / 16 bytes per element each way.
@@ -43,7 +45,7 @@ size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct VrPlan {
     int vec, ng, K, Lc, S;          // neurons per thread, thread columns per row, chunks, chunk length, pieces
-    size_t off_sum, off_cp, off_w, off_cm, off_gr, total;
+    size_t off_sum, off_cp, off_w, off_ce, off_cg, total;
 };
 
 VrPlan vr_plan(int B, int R, int T, int N) {
@@ -65,9 +67,9 @@ VrPlan vr_plan(int B, int R, int T, int N) {
     p.off_sum = 0;
     p.off_cp = a256(bkn * R * 3 * sizeof(double));
     p.off_w = p.off_cp + a256(bkn * p.S * R * sizeof(float));
-    p.off_cm = p.off_w + a256((size_t)B * R * N * sizeof(float));
-    p.off_gr = p.off_cm + a256(bkn * sizeof(double));
-    p.total = p.off_gr + a256(bkn * sizeof(double));
+    p.off_ce = p.off_w + a256((size_t)B * R * N * sizeof(float));
+    p.off_cg = p.off_ce + a256(bkn * R * sizeof(double));
+    p.total = p.off_cg + a256(bkn * R * sizeof(double));
     return p;
 }
 
@@ -159,77 +161,49 @@ __global__ void __launch_bounds__(256) k_vr_chunks(int B, int R, int r0, int T, 
     }
 }
 
-// Per (b, neuron): distances, repeat weights, chunk carries of c and of g. All
-// chunks but the last have length Lc: their decay a^Lc and sum G are passed in
-// (aL, G for full chunks; aLl, Gl for the last one).
+// Per (b, repeat, neuron): the distance, the repeat's weight w_r, and per chunk
+// k the carries of e_r and of g_r = sum_{t >= s} a^(t - s) e_r[t] (unweighted;
+// the gradient kernel forms sum_r w_r of both). All chunks but the last have
+// length Lc: their decay a^Lc and sum G are passed in (aL, G; aLl, Gl for the last).
 __global__ void __launch_bounds__(256) k_vr_combine(int B, int R, int N, int K, double a, double aL, double G,
                                                     double aLl, double Gl, double dt_over_tau, double scale,
                                                     const double *__restrict__ sums, float *__restrict__ dist,
-                                                    float *__restrict__ wts, double *__restrict__ cm,
-                                                    double *__restrict__ gr, int want_grad) {
+                                                    float *__restrict__ wts, double *__restrict__ ce,
+                                                    double *__restrict__ cg, int want_grad) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)B * N) return;
-    const int b = (int)(i / N), n = (int)(i % N);
-    const double *col = sums + (size_t)b * K * R * 3 * N + n;   // [k][r][E, P, Q][N]
+    if (i >= (long long)B * R * N) return;
+    const int n = (int)(i % N);
+    const int r = (int)((i / N) % R);
+    const int b = (int)(i / ((long long)N * R));
     const size_t kstride = (size_t)R * 3 * N;
-    double C[VR_MAX_R], D2[VR_MAX_R];
-#pragma unroll
-    for (int r = 0; r < VR_MAX_R; r++) C[r] = D2[r] = 0.0;
-#pragma unroll 2
+    const double *col = sums + (size_t)b * K * kstride + (size_t)(3 * r) * N + n;   // [k][r][E, P, Q][N]
+    double *cec = ce + ((size_t)b * K * R + r) * N + n;                           // [b][k][r][N]
+    double *cgc = cg + ((size_t)b * K * R + r) * N + n;
+    const size_t ko = (size_t)R * N;
+    double C = 0.0, D2 = 0.0;
+#pragma unroll 4
     for (int k = 0; k < K; k++) {
         const bool last = k == K - 1;
-        const double ak = last ? aLl : aL, Gk = last ? Gl : G;
         const double *s = col + k * kstride;
-#pragma unroll
-        for (int r = 0; r < VR_MAX_R; r++) {
-            if (r >= R) break;
-            const double E = s[(size_t)(3 * r) * N], P = s[(size_t)(3 * r + 1) * N], Q = s[(size_t)(3 * r + 2) * N];
-            D2[r] += P + 2.0 * C[r] * Q + C[r] * C[r] * Gk;
-            C[r] = fma(ak, C[r], E);
-        }
+        const double E = s[0], P = s[N], Q = s[2 * N];
+        if (want_grad) cec[k * ko] = C;
+        D2 += P + 2.0 * C * Q + C * C * (last ? Gl : G);
+        C = fma(last ? aLl : aL, C, E);
     }
-    double w[VR_MAX_R];
-#pragma unroll
-    for (int r = 0; r < VR_MAX_R; r++) {
-        w[r] = 0.0;
-        if (r >= R) continue;
-        const double d = sqrt(fmax(0.0, dt_over_tau * D2[r]));
-        if (dist) dist[((size_t)b * R + r) * N + n] = (float)d;
-        w[r] = d > 0.0 ? scale * dt_over_tau / d : 0.0;
-        if (want_grad) wts[((size_t)b * R + r) * N + n] = (float)w[r];
-    }
+    const double d = sqrt(fmax(0.0, dt_over_tau * D2));
+    if (dist) dist[((size_t)b * R + r) * N + n] = (float)d;
     if (!want_grad) return;
-    // carries of c = sum_r w_r e_r into each chunk; q_k = sum_r w_r Q_r(k) for the pass below
-#pragma unroll
-    for (int r = 0; r < VR_MAX_R; r++) C[r] = 0.0;
-    double *cmc = cm + (size_t)b * K * N + n;
-    double *grc = gr + (size_t)b * K * N + n;
-#pragma unroll 2
-    for (int k = 0; k < K; k++) {
-        const double ak = k == K - 1 ? aLl : aL;
-        const double *s = col + k * kstride;
-        double m = 0.0, q = 0.0;
-#pragma unroll
-        for (int r = 0; r < VR_MAX_R; r++) {
-            if (r >= R) break;
-            m = fma(w[r], C[r], m);
-            q = fma(w[r], s[(size_t)(3 * r + 2) * N], q);
-            C[r] = fma(ak, C[r], s[(size_t)(3 * r) * N]);
-        }
-        cmc[(size_t)k * N] = m;
-        grc[(size_t)k * N] = q;      // holds q_k until the pass below replaces it
-    }
-    // g at the first step of each chunk, from the right:
-    // g[t0] = sum_j a^j c[t0 + j] + a^L g[t0 + L], sum_j a^j c[t0 + j] = (q_k + G Cm_k) / a
+    wts[((size_t)b * R + r) * N + n] = d > 0.0 ? (float)(scale * dt_over_tau / d) : 0.0f;
+    // g_r at the first step of each chunk, from the right:
+    // g[t0] = sum_j a^j e[t0 + j] + a^L g[t0 + L], sum_j a^j e[t0 + j] = (Q + G C) / a
     const double inv_a = 1.0 / a;
     double g = 0.0;
-#pragma unroll 2
+#pragma unroll 4
     for (int k = K - 1; k >= 0; k--) {
         const bool last = k == K - 1;
-        const double ak = last ? aLl : aL, Gk = last ? Gl : G;
-        const double A = (grc[(size_t)k * N] + Gk * cmc[(size_t)k * N]) * inv_a;
-        grc[(size_t)k * N] = g;
-        g = fma(ak, g, A);
+        const double A = (col[k * kstride + 2 * N] + (last ? Gl : G) * cec[k * ko]) * inv_a;
+        cgc[k * ko] = g;
+        g = fma(last ? aLl : aL, g, A);
     }
 }
 
@@ -237,7 +211,7 @@ template <int VEC>
 __global__ void __launch_bounds__(256) k_vr_grad(int B, int R, int T, int N, int ng, int K, int Lc, int S,
                                                  double lna, const uint8_t *__restrict__ x,
                                                  const uint8_t *__restrict__ y, const float *__restrict__ wts,
-                                                 const double *__restrict__ cm, const double *__restrict__ gr,
+                                                 const double *__restrict__ ce, const double *__restrict__ cg,
                                                  const float *__restrict__ cp, float *__restrict__ grad) {
     long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= (long long)B * K * ng) return;
@@ -258,12 +232,21 @@ __global__ void __launch_bounds__(256) k_vr_grad(int B, int R, int T, int N, int
             w[r][v] = r < R ? wts[((size_t)b * R + r) * N + n0 + v] : 0.f;
             W[v] += w[r][v];
         }
+    // carries into this chunk of c = sum_r w_r e_r and of g = sum_r w_r g_r
     double cmk[VEC];
     float g[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; v++) {
-        cmk[v] = cm[((size_t)b * K + k) * N + n0 + v];
-        g[v] = (float)gr[((size_t)b * K + k) * N + n0 + v];
+        const size_t o = ((size_t)b * K + k) * R * N + n0 + v;
+        double cc = 0.0, gg = 0.0;
+#pragma unroll
+        for (int r = 0; r < VR_MAX_R; r++)
+            if (r < R) {
+                cc = fma((double)w[r][v], ce[o + (size_t)r * N], cc);
+                gg = fma((double)w[r][v], cg[o + (size_t)r * N], gg);
+            }
+        cmk[v] = cc;
+        g[v] = (float)gg;
     }
     const size_t xrow = (size_t)b * T * N + n0;
     const size_t ytr = (size_t)T * N;
@@ -422,8 +405,8 @@ int alif_van_rossum(int32_t B, int32_t R, int32_t T, int32_t N, double dt_ms, do
     double *sums = (double *)(ws + p.off_sum);
     float *cp = (float *)(ws + p.off_cp);
     float *wts = (float *)(ws + p.off_w);
-    double *cm = (double *)(ws + p.off_cm);
-    double *gr = (double *)(ws + p.off_gr);
+    double *ce = (double *)(ws + p.off_ce);
+    double *cg = (double *)(ws + p.off_cg);
     const double lna = -dt_ms / tau_ms;
     const double a = exp(lna);
     hipError_t e = hipSuccess;
@@ -433,23 +416,23 @@ int alif_van_rossum(int32_t B, int32_t R, int32_t T, int32_t N, double dt_ms, do
                        : launch_chunks_rg<1>(rg, p, B, R, r0, T, N, a, spikes, targets, sums, cp, st);
     }
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
-    const long long cols = (long long)B * N;
+    const long long cols = (long long)B * R * N;
     const int Ll = T - (p.K - 1) * p.Lc;   // length of the last chunk
     const double den = expm1(2.0 * lna);
     const double aL = exp(p.Lc * lna), G = a * a * expm1(2.0 * p.Lc * lna) / den;
     const double aLl = exp(Ll * lna), Gl = a * a * expm1(2.0 * Ll * lna) / den;
     hipLaunchKernelGGL(k_vr_combine, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, st, B, R, N, p.K, a, aL, G,
-                       aLl, Gl, dt_ms / tau_ms, (double)scale, sums, dist, wts, cm, gr, grad ? 1 : 0);
+                       aLl, Gl, dt_ms / tau_ms, (double)scale, sums, dist, wts, ce, cg, grad ? 1 : 0);
     e = hipGetLastError();
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
     if (!grad) return ALIF_OK;
     const long long n = (long long)B * p.K * p.ng;
     if (p.vec == 4)
         hipLaunchKernelGGL(k_vr_grad<4>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, R, T, N, p.ng, p.K,
-                           p.Lc, p.S, lna, spikes, targets, wts, cm, gr, cp, grad);
+                           p.Lc, p.S, lna, spikes, targets, wts, ce, cg, cp, grad);
     else
         hipLaunchKernelGGL(k_vr_grad<1>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, R, T, N, p.ng, p.K,
-                           p.Lc, p.S, lna, spikes, targets, wts, cm, gr, cp, grad);
+                           p.Lc, p.S, lna, spikes, targets, wts, ce, cg, cp, grad);
     e = hipGetLastError();
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
     return ALIF_OK;
