@@ -420,8 +420,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_fwd(FwdArgs a) {
     };
 
     // Pipelined form (SEG 4 or 8: every wave of a workgroup holds the same 64
-    // neurons, so a vote over one wave is a vote over the workgroup; 16 segments
-    // would not fit two copies of the exchange arrays in LDS at T_R = 128). The
+    // neurons, so a vote over one wave is a vote over the workgroup). The
     // iteration for block nb integrates block nb from its scan and Horner sums,
     // done one iteration earlier, and scans block nb + 1 assuming no refractory
     // mask; both results go through LDS behind a single barrier. Once t_s of
@@ -603,6 +602,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     // With one segment per block there is no barrier to share, and each block's
     // membrane is computed in its own iteration instead.
     constexpr bool PIPE = SEG > 1;
+    constexpr bool RECOMP = L > 8;   // long segments: recompute instead of store (see below)
     const auto par = [](int nb) { return (nb & 1) * Exch<SEG>::SIZE; };
     float vtn[L], thn[L];   // V~ and theta of the block the next iteration finishes
     if constexpr (PIPE) {
@@ -663,55 +663,108 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
 
         // local reverse recurrences over this segment's steps, from zero:
         //   rv: lambda_V (source dL/dV + dL/dS s'), pv: its decay across the segment,
-        //   ra: lambda_a' (source lambda_theta = dL/dtheta - dL/dS s')
-        float Vk[L], ak[L], lt[L], rV[L], PVk[L], rA[L];
+        //   ra: lambda_a' (source lambda_theta = dL/dtheta - dL/dS s').
+        // Short segments keep every step's lambdas, membrane, adaptation and gate in
+        // registers for the gradient pass. Long ones (RECOMP) keep only dL/dS s' per
+        // step; the gradient pass reruns the same recurrences step by step (the same
+        // operations, so the same values), which frees about 6 L registers per lane.
+        float Vk[L], ak[L], lt[L], rV[L], PVk[L], rA[L], gsv[L];
         bool gate[L];
         float rv = 0.0f, pv = 1.0f, ra = 0.0f;
-        if (quiet) {
+        float VLast = vt[L - 1];   // V of this segment's last step (after a spike: 0)
+        if constexpr (!RECOMP) {
+            if (quiet) {
 #pragma unroll
-            for (int k = L - 1; k >= 0; k--) {
-                const float gsk = cur.gs[k] * surrogate_grad<SG>(vt[k] - th[k], a.slope);
-                float src;
-                if constexpr (GVT) {
-                    src = cur.gv[k] + gsk;
-                    lt[k] = cur.gt[k] - gsk;
-                } else {
-                    src = gsk;
-                    lt[k] = -gsk;
+                for (int k = L - 1; k >= 0; k--) {
+                    const float gsk = cur.gs[k] * surrogate_grad<SG>(vt[k] - th[k], a.slope);
+                    float src;
+                    if constexpr (GVT) {
+                        src = cur.gv[k] + gsk;
+                        lt[k] = cur.gt[k] - gsk;
+                    } else {
+                        src = gsk;
+                        lt[k] = -gsk;
+                    }
+                    rv = fmaf(c.bdec(k), rv, src);
+                    ra = fmaf(c.pdec(k), ra, lt[k]);
+                    rV[k] = rv;
+                    rA[k] = ra;
                 }
-                rv = fmaf(c.bdec(k), rv, src);
-                ra = fmaf(c.pdec(k), ra, lt[k]);
-                rV[k] = rv;
-                rA[k] = ra;
+                pv = c.PB(0);
+            } else {
+#pragma unroll
+                for (int k = L - 1; k >= 0; k--) {
+                    const int t = c.t0 + k + 1;
+                    const bool after = t > ts;
+                    const float pa = pf_tab[pfrow - tsc + k];   // p^(t - 1 - t_s)
+                    Vk[k] = after ? 0.0f : vt[k];
+                    ak[k] = after ? fmaf(c.pt[k], a1, pa) : c.pt[k] * a1;
+                    const float thk = after ? fmaf(c.dd, pa, th[k]) : th[k];
+                    gate[k] = (t > mpre) && !after;
+                    const float gsk = cur.gs[k] * surrogate_grad<SG>(Vk[k] - thk, a.slope);
+                    float src;
+                    if constexpr (GVT) {
+                        src = cur.gv[k] + gsk;
+                        lt[k] = cur.gt[k] - gsk;
+                    } else {
+                        src = gsk;
+                        lt[k] = -gsk;
+                    }
+                    const float fV = t == ts ? 0.0f : c.bdec(k);
+                    rv = fmaf(fV, rv, src);
+                    pv = pv * fV;
+                    ra = fmaf(c.pdec(k), ra, lt[k]);
+                    rV[k] = rv;
+                    PVk[k] = pv;
+                    rA[k] = ra;
+                }
             }
-            pv = c.PB(0);
+
+            VLast = quiet ? vt[L - 1] : Vk[L - 1];
         } else {
+            if (quiet) {
 #pragma unroll
-            for (int k = L - 1; k >= 0; k--) {
-                const int t = c.t0 + k + 1;
-                const bool after = t > ts;
-                const float pa = pf_tab[pfrow - tsc + k];   // p^(t - 1 - t_s)
-                Vk[k] = after ? 0.0f : vt[k];
-                ak[k] = after ? fmaf(c.pt[k], a1, pa) : c.pt[k] * a1;
-                const float thk = after ? fmaf(c.dd, pa, th[k]) : th[k];
-                gate[k] = (t > mpre) && !after;
-                const float gsk = cur.gs[k] * surrogate_grad<SG>(Vk[k] - thk, a.slope);
-                float src;
-                if constexpr (GVT) {
-                    src = cur.gv[k] + gsk;
-                    lt[k] = cur.gt[k] - gsk;
-                } else {
-                    src = gsk;
-                    lt[k] = -gsk;
+                for (int k = L - 1; k >= 0; k--) {
+                    const float gsk = cur.gs[k] * surrogate_grad<SG>(vt[k] - th[k], a.slope);
+                    gsv[k] = gsk;
+                    float src, ltk;
+                    if constexpr (GVT) {
+                        src = cur.gv[k] + gsk;
+                        ltk = cur.gt[k] - gsk;
+                    } else {
+                        src = gsk;
+                        ltk = -gsk;
+                    }
+                    rv = fmaf(c.bdec(k), rv, src);
+                    ra = fmaf(c.pdec(k), ra, ltk);
                 }
-                const float fV = t == ts ? 0.0f : c.bdec(k);
-                rv = fmaf(fV, rv, src);
-                pv = pv * fV;
-                ra = fmaf(c.pdec(k), ra, lt[k]);
-                rV[k] = rv;
-                PVk[k] = pv;
-                rA[k] = ra;
+                pv = c.PB(0);
+            } else {
+                VLast = c.t0 + L > ts ? 0.0f : vt[L - 1];
+#pragma unroll
+                for (int k = L - 1; k >= 0; k--) {
+                    const int t = c.t0 + k + 1;
+                    const bool after = t > ts;
+                    const float pa = pf_tab[pfrow - tsc + k];   // p^(t - 1 - t_s)
+                    const float Vkk = after ? 0.0f : vt[k];
+                    const float thk = after ? fmaf(c.dd, pa, th[k]) : th[k];
+                    const float gsk = cur.gs[k] * surrogate_grad<SG>(Vkk - thk, a.slope);
+                    gsv[k] = gsk;
+                    float src, ltk;
+                    if constexpr (GVT) {
+                        src = cur.gv[k] + gsk;
+                        ltk = cur.gt[k] - gsk;
+                    } else {
+                        src = gsk;
+                        ltk = -gsk;
+                    }
+                    const float fV = t == ts ? 0.0f : c.bdec(k);
+                    rv = fmaf(fV, rv, src);
+                    pv = pv * fV;
+                    ra = fmaf(c.pdec(k), ra, ltk);
+                }
             }
+
         }
 
         // stage 2: one barrier, then the incoming lambdas at this segment's end
@@ -723,7 +776,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
             ex.M[po + c.w * NWG + c.nl] = pv;
             ex.R[po + c.w * NWG + c.nl] = rv;
             ex.RA[po + c.w * NWG + c.nl] = ra;
-            ex.VL[po + c.w * NWG + c.nl] = quiet ? vt[L - 1] : Vk[L - 1];
+            ex.VL[po + c.w * NWG + c.nl] = VLast;
             __syncthreads();
             float lv = lamV_c, la = lamA_c;
             lVin = lv;
@@ -753,51 +806,142 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
         //   d/dbias   += (1 - beta) gate lambda_V[t]
         float pb = 0.0f, pp = 0.0f, pdd = 0.0f, pth = 0.0f, pbias = 0.0f;
         const uint32_t bo = (uint32_t)nb * blk4;
-        if (quiet) {
-            // a[t] = p^(t-1) a1 throughout a quiet block, so a1 factors out of the
-            // d and p sums; the bias term of I factors out of the beta sum
-            const float aprev0 = c.w == 0 ? ca : c.ptm1 * a1;
-            float slV = 0.0f, qd = 0.0f, qp = 0.0f, lA0 = 0.0f;
+        if constexpr (!RECOMP) {
+            if (quiet) {
+                // a[t] = p^(t-1) a1 throughout a quiet block, so a1 factors out of the
+                // d and p sums; the bias term of I factors out of the beta sum
+                const float aprev0 = c.w == 0 ? ca : c.ptm1 * a1;
+                float slV = 0.0f, qd = 0.0f, qp = 0.0f, lA0 = 0.0f;
 #pragma unroll
-            for (int k = 0; k < L; k++) {
-                const float lV = c.kvalid(k) ? fmaf(c.PB(k), lVin, rV[k]) : 0.0f;
-                const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
-                const float Vprev = (k == 0) ? Vprev0 : vt[k > 0 ? k - 1 : 0];
-                slV += lV;
-                pb = fmaf(Vprev - cur.x[k], lV, pb);
-                qd = fmaf(c.pt[k], lt[k], qd);
-                if (k == 0) lA0 = lA;
-                else qp = fmaf(c.pt[k > 0 ? k - 1 : 0], lA, qp);
-                pth += lt[k];
-                if constexpr (GI) st_f32(rGI, c.off(k, bo), c.omb * lV);
-            }
-            pb = fmaf(-bias, slV, pb);
-            pp = c.dd * fmaf(a1, qp, aprev0 * lA0);
-            pdd = a1 * qd;
-            pbias = c.omb * slV;
-        } else {
-            const float pa0 = pf_tab[pfrow - tsc - 1];     // p^(t0 - 1 - t_s)
-            const float aprev0 = c.w == 0 ? ca : (c.t0 > ts ? fmaf(c.ptm1, a1, pa0) : c.ptm1 * a1);
-            float sglV = 0.0f;
+                for (int k = 0; k < L; k++) {
+                    const float lV = c.kvalid(k) ? fmaf(c.PB(k), lVin, rV[k]) : 0.0f;
+                    const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
+                    const float Vprev = (k == 0) ? Vprev0 : vt[k > 0 ? k - 1 : 0];
+                    slV += lV;
+                    pb = fmaf(Vprev - cur.x[k], lV, pb);
+                    qd = fmaf(c.pt[k], lt[k], qd);
+                    if (k == 0) lA0 = lA;
+                    else qp = fmaf(c.pt[k > 0 ? k - 1 : 0], lA, qp);
+                    pth += lt[k];
+                    if constexpr (GI) st_f32(rGI, c.off(k, bo), c.omb * lV);
+                }
+                pb = fmaf(-bias, slV, pb);
+                pp = c.dd * fmaf(a1, qp, aprev0 * lA0);
+                pdd = a1 * qd;
+                pbias = c.omb * slV;
+            } else {
+                const float pa0 = pf_tab[pfrow - tsc - 1];     // p^(t0 - 1 - t_s)
+                const float aprev0 = c.w == 0 ? ca : (c.t0 > ts ? fmaf(c.ptm1, a1, pa0) : c.ptm1 * a1);
+                float sglV = 0.0f;
 #pragma unroll
-            for (int k = 0; k < L; k++) {
-                const float lV = c.kvalid(k) ? fmaf(PVk[k], lVin, rV[k]) : 0.0f;
-                const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
-                const int t = c.t0 + k + 1;
-                const bool sprev = (t == 1) ? (cts == TR) : (t - 1 == ts);
-                const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
-                const float aprev = (k == 0) ? aprev0 : ak[k > 0 ? k - 1 : 0];
-                const float glV = gate[k] ? lV : 0.0f;
-                const float im = gate[k] ? cur.x[k] + bias : 0.0f;
-                pb = fmaf(sprev ? 0.0f : Vprev - im, lV, pb);
-                pp = fmaf(aprev, lA, pp);
-                pdd = fmaf(ak[k], lt[k], pdd);
-                pth += lt[k];
-                sglV += glV;
-                if constexpr (GI) st_f32(rGI, c.off(k, bo), c.omb * glV);
+                for (int k = 0; k < L; k++) {
+                    const float lV = c.kvalid(k) ? fmaf(PVk[k], lVin, rV[k]) : 0.0f;
+                    const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, rA[k]) : 0.0f;
+                    const int t = c.t0 + k + 1;
+                    const bool sprev = (t == 1) ? (cts == TR) : (t - 1 == ts);
+                    const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
+                    const float aprev = (k == 0) ? aprev0 : ak[k > 0 ? k - 1 : 0];
+                    const float glV = gate[k] ? lV : 0.0f;
+                    const float im = gate[k] ? cur.x[k] + bias : 0.0f;
+                    pb = fmaf(sprev ? 0.0f : Vprev - im, lV, pb);
+                    pp = fmaf(aprev, lA, pp);
+                    pdd = fmaf(ak[k], lt[k], pdd);
+                    pth += lt[k];
+                    sglV += glV;
+                    if constexpr (GI) st_f32(rGI, c.off(k, bo), c.omb * glV);
+                }
+                pp *= c.dd;
+                pbias = c.omb * sglV;
             }
-            pp *= c.dd;
-            pbias = c.omb * sglV;
+        } else {   // steps last to first, rerunning the local recurrences
+            if (quiet) {
+                // a[t] = p^(t-1) a1 throughout a quiet block, so a1 factors out of the
+                // d and p sums; the bias term of I factors out of the beta sum
+                const float aprev0 = c.w == 0 ? ca : c.ptm1 * a1;
+                float slV = 0.0f, qd = 0.0f, qp = 0.0f, lA0 = 0.0f, rv2 = 0.0f, ra2 = 0.0f;
+#pragma unroll
+                for (int k = L - 1; k >= 0; k--) {
+                    const float gsk = gsv[k];
+                    float src, ltk;
+                    if constexpr (GVT) {
+                        src = cur.gv[k] + gsk;
+                        ltk = cur.gt[k] - gsk;
+                    } else {
+                        src = gsk;
+                        ltk = -gsk;
+                    }
+                    rv2 = fmaf(c.bdec(k), rv2, src);
+                    ra2 = fmaf(c.pdec(k), ra2, ltk);
+                    const float lV = c.kvalid(k) ? fmaf(c.PB(k), lVin, rv2) : 0.0f;
+                    const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, ra2) : 0.0f;
+                    const float Vprev = (k == 0) ? Vprev0 : vt[k > 0 ? k - 1 : 0];
+                    slV += lV;
+                    pb = fmaf(Vprev - cur.x[k], lV, pb);
+                    qd = fmaf(c.pt[k], ltk, qd);
+                    if (k == 0) lA0 = lA;
+                    else qp = fmaf(c.pt[k > 0 ? k - 1 : 0], lA, qp);
+                    pth += ltk;
+                    if constexpr (GI) st_f32(rGI, c.off(k, bo), c.omb * lV);
+                }
+                pb = fmaf(-bias, slV, pb);
+                pp = c.dd * fmaf(a1, qp, aprev0 * lA0);
+                pdd = a1 * qd;
+                pbias = c.omb * slV;
+            } else {
+                const float pa0 = pf_tab[pfrow - tsc - 1];     // p^(t0 - 1 - t_s)
+                const float aprev0 = c.w == 0 ? ca : (c.t0 > ts ? fmaf(c.ptm1, a1, pa0) : c.ptm1 * a1);
+                float sglV = 0.0f, rv2 = 0.0f, pv2 = 1.0f, ra2 = 0.0f;
+                // a at step k (corrected after the spike), carried down to the next step
+                float ak_c;
+                {
+                    const int t = c.t0 + L;
+                    const float pa = pf_tab[pfrow - tsc + L - 1];
+                    ak_c = t > ts ? fmaf(c.pt[L - 1], a1, pa) : c.pt[L - 1] * a1;
+                }
+#pragma unroll
+                for (int k = L - 1; k >= 0; k--) {
+                    const int t = c.t0 + k + 1;
+                    const bool after = t > ts;
+                    const float gsk = gsv[k];
+                    float src, ltk;
+                    if constexpr (GVT) {
+                        src = cur.gv[k] + gsk;
+                        ltk = cur.gt[k] - gsk;
+                    } else {
+                        src = gsk;
+                        ltk = -gsk;
+                    }
+                    const float fV = t == ts ? 0.0f : c.bdec(k);
+                    rv2 = fmaf(fV, rv2, src);
+                    pv2 = pv2 * fV;
+                    ra2 = fmaf(c.pdec(k), ra2, ltk);
+                    const float lV = c.kvalid(k) ? fmaf(pv2, lVin, rv2) : 0.0f;
+                    const float lA = c.kvalid(k) ? fmaf(c.PP(k), lAin, ra2) : 0.0f;
+                    const bool sprev = (t == 1) ? (cts == TR) : (t - 1 == ts);
+                    float Vprev, aprev;
+                    if (k == 0) {
+                        Vprev = Vprev0;
+                        aprev = aprev0;
+                    } else {
+                        const bool afterp = t - 1 > ts;
+                        const float pap = pf_tab[pfrow - tsc + k - 1];
+                        Vprev = afterp ? 0.0f : vt[k > 0 ? k - 1 : 0];
+                        aprev = afterp ? fmaf(c.pt[k > 0 ? k - 1 : 0], a1, pap) : c.pt[k > 0 ? k - 1 : 0] * a1;
+                    }
+                    const bool gate = (t > mpre) && !after;
+                    const float glV = gate ? lV : 0.0f;
+                    const float im = gate ? cur.x[k] + bias : 0.0f;
+                    pb = fmaf(sprev ? 0.0f : Vprev - im, lV, pb);
+                    pp = fmaf(aprev, lA, pp);
+                    pdd = fmaf(ak_c, ltk, pdd);
+                    pth += ltk;
+                    sglV += glV;
+                    if constexpr (GI) st_f32(rGI, c.off(k, bo), c.omb * glV);
+                    ak_c = aprev;
+                }
+                pp *= c.dd;
+                pbias = c.omb * sglV;
+            }
         }
         acc_b += (double)pb;
         acc_p += (double)pp;

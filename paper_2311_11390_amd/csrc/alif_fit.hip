@@ -39,7 +39,10 @@ namespace {
 
 constexpr int VR_SUB = 16;          // steps per checkpointed piece
 constexpr int VR_MAX_R = 8;         // repeats per model train (the error messages say 8)
-constexpr long long VR_TARGET_THREADS = 1 << 17;
+#ifndef ALIF_VR_THREADS_LOG2
+#define ALIF_VR_THREADS_LOG2 17   // threads the chunking aims at
+#endif
+constexpr long long VR_TARGET_THREADS = 1LL << ALIF_VR_THREADS_LOG2;
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
