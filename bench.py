@@ -52,8 +52,8 @@ def algorithmic_bytes(TR):
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 COUNTERS = os.path.join(HERE, "profiles", "block_fwd_bwd_fine_dt_hbm_counters.md")
-KERNEL_SOURCES = ["alif_blocks.hip", "alif_blocks_impl.h", "alif_blocks_s1.hip", "alif_blocks_s16.hip",
-                  "alif_blocks_s2.hip", "alif_blocks_s4.hip", "alif_blocks_s8.hip", "alif_common.h",
+KERNEL_SOURCES = ["alif_blocks.hip", "alif_blocks_impl.h", "alif_blocks_s1.hip", "alif_blocks_s2.hip",
+                  "alif_blocks_s4.hip", "alif_blocks_s8.hip", "alif_blocks_s8_long.hip", "alif_common.h",
                   "alif_kernels.h"]
 
 
@@ -62,8 +62,11 @@ def kernel_sources_digest():
     h = hashlib.sha256()
     for name in sorted(KERNEL_SOURCES):
         h.update(name.encode())
-        with open(os.path.join(HERE, "paper_2311_11390_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        try:
+            with open(os.path.join(HERE, "paper_2311_11390_amd", "csrc", name), "rb") as f:
+                h.update(f.read())
+        except OSError:
+            return None   # a listed source is gone: the counters cannot be matched
     return h.hexdigest()
 
 
@@ -83,7 +86,8 @@ def measured_traffic():
             for kv in line.split(":", 1)[1].split():
                 k, v = kv.split("=")
                 traffic[k] = float(v)
-    return traffic if digest == kernel_sources_digest() else {}
+    cur = kernel_sources_digest()
+    return traffic if cur is not None and digest == cur else {}
 
 
 def smoothed_mse_grad(S, S_tgt, sigma_steps):
