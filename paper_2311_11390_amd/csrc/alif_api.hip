@@ -358,8 +358,9 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
     if ((rc = check_params(prm))) return rc;
     if (desc->algo == ALIF_ALGO_SEQUENTIAL_STEP)
         return fail(ALIF_EUNSUPPORTED, "the per-step-launch baseline is forward only");
-    if (desc->algo == ALIF_ALGO_SEQUENTIAL && p.TR > seq_bwd_max_tr())
-        return fail(ALIF_EUNSUPPORTED, "sequential backward supports T_R <= %d", seq_bwd_max_tr());
+    if (desc->algo == ALIF_ALGO_SEQUENTIAL && p.TR > seq_bwd_max_tr(grad_v || grad_theta))
+        return fail(ALIF_EUNSUPPORTED, "sequential backward supports T_R <= %d here",
+                    seq_bwd_max_tr(grad_v || grad_theta));
     const size_t work = (size_t)p.B * p.T * p.N;
     if (work == 0) {
         // nothing to differentiate: parameter gradients are zero

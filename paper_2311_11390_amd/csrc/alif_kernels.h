@@ -124,6 +124,6 @@ hipError_t launch_decay_tables(int N, int TR, double dt, const float *tau_m, con
 hipError_t launch_seq_fwd(const SeqArgs &a, hipStream_t st);
 hipError_t launch_seq_step_fwd(SeqArgs a, hipStream_t st);
 hipError_t launch_seq_bwd(const SeqArgs &a, hipStream_t st);
-int seq_bwd_max_tr();
+int seq_bwd_max_tr(bool with_v_theta_grads);
 
 }  // namespace alif

@@ -304,13 +304,16 @@ hipError_t launch_seq_step_fwd(SeqArgs a, hipStream_t st) {
     return hipSuccess;
 }
 
-int seq_bwd_max_tr() { return 64; }
+// LDS holds one block of T_R steps x 64 neurons: V, theta, a, x, dL/dS (and dL/dV,
+// dL/dtheta) in FP32 plus the step flags, within the 160 KiB of a gfx950 CU.
+static size_t seq_bwd_lds_bytes(int TR, bool gvt) { return (size_t)TR * 64 * ((gvt ? 7 : 5) * sizeof(float) + 1); }
+int seq_bwd_max_tr(bool gvt) { return (int)((size_t)160 * 1024 / seq_bwd_lds_bytes(1, gvt)); }
 
 hipError_t launch_seq_bwd(const SeqArgs &a, hipStream_t st) {
     const int grid = a.B * ((a.N + 63) / 64);
     if (grid == 0) return hipSuccess;
     const bool gvt = a.gV || a.gTH;
-    const size_t smem = (size_t)a.TR * 64 * ((gvt ? 7 : 5) * sizeof(float) + 1);
+    const size_t smem = seq_bwd_lds_bytes(a.TR, gvt);
 #define ALIF_SB(G)                                                                                \
     do {                                                                                          \
         if (a.surrogate == 1) hipLaunchKernelGGL((k_seq_bwd<G, 1>), dim3(grid), dim3(64), smem, st, a); \

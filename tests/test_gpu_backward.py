@@ -49,14 +49,39 @@ def test_blocks_backward_matches_oracle(TR, dt):
     _run(TR, dt, 0, 500 + TR)
 
 
-@pytest.mark.parametrize("TR,dt", [(2, 1.0), (40, 0.05)])
+@pytest.mark.parametrize("TR,dt", [(2, 1.0), (40, 0.05), (80, 0.025), (100, 0.02), (128, 2.0 / 128)])
 def test_blocks_backward_spike_grad_only(TR, dt):
     _run(TR, dt, 0, 600 + TR, gv=False, bias=False)
 
 
-@pytest.mark.parametrize("TR,dt", [(2, 1.0), (4, 0.5), (20, 0.1), (40, 0.05)])
+@pytest.mark.parametrize("TR,dt", [(2, 1.0), (4, 0.5), (20, 0.1), (40, 0.05), (80, 0.025)])
 def test_sequential_backward_matches_oracle(TR, dt):
     _run(TR, dt, 1, 700 + TR)
+
+
+@pytest.mark.parametrize("TR,dt", [(100, 0.02), (121, 2.0 / 121)])
+def test_sequential_backward_spike_grad_only_long_blocks(TR, dt):
+    """Without dL/dV and dL/dtheta the sequential backward's LDS staging fits T_R <= 121."""
+    _run(TR, dt, 1, 800 + TR, gv=False)
+
+
+@pytest.mark.parametrize("TR,gv", [(100, True), (128, False)])
+def test_sequential_backward_rejects_blocks_beyond_lds(TR, gv):
+    """T_R 89-121 with dL/dV, dL/dtheta, and T_R > 121 without, do not fit the
+    sequential backward's LDS staging: ALIF_EUNSUPPORTED before any work."""
+    import torch
+
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif
+    B, N, T, dt = 1, 64, 3 * TR, 2.0 / TR
+    I = driven_current(900 + TR, B, T, N)
+    prm = random_params(900 + TR, N)
+    log(f"[bwd] sequential rejects T_R={TR} gv={gv}")
+    f, It, P = gpu_forward(I, prm, dt, 2.0, algo=1, traces=False, save=True)
+    g = torch.zeros((B, T, N), dtype=torch.float32, device="cuda")
+    with pytest.raises(L.AlifError) as ei:
+        alif.backward(f, It, P, grad_spikes=g, grad_v=g if gv else None)
+    assert ei.value.code == L.ALIF_EUNSUPPORTED
 
 
 def test_fine_dt_backward_ou_workload_small():
