@@ -55,7 +55,7 @@ def _load():
                                         ctypes.c_double, ctypes.c_int, _i8p,
                                         _u8p, _f64p, _f64p, _f64p, _u8p]
     lib.oracle_alif_backward.argtypes = [_i64, _i64, _f64p, _f64p, _f64p, _f64p, _f64p,
-                                         ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                          _u8p, _f64p, _f64p, _f64p, _u8p,
                                          _f64p, _f64p, _f64p,
                                          _f64p, _f64p, _f64p, _f64p, _f64p]
@@ -162,8 +162,10 @@ def surrogate(kind, u: float, slope: float = 10.0) -> float:
 
 
 def backward_rows(fw, tau_m, tau_a, d, theta0, dt, slope=10.0, gS=None, gV=None, gTH=None,
-                  want_gI=True, surrogate="fast_sigmoid"):
-    """Sequential surrogate-gradient adjoint of ``forward_rows`` (detached policy).
+                  want_gI=True, surrogate="fast_sigmoid", attached=False):
+    """Sequential surrogate-gradient adjoint of ``forward_rows`` under the detached
+    policy, or with ``attached`` the spike's own effect through reset and adaptation
+    (supplementary "Detaching gradients").
 
     Returns dict with gI [R][T] (or None) and g_tau_m, g_tau_a, g_d, g_theta0 [R].
     """
@@ -176,7 +178,7 @@ def backward_rows(fw, tau_m, tau_a, d, theta0, dt, slope=10.0, gS=None, gV=None,
     gI = np.empty((R, T)) if want_gI else None
     outs = [np.empty(R) for _ in range(4)]
     _load().oracle_alif_backward(R, T, _p(I, ctypes.c_double), *[_p(q, ctypes.c_double) for q in pr],
-                                 float(dt), _sg_kind(surrogate), float(slope),
+                                 float(dt), _sg_kind(surrogate), float(slope), int(bool(attached)),
                                  _p(fw["S"], ctypes.c_uint8), _p(fw["V"], ctypes.c_double),
                                  _p(fw["TH"], ctypes.c_double), _p(fw["A"], ctypes.c_double),
                                  _p(fw["MASK"], ctypes.c_uint8),
@@ -267,7 +269,7 @@ def recurrent_weight_grad(gI, S, D):
 
 
 def alif_backward(fwd, dt, slope=10.0, gS=None, gV=None, gTH=None, want_gI=True,
-                  surrogate="fast_sigmoid"):
+                  surrogate="fast_sigmoid", attached=False):
     """Adjoint for ``alif_forward`` output; gradients summed over the batch.
 
     gS, gV, gTH are [B][T][N] (or None). Returns gI [B][T][N] (or None) and
@@ -276,7 +278,7 @@ def alif_backward(fwd, dt, slope=10.0, gS=None, gV=None, gTH=None, want_gI=True,
     B, T, N = fwd["S"].shape
     conv = lambda g: None if g is None else _to_rows(np.asarray(g, np.float64))
     bw = backward_rows(fwd["rows"], *fwd["params"], dt, slope, conv(gS), conv(gV), conv(gTH),
-                       want_gI=want_gI, surrogate=surrogate)
+                       want_gI=want_gI, surrogate=surrogate, attached=attached)
     out = {"gI": None if bw["gI"] is None else _from_rows(bw["gI"], B, N)}
     for k in ("g_tau_m", "g_tau_a", "g_d", "g_theta0"):
         out[k] = bw[k].reshape(B, N).sum(axis=0)

@@ -224,23 +224,29 @@ double oracle_surrogate(int kind, double u, double k)
 }
 
 /*
- * Adjoint of oracle_alif_forward under the detached policy, reverse over t with
- * lambda_V[T+1] = lambda_a[T+1] = 0 (sigma' is oracle_surrogate of `surrogate`):
+ * Adjoint of oracle_alif_forward, reverse over t with lambda_V[T+1] =
+ * lambda_a[T+1] = 0 (sigma' is oracle_surrogate of `surrogate`):
  *   s        = sigma'(V[t] - th[t])
- *   lamV[t]  = gV[t] + gS[t] s + beta (1 - S[t]) lamV[t+1]
- *   lamTh[t] = gTh[t] - gS[t] s
+ *   lamS[t]  = gS[t]                                   (detached policy)
+ *            = gS[t] - c[t] lamV[t+1] + lamA[t+1]      (attached: the spike also
+ *              acts through the reset of V[t+1] and the jump of a[t+1], with
+ *              c[t] = beta V[t] + (1 - beta) MASK[t+1] I[t+1], the membrane the
+ *              reset removes, and dV[t+1]/dS[t] = -c[t], da[t+1]/dS[t] = 1)
+ *   lamV[t]  = gV[t] + lamS[t] s + beta (1 - S[t]) lamV[t+1]
+ *   lamTh[t] = gTh[t] - lamS[t] s
  *   lamA[t]  = d lamTh[t] + p lamA[t+1]
  *   gI[t]    = (1 - beta) MASK[t] (1 - S[t-1]) lamV[t]        (gradient w.r.t. I~[t])
  *   gbeta   += (1 - S[t-1]) (V[t-1] - MASK[t] I[t]) lamV[t]
  *   gp      += a[t-1] lamA[t];  gd += a[t] lamTh[t];  gtheta0 += lamTh[t]
  * then g_tau_m = gbeta beta DT / tau_m^2 and g_tau_a = gp p DT / tau_a^2.
- * gS, gV, gTH: [R][T], each may be NULL (= zero). Outputs: gI [R][T] (may be NULL),
- * g_tau_m, g_tau_a, g_d, g_theta0 [R] (each may be NULL).
+ * The ARP gate MASK is a step function of the spike history: no gradient in
+ * either policy. gS, gV, gTH: [R][T], each may be NULL (= zero). Outputs: gI
+ * [R][T] (may be NULL), g_tau_m, g_tau_a, g_d, g_theta0 [R] (each may be NULL).
  */
 void oracle_alif_backward(int64_t R, int64_t T, const double *I,
                           const double *tau_m, const double *tau_a,
                           const double *d, const double *theta0,
-                          double dt, int surrogate, double slope,
+                          double dt, int surrogate, double slope, int attached,
                           const uint8_t *S, const double *V, const double *TH,
                           const double *A, const uint8_t *MASK,
                           const double *gS, const double *gV, const double *gTH,
@@ -257,10 +263,15 @@ void oracle_alif_backward(int64_t R, int64_t T, const double *I,
         double gbeta = 0.0, gp = 0.0, gd = 0.0, gth0 = 0.0;
         for (int64_t t = T - 1; t >= 0; t--) {
             double sg = oracle_surrogate(surrogate, V[o + t] - TH[o + t], slope);
-            double gs = gS ? gS[o + t] : 0.0;
-            double lamV = (gV ? gV[o + t] : 0.0) + gs * sg
+            double lamS = gS ? gS[o + t] : 0.0;
+            if (attached && t + 1 < T) {
+                double in_next = MASK[o + t + 1] ? I[o + t + 1] : 0.0;
+                double c = beta * V[o + t] + (1.0 - beta) * in_next;
+                lamS += -c * lamV_next + lamA_next;
+            }
+            double lamV = (gV ? gV[o + t] : 0.0) + lamS * sg
                         + beta * (1.0 - (double)S[o + t]) * lamV_next;
-            double lamTh = (gTH ? gTH[o + t] : 0.0) - gs * sg;
+            double lamTh = (gTH ? gTH[o + t] : 0.0) - lamS * sg;
             double lamA = d[r] * lamTh + p * lamA_next;
             double s_prev = t > 0 ? (double)S[o + t - 1] : 0.0;
             double v_prev = t > 0 ? V[o + t - 1] : 0.0;
