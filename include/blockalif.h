@@ -102,6 +102,17 @@ enum alif_surrogate {
     ALIF_SG_MULTI_GAUSSIAN = 2  /* 1.15 N(u|0, 0.5^2) - 0.15 N(u|3, 3^2) - 0.15 N(u|-3, 3^2) */
 };
 
+/* Gradient policy of the backward (supplementary "Detaching gradients"). Detached:
+ * the spike's uses in the reset of V[t+1] and in the adaptation jump of a[t+1] are
+ * constants; gradient flows through the feedforward connections only. Attached:
+ * those uses stay in the gradient, dV[t+1]/dS[t] = -(beta V[t] + (1 - beta) I[t+1])
+ * (the membrane the reset removes) and da[t+1]/dS[t] = 1. The ARP gate is a step
+ * function of the spike history under both. */
+enum alif_grad_policy {
+    ALIF_GRAD_DETACHED = 0,
+    ALIF_GRAD_ATTACHED = 1   /* ALIF_ALGO_SEQUENTIAL backward only; blocks: ALIF_EUNSUPPORTED */
+};
+
 /* ---- problem descriptor ------------------------------------------------------ */
 typedef struct alif_desc {
     int32_t batch;          /* B >= 0 */
@@ -116,6 +127,7 @@ typedef struct alif_desc {
     int32_t algo;           /* enum alif_algo */
     int32_t surrogate;      /* enum alif_surrogate */
     float   sg_slope;       /* fast-sigmoid slope k (supplementary uses 10); >= 0 */
+    int32_t grad_policy;    /* enum alif_grad_policy (0 = detached) */
 } alif_desc;
 
 /* Per-neuron parameters, device float [N] each (Eqs. 2-5). bias may be NULL (= 0). */

@@ -29,6 +29,7 @@ GEMM_FP32, GEMM_BF16 = 0, 1
 SPIKES_U8, SPIKES_BF16, SPIKES_F32 = 0, 1, 2
 ALGO_BLOCKS, ALGO_SEQUENTIAL, ALGO_SEQUENTIAL_STEP = 0, 1, 2
 SG_FAST_SIGMOID, SG_BOXCAR, SG_MULTI_GAUSSIAN = 0, 1, 2
+GRAD_DETACHED, GRAD_ATTACHED = 0, 1
 REQ_HOST_CURRENT, REQ_OU = 0, 1
 
 
@@ -36,7 +37,7 @@ class AlifDesc(Structure):
     _fields_ = [("batch", c_int32), ("n_in", c_int32), ("n_neurons", c_int32), ("T", c_int32),
                 ("dt_ms", c_double), ("arp_ms", c_double), ("input_kind", c_int32),
                 ("gemm_precision", c_int32), ("spike_dtype", c_int32), ("algo", c_int32),
-                ("surrogate", c_int32), ("sg_slope", c_float)]
+                ("surrogate", c_int32), ("sg_slope", c_float), ("grad_policy", c_int32)]
 
 
 class AlifParams(Structure):

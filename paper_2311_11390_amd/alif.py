@@ -58,9 +58,10 @@ def refractory_steps(dt_ms: float, arp_ms: float) -> int:
 
 def make_desc(B, T, N, dt, arp, n_in=0, input_kind=L.INPUT_CURRENT_F32, gemm_precision=L.GEMM_FP32,
               spike_dtype=L.SPIKES_U8, algo=L.ALGO_BLOCKS, slope=10.0,
-              surrogate=L.SG_FAST_SIGMOID) -> L.AlifDesc:
+              surrogate=L.SG_FAST_SIGMOID, grad_policy=L.GRAD_DETACHED) -> L.AlifDesc:
     return L.AlifDesc(int(B), int(n_in), int(N), int(T), float(dt), float(arp), int(input_kind),
-                      int(gemm_precision), int(spike_dtype), int(algo), int(surrogate), float(slope))
+                      int(gemm_precision), int(spike_dtype), int(algo), int(surrogate), float(slope),
+                      int(grad_policy))
 
 
 def carry_bytes(desc) -> int:
@@ -88,7 +89,7 @@ def _cstate(s):
 def forward(inp: torch.Tensor, params: Params, dt: float, arp: float, W: torch.Tensor | None = None, *,
             gemm_precision=L.GEMM_FP32, spike_dtype=L.SPIKES_U8, algo=L.ALGO_BLOCKS,
             want_v=False, want_theta=False, save=False, init=None, want_final=False,
-            slope=10.0, surrogate=L.SG_FAST_SIGMOID, out=None) -> dict:
+            slope=10.0, surrogate=L.SG_FAST_SIGMOID, grad_policy=L.GRAD_DETACHED, out=None) -> dict:
     """One ALIF layer over T steps (alif_forward).
 
     ``inp`` is the current float32 [B][T][N] when ``W`` is None, else presynaptic
@@ -96,7 +97,8 @@ def forward(inp: torch.Tensor, params: Params, dt: float, arp: float, W: torch.T
     ``spikes`` (dtype from ``spike_dtype``), optional ``v``/``theta``, and what the
     backward needs (``current``, ``carries``, ``desc``) when ``save``. ``surrogate``
     (SG_FAST_SIGMOID with ``slope``, SG_BOXCAR, SG_MULTI_GAUSSIAN) selects the
-    surrogate derivative the backward of this forward uses."""
+    surrogate derivative the backward of this forward uses, ``grad_policy``
+    (GRAD_DETACHED, GRAD_ATTACHED) its gradient policy."""
     assert inp.is_cuda and inp.is_contiguous()
     B, T = inp.shape[0], inp.shape[1]
     dev = inp.device
@@ -108,7 +110,8 @@ def forward(inp: torch.Tensor, params: Params, dt: float, arp: float, W: torch.T
         N, n_in = W.shape
         assert inp.shape[2] == n_in
         kind = _INPUT_KIND[inp.dtype]
-    desc = make_desc(B, T, N, dt, arp, n_in, kind, gemm_precision, spike_dtype, algo, slope, surrogate)
+    desc = make_desc(B, T, N, dt, arp, n_in, kind, gemm_precision, spike_dtype, algo, slope, surrogate,
+                     grad_policy)
     o = out or {}
     spikes = o.get("spikes")
     if spikes is None:

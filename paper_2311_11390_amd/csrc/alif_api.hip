@@ -89,6 +89,8 @@ int check_desc(const alif_desc *d, Prob *p) {
     if (d->surrogate != ALIF_SG_FAST_SIGMOID && d->surrogate != ALIF_SG_BOXCAR &&
         d->surrogate != ALIF_SG_MULTI_GAUSSIAN)
         return fail(ALIF_EINVAL, "unknown surrogate %d", d->surrogate);
+    if (d->grad_policy != ALIF_GRAD_DETACHED && d->grad_policy != ALIF_GRAD_ATTACHED)
+        return fail(ALIF_EINVAL, "unknown grad_policy %d", d->grad_policy);
     if (!(d->sg_slope >= 0.0f) || !std::isfinite(d->sg_slope)) return fail(ALIF_EINVAL, "bad sg_slope");
     const bool sp = d->input_kind != ALIF_INPUT_CURRENT_F32;
     if (sp) {
@@ -358,6 +360,8 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
     if ((rc = check_params(prm))) return rc;
     if (desc->algo == ALIF_ALGO_SEQUENTIAL_STEP)
         return fail(ALIF_EUNSUPPORTED, "the per-step-launch baseline is forward only");
+    if (desc->grad_policy == ALIF_GRAD_ATTACHED && desc->algo != ALIF_ALGO_SEQUENTIAL)
+        return fail(ALIF_EUNSUPPORTED, "attached gradients: the sequential backward only");
     if (desc->algo == ALIF_ALGO_SEQUENTIAL && p.TR > seq_bwd_max_tr(grad_v || grad_theta))
         return fail(ALIF_EUNSUPPORTED, "sequential backward supports T_R <= %d here",
                     seq_bwd_max_tr(grad_v || grad_theta));
@@ -414,6 +418,7 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
         a.dt = desc->dt_ms;
         a.slope = desc->sg_slope;
         a.surrogate = desc->surrogate;
+        a.attached = desc->grad_policy == ALIF_GRAD_ATTACHED;
         a.I = I;
         a.bias_k = bias_k;
         a.tau_m = prm->tau_mem_ms; a.tau_a = prm->tau_adapt_ms; a.d = prm->d; a.theta0 = prm->theta0;

@@ -103,6 +103,23 @@ __device__ __forceinline__ float surrogate_grad(float u, float k) {
     }
 }
 
+// The same three surrogates in FP64 (the attached sequential backward, whose
+// coupled recurrence amplifies input rounding).
+template <int SG>
+__device__ __forceinline__ double surrogate_grad_f64(double u, double k) {
+    if constexpr (SG == 1) {
+        return fabs(u) <= 0.5 ? 0.5 : 0.0;
+    } else if constexpr (SG == 2) {
+        const double rs2pi = 0.3989422804014327;   // 1 / sqrt(2 pi)
+        const double um = u - 3.0, up = u + 3.0;
+        return 1.15 * rs2pi / 0.5 * exp(-2.0 * u * u) -
+               0.15 * rs2pi / 3.0 * (exp(um * um * (-1.0 / 18.0)) + exp(up * up * (-1.0 / 18.0)));
+    } else {
+        const double q = k * fabs(u) + 1.0;
+        return 1.0 / (q * q);
+    }
+}
+
 // parameter sanity for the block method (positive threshold during refractory)
 __device__ __forceinline__ bool params_ok(float tm, float ta, float d, float th0) {
     return tm > 0.f && ta > 0.f && d >= 0.f && th0 > 0.f && isfinite(tm) && isfinite(ta) &&

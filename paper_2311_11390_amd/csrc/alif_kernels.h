@@ -65,6 +65,7 @@ struct SeqArgs {
     int B, T, N, TR, NB;
     double dt;
     int surrogate;  // enum alif_surrogate (backward)
+    int attached;   // gradient policy of the backward: 1 = attached
     float slope;
     const float *I;
     const float *bias_k;

@@ -8,11 +8,14 @@
 //    cost structure of a framework-level "standard" implementation.
 //  * k_seq_bwd: reverse over the T_R-step intervals; each interval is
 //    recomputed forward from its checkpoint into shared memory, then the
-//    adjoint recurrence runs backwards over it step by step.
+//    adjoint recurrence runs backwards over it step by step, under the detached
+//    gradient policy or the attached one (supplementary "Detaching gradients").
 //
 // The membrane and adaptation state are FP64 (FP64 vector math runs at the FP32
 // rate on CDNA4, and an FP32 per-step recurrence drifts by ~1e-5 over
 // thousands of small steps, which would flip near-threshold spikes).
+#include <type_traits>
+
 #include "alif_common.h"
 #include "alif_kernels.h"
 
@@ -178,9 +181,14 @@ __global__ __launch_bounds__(256) void k_seq_step(SeqArgs a) {
     }
 }
 
+__device__ __forceinline__ float rfma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double rfma(double a, double b, double c) { return fma(a, b, c); }
+
 // Sequential backward. Shared memory per lane and step of the current interval:
-// V, theta, a, x, gS (+ gV, gTheta) as float and a flag byte.
-template <bool GVT, int SG>
+// V, theta, a, x, gS (+ gV, gTheta) as float and a flag byte. ATT: attached
+// gradient policy, where dL/dS[t] also takes -c[t] lambda_V[t+1] + lambda_a[t+1]
+// with c[t] = beta V[t] + (1 - beta) gate[t+1] x[t+1] (the membrane the reset removes).
+template <bool GVT, int SG, bool ATT>
 __global__ __launch_bounds__(64) void k_seq_bwd(SeqArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     int b, n;
@@ -206,7 +214,17 @@ __global__ __launch_bounds__(64) void k_seq_bwd(SeqArgs a) {
     const int nc = L.valid ? n : N - 1;
     const float fbeta = (float)L.beta, fomb = (float)L.omb, fp = (float)L.p, fd = (float)L.d;
 
-    float lamV = 0.0f, lamA = 0.0f;
+    // The attached adjoint couples lambda_V and lambda_a at every step where the
+    // surrogate is nonzero and can grow by orders of magnitude (the wide
+    // multi-Gaussian); in FP32 its rounding reaches ~1e-3 relative. That policy
+    // therefore evaluates the surrogate, the coefficients, the recurrence and the
+    // sums in FP64 from the FP32-staged V, theta, a and x.
+    using R = typename std::conditional<ATT, double, float>::type;
+    const R rbeta = ATT ? (R)L.beta : (R)fbeta, romb = ATT ? (R)L.omb : (R)fomb;
+    const R rp = ATT ? (R)L.p : (R)fp, rd = ATT ? (R)L.d : (R)fd;
+    R lamV = 0, lamA = 0;
+    float x_next = 0.0f;   // attached: input (with bias) of the step after this block's last
+    bool pass_next = false;
     double acc[5] = {0, 0, 0, 0, 0};
     constexpr int CH = 8;  // loads issued a chunk at a time
     for (int nb = a.NB - 1; nb >= 0; nb--) {
@@ -248,28 +266,44 @@ __global__ __launch_bounds__(64) void k_seq_bwd(SeqArgs a) {
                 }
             }
         }
-        float pb = 0.f, pp = 0.f, pd = 0.f, pth = 0.f, pbias = 0.f;
+        R pb = 0, pp = 0, pd = 0, pth = 0, pbias = 0;
         for (int k = len - 1; k >= 0; k--) {
             const int q = k * 64 + lane;
             const uint8_t f = sF[q];
             const bool s = f & 1, pass = f & 2, sp = f & 4;
             const float V = sV[q], th = sTh[q], av_k = sA[q], x = sX[q];
-            const float sg = surrogate_grad<SG>(V - th, a.slope);
-            const float gsk = sGS[q] * sg;
-            const float cV = (GVT ? sGV[q] : 0.0f) + gsk;
-            const float lt = (GVT ? sGT[q] : 0.0f) - gsk;
-            lamV = fmaf(s ? 0.0f : fbeta, lamV, cV);
-            lamA = fmaf(fp, lamA, fd * lt);
+            R sg;
+            if constexpr (ATT) sg = surrogate_grad_f64<SG>((double)V - (double)th, (double)a.slope);
+            else sg = surrogate_grad<SG>(V - th, a.slope);
+            R lamS = sGS[q];
+            if constexpr (ATT) {
+                // lamV, lamA still hold step t + 1's values here (0 after the last step)
+                const float xn = k + 1 < len ? sX[q + 64] : x_next;
+                const bool pn = k + 1 < len ? (sF[q + 64] & 2) != 0 : pass_next;
+                const R c = rfma(rbeta, (R)V, pn ? romb * (R)xn : (R)0);
+                lamS = rfma(-c, lamV, lamS + lamA);
+            }
+            const R gsk = lamS * sg;
+            const R cV = (GVT ? (R)sGV[q] : (R)0) + gsk;
+            const R lt = (GVT ? (R)sGT[q] : (R)0) - gsk;
+            lamV = rfma(s ? (R)0 : rbeta, lamV, cV);
+            lamA = rfma(rp, lamA, rd * lt);
             const bool gate = pass && !sp;
-            const float gI = gate ? fomb * lamV : 0.0f;
+            const R gI = gate ? romb * lamV : (R)0;
             const float Vprev = k > 0 ? sV[q - 64] : v_in;
             const float aprev = k > 0 ? sA[q - 64] : a_in;
-            pb = fmaf(sp ? 0.0f : (Vprev - (pass ? x : 0.0f)), lamV, pb);
-            pp = fmaf(aprev, lamA, pp);
-            pd = fmaf(av_k, lt, pd);
+            pb = rfma(sp ? (R)0 : (R)(Vprev - (pass ? x : 0.0f)), lamV, pb);
+            pp = rfma((R)aprev, lamA, pp);
+            pd = rfma((R)av_k, lt, pd);
             pth += lt;
             pbias += gI;
-            if (a.gI) st_f32(rGI, L.valid ? (uint32_t)((tb + k) * N + n) * 4u : ALIF_OOB, gI);
+            if (a.gI) st_f32(rGI, L.valid ? (uint32_t)((tb + k) * N + n) * 4u : ALIF_OOB, (float)gI);
+            if constexpr (ATT) {
+                if (k == 0) {
+                    x_next = x;
+                    pass_next = pass;
+                }
+            }
         }
         acc[0] += pb;
         acc[1] += pp;
@@ -314,14 +348,19 @@ hipError_t launch_seq_bwd(const SeqArgs &a, hipStream_t st) {
     if (grid == 0) return hipSuccess;
     const bool gvt = a.gV || a.gTH;
     const size_t smem = seq_bwd_lds_bytes(a.TR, gvt);
-#define ALIF_SB(G)                                                                                \
+#define ALIF_SB(G, A)                                                                             \
     do {                                                                                          \
-        if (a.surrogate == 1) hipLaunchKernelGGL((k_seq_bwd<G, 1>), dim3(grid), dim3(64), smem, st, a); \
-        else if (a.surrogate == 2) hipLaunchKernelGGL((k_seq_bwd<G, 2>), dim3(grid), dim3(64), smem, st, a); \
-        else hipLaunchKernelGGL((k_seq_bwd<G, 0>), dim3(grid), dim3(64), smem, st, a);           \
+        if (a.surrogate == 1) hipLaunchKernelGGL((k_seq_bwd<G, 1, A>), dim3(grid), dim3(64), smem, st, a); \
+        else if (a.surrogate == 2) hipLaunchKernelGGL((k_seq_bwd<G, 2, A>), dim3(grid), dim3(64), smem, st, a); \
+        else hipLaunchKernelGGL((k_seq_bwd<G, 0, A>), dim3(grid), dim3(64), smem, st, a);        \
     } while (0)
-    if (gvt) ALIF_SB(true);
-    else ALIF_SB(false);
+    if (a.attached) {
+        if (gvt) ALIF_SB(true, true);
+        else ALIF_SB(false, true);
+    } else {
+        if (gvt) ALIF_SB(true, false);
+        else ALIF_SB(false, false);
+    }
 #undef ALIF_SB
     return hipGetLastError();
 }

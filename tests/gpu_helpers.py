@@ -41,14 +41,15 @@ def to_dev(prm: LayerParams):
 
 
 def gpu_forward(I, prm, dt, arp, algo=0, traces=True, save=False, init=None, want_final=False,
-                spike_dtype=0, surrogate=0):
+                spike_dtype=0, surrogate=0, grad_policy=0):
     import torch
 
     from paper_2311_11390_amd import alif
     It = torch.as_tensor(I, device="cuda").contiguous()
     P = to_dev(prm)
     f = alif.forward(It, P, dt, arp, algo=algo, want_v=traces, want_theta=traces, save=save,
-                     init=init, want_final=want_final, spike_dtype=spike_dtype, surrogate=surrogate)
+                     init=init, want_final=want_final, spike_dtype=spike_dtype, surrogate=surrogate,
+                     grad_policy=grad_policy)
     torch.cuda.synchronize()
     return f, It, P
 
