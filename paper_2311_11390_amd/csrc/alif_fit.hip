@@ -210,7 +210,10 @@ __global__ void __launch_bounds__(256) k_vr_combine(int B, int R, int N, int K, 
     }
 }
 
-template <int VEC>
+// RM: compile-time bound on the repeats (4 or 8), so that the weights and one
+// piece's target words sit in registers and every load of a piece is issued
+// before its arithmetic.
+template <int VEC, int RM>
 __global__ void __launch_bounds__(256) k_vr_grad(int B, int R, int T, int N, int ng, int K, int Lc, int S,
                                                  double lna, const uint8_t *__restrict__ x,
                                                  const uint8_t *__restrict__ y, const float *__restrict__ wts,
@@ -225,11 +228,11 @@ __global__ void __launch_bounds__(256) k_vr_grad(int B, int R, int T, int N, int
     const int n0 = j * VEC;
     const int t0 = k * Lc, t1 = min(T, t0 + Lc);
     const float a = (float)exp(lna);
-    float w[VR_MAX_R][VEC], W[VEC];
+    float w[RM][VEC], W[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; v++) W[v] = 0.f;
 #pragma unroll
-    for (int r = 0; r < VR_MAX_R; r++)
+    for (int r = 0; r < RM; r++)
 #pragma unroll
         for (int v = 0; v < VEC; v++) {
             w[r][v] = r < R ? wts[((size_t)b * R + r) * N + n0 + v] : 0.f;
@@ -243,7 +246,7 @@ __global__ void __launch_bounds__(256) k_vr_grad(int B, int R, int T, int N, int
         const size_t o = ((size_t)b * K + k) * R * N + n0 + v;
         double cc = 0.0, gg = 0.0;
 #pragma unroll
-        for (int r = 0; r < VR_MAX_R; r++)
+        for (int r = 0; r < RM; r++)
             if (r < R) {
                 cc = fma((double)w[r][v], ce[o + (size_t)r * N], cc);
                 gg = fma((double)w[r][v], cg[o + (size_t)r * N], gg);
@@ -260,6 +263,16 @@ __global__ void __launch_bounds__(256) k_vr_grad(int B, int R, int T, int N, int
     for (int s = s_last; s >= 0; s--, pw *= inv_a16) {
         const int ts = t0 + s * VR_SUB;
         const int len = min(VR_SUB, t1 - ts);
+        // all loads of the piece first: model spikes, every target, the checkpoints
+        typename Bytes<VEC>::W wx[VR_SUB], wy[RM][VR_SUB];
+#pragma unroll
+        for (int i = 0; i < VR_SUB; i++) {
+            const int t = i < len ? ts + i : ts;
+            wx[i] = load_w<VEC>(x, xrow + (size_t)t * N);
+#pragma unroll
+            for (int r = 0; r < RM; r++)
+                wy[r][i] = r < R ? load_w<VEC>(y, yrow + r * ytr + (size_t)t * N) : (typename Bytes<VEC>::W)0;
+        }
         float c[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; v++) {
@@ -267,40 +280,21 @@ __global__ void __launch_bounds__(256) k_vr_grad(int B, int R, int T, int N, int
             if (s > 0) {
                 const float *q = cp + (((size_t)b * K + k) * S + s) * R * N + n0 + v;
 #pragma unroll
-                for (int r = 0; r < VR_MAX_R; r++)
+                for (int r = 0; r < RM; r++)
                     if (r < R) cc = fma((double)w[r][v], (double)q[(size_t)r * N], cc);
             }
             c[v] = (float)cc;
         }
-        typename Bytes<VEC>::W wx[VR_SUB];
+        // drive m[t] = W x[t] - sum_r w_r y_r[t], then c[t] in place
         float cs[VR_SUB][VEC];
-#pragma unroll
-        for (int i = 0; i < VR_SUB; i++) {
-            const int t = i < len ? ts + i : ts;
-            wx[i] = load_w<VEC>(x, xrow + (size_t)t * N);
-#pragma unroll
-            for (int v = 0; v < VEC; v++) cs[i][v] = W[v] * Bytes<VEC>::get(wx[i], v);
-        }
-#pragma unroll
-        for (int r = 0; r < VR_MAX_R; r++) {
-            if (r >= R) break;
-            typename Bytes<VEC>::W wy[VR_SUB];
-#pragma unroll
-            for (int i = 0; i < VR_SUB; i++) {
-                const int t = i < len ? ts + i : ts;
-                wy[i] = load_w<VEC>(y, yrow + r * ytr + (size_t)t * N);
-            }
-#pragma unroll
-            for (int i = 0; i < VR_SUB; i++)
-#pragma unroll
-                for (int v = 0; v < VEC; v++) cs[i][v] = fmaf(-w[r][v], Bytes<VEC>::get(wy[i], v), cs[i][v]);
-        }
-        // cs holds the drive m[t]; turn it into c[t] in place
 #pragma unroll
         for (int i = 0; i < VR_SUB; i++)
 #pragma unroll
             for (int v = 0; v < VEC; v++) {
-                c[v] = fmaf(a, c[v], cs[i][v]);
+                float m = W[v] * Bytes<VEC>::get(wx[i], v);
+#pragma unroll
+                for (int r = 0; r < RM; r++) m = fmaf(-w[r][v], Bytes<VEC>::get(wy[r][i], v), m);
+                c[v] = fmaf(a, c[v], m);
                 cs[i][v] = c[v];
             }
 #pragma unroll
@@ -430,12 +424,17 @@ int alif_van_rossum(int32_t B, int32_t R, int32_t T, int32_t N, double dt_ms, do
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
     if (!grad) return ALIF_OK;
     const long long n = (long long)B * p.K * p.ng;
-    if (p.vec == 4)
-        hipLaunchKernelGGL(k_vr_grad<4>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, R, T, N, p.ng, p.K,
-                           p.Lc, p.S, lna, spikes, targets, wts, ce, cg, cp, grad);
-    else
-        hipLaunchKernelGGL(k_vr_grad<1>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, R, T, N, p.ng, p.K,
-                           p.Lc, p.S, lna, spikes, targets, wts, ce, cg, cp, grad);
+    const dim3 gg((unsigned)((n + 255) / 256)), bb(256);
+#define ALIF_VRG(V, RM) hipLaunchKernelGGL((k_vr_grad<V, RM>), gg, bb, 0, st, B, R, T, N, p.ng, p.K, p.Lc, p.S, lna, \
+                                           spikes, targets, wts, ce, cg, cp, grad)
+    if (p.vec == 4) {
+        if (R <= 4) ALIF_VRG(4, 4);
+        else ALIF_VRG(4, 8);
+    } else {
+        if (R <= 4) ALIF_VRG(1, 4);
+        else ALIF_VRG(1, 8);
+    }
+#undef ALIF_VRG
     e = hipGetLastError();
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
     return ALIF_OK;
