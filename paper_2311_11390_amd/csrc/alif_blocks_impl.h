@@ -602,7 +602,9 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     // With one segment per block there is no barrier to share, and each block's
     // membrane is computed in its own iteration instead.
     constexpr bool PIPE = SEG > 1;
-    constexpr bool RECOMP = L > 8;   // long segments: recompute instead of store (see below)
+    // recompute instead of store (see below): long segments, and 6-8 steps when the
+    // dL/dV, dL/dtheta inputs take the registers (T_R 64: 0.79 against 1.74 ms)
+    constexpr bool RECOMP = L > 8 || (GVT && L > 5);
     const auto par = [](int nb) { return (nb & 1) * Exch<SEG>::SIZE; };
     float vtn[L], thn[L];   // V~ and theta of the block the next iteration finishes
     if constexpr (PIPE) {
@@ -968,7 +970,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     // Depth 2 is still correct (the masked scan then waits on a load issued one
     // block earlier); it is used only for 16-step segments, whose per-block work
     // covers more of the latency and whose registers cannot hold a third slot.
-    static_assert(!PIPE || DEPTH >= 3 || RECOMP, "the backward pipeline reads the next block's slot one iteration early");
+    static_assert(!PIPE || DEPTH >= 3 || L >= 16, "the backward pipeline reads the next block's slot one iteration early");
     wait_vmem_all();
     int r0 = 0;
     for (; r0 + DEPTH <= a.NB; r0 += DEPTH) {
