@@ -62,6 +62,18 @@ def test_van_rossum_matches_oracle(B, R, T, N, dt, tau):
         f"{np.abs(gr - G).max() / np.abs(G).max():.2e}")
 
 
+@pytest.mark.parametrize("B,R,T,N", [(1, 1, 1, 4), (1, 2, 15, 5), (2, 3, 17, 8), (1, 5, 31, 3)])
+def test_van_rossum_short_trains(B, R, T, N):
+    """Trains shorter than one 16-step piece, or just over one, with one or four
+    neurons per thread and one or two repeat groups."""
+    x, y = _trains(77 + T, B, R, T, N, p=0.3)
+    log(f"[vr] short B={B} R={R} T={T} N={N}")
+    d, gr = _gpu_vr(x, y, 0.5, 3.0, 0.25)
+    D, G = oracle.van_rossum(x, y, 0.5, 3.0, 0.25)
+    np.testing.assert_allclose(d, D, rtol=2e-6, atol=1e-7)
+    np.testing.assert_allclose(gr, G, rtol=0, atol=_grad_tol(T, G))
+
+
 def test_van_rossum_outputs_alone_and_empty():
     import torch
 
