@@ -194,6 +194,29 @@ int alif_input_current(const alif_desc *desc, const void *input, const float *W,
                        const float *bias, float *current, void *stream);
 
 /*
+ * The same input current of Eq. 3, I~[b][t][i] = bias[i] + sum_j W[i][j] x[b][t][j],
+ * computed from the active inputs only: for each (b, t) row the nonzero entries
+ * of x are gathered and their weight columns summed in increasing input order
+ * (FP32, value times weight), instead of a dense MFMA GEMM. For sparse spike
+ * trains (a few percent of the entries or fewer) this moves the bytes the
+ * result needs instead of doing n_in multiply-adds per output.
+ *   desc     B, T, n_in, n_neurons and a spike input_kind (gemm_precision ignored)
+ *   input    device spikes [B][T][n_in] of desc->input_kind (any values, 0 skipped)
+ *   WT       device float [n_in][N]: W transposed (alif_transpose(N, n_in, W, WT))
+ *   bias     device float [N] or NULL;  current  device float [B][T][N] output
+ * Pass `current` to alif_forward as ALIF_INPUT_CURRENT_F32 input (with bias NULL
+ * in that call's params, or computed here with bias NULL). The dW and dx of the
+ * backward are alif_weight_grad and alif_input_grad as for the GEMM path.
+ * ALIF_EUNSUPPORTED for n_in > 16384 or B * T >= 2^31.
+ *
+ * alif_transpose: out[c][r] = in[r][c] for a device float rows x cols matrix
+ * (out must not alias in).
+ */
+int alif_transpose(int32_t rows, int32_t cols, const float *in, float *out, void *stream);
+int alif_input_current_events(const alif_desc *desc, const void *input, const float *WT, const float *bias,
+                              float *current, void *stream);
+
+/*
  * Gradients of the Eq. 3 projection for a spike-input layer, given the gradient
  * of the loss with respect to its input current (what alif_backward writes to
  * grad_current), as MFMA GEMMs in desc->gemm_precision (BF16 rounds

@@ -91,6 +91,8 @@ _SIGNATURES = {
                                 _P, _P, _P, _P]),
     "alif_adam_step": (c_int, [c_int32, _P, _P, _P, _P, c_int32, c_double, c_double, c_double, c_double,
                                c_float, c_float, _P]),
+    "alif_transpose": (c_int, [c_int32, c_int32, _P, _P, _P]),
+    "alif_input_current_events": (c_int, [POINTER(AlifDesc), _P, _P, _P, _P, _P]),
     "alif_device_status": (c_int, [POINTER(c_uint32), _P]),
     "alif_last_error": (ctypes.c_char_p, []),
     "alif_ou_workspace_bytes": (c_int, [c_int32, c_int32, POINTER(c_size_t)]),

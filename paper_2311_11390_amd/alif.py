@@ -253,6 +253,28 @@ def input_current(x: torch.Tensor, W: torch.Tensor, bias=None, gemm_precision=L.
     return out
 
 
+def transpose(m: torch.Tensor) -> torch.Tensor:
+    """float32 [rows][cols] -> [cols][rows] on the device (alif_transpose)."""
+    assert m.dtype == torch.float32 and m.is_contiguous() and m.dim() == 2
+    out = torch.empty(m.shape[1], m.shape[0], dtype=torch.float32, device=m.device)
+    L.check(L.load().alif_transpose(m.shape[0], m.shape[1], _p(m), _p(out), _stream(m.device)))
+    return out
+
+
+def input_current_events(x: torch.Tensor, WT: torch.Tensor, bias=None, out=None):
+    """Eq. 3's current from the active inputs only (alif_input_current_events):
+    x spikes [B][T][n_in] (uint8, bfloat16 or float32), WT = W transposed [n_in][N]."""
+    assert x.is_contiguous() and WT.dtype == torch.float32 and WT.is_contiguous()
+    B, T, n_in = x.shape
+    N = WT.shape[1]
+    assert WT.shape[0] == n_in
+    desc = make_desc(B, T, N, 1.0, 2.0, n_in, _INPUT_KIND[x.dtype])
+    cur = out if out is not None else torch.empty(B, T, N, dtype=torch.float32, device=x.device)
+    L.check(L.load().alif_input_current_events(ctypes.byref(desc), _p(x), _p(WT), _p(bias), _p(cur),
+                                               _stream(x.device)))
+    return cur
+
+
 def weight_grad(grad_current: torch.Tensor, x: torch.Tensor, gemm_precision=L.GEMM_FP32, workspace=None):
     """grad_W [N][n_in] = sum_{b,t} grad_current[b][t][:]^T x[b][t][:] (alif_weight_grad)."""
     B, T, n_in = x.shape
