@@ -153,7 +153,8 @@ def three_layer_leg(steps, warmup, seed=4):
     One step = the three forward layers (Eq. 3 GEMM + block kernels) and the
     backward chain of loss = sum of last-layer spikes (block backward, then
     dW = gI^T x and dx = gI W per layer). Also times every GEMM of the step on
-    its own, against the BF16 MFMA peak."""
+    its own, against the BF16 MFMA peak, and each layer's forward current from
+    its active inputs alone (the event kernel) beside the GEMM."""
     import torch
 
     from paper_2311_11390_amd import _lib as L
@@ -192,7 +193,7 @@ def three_layer_leg(steps, warmup, seed=4):
     ms = (time.perf_counter() - t0) / steps * 1e3
     neurons = sum(W.shape[0] for W in Ws)
     spikes = [int(f["spikes"].sum().item()) for f in st["fs"]]
-    gemms = {}
+    gemms, events = {}, {}
     for li, (W, h) in enumerate(zip(Ws, st["ins"])):
         N, K = W.shape
         M = B * T
@@ -206,14 +207,24 @@ def three_layer_leg(steps, warmup, seed=4):
             t = _event_ms(fn, 5)
             tf = flops / (t * 1e-3) / 1e12
             gemms[name] = {"ms": t, "tflops": tf, "frac_of_peak": tf / MFMA_PEAK_TFLOPS["bf16"]}
-        del gI
+        # the same current from the active inputs only (FP32 weights, W transposed once)
+        WT = alif.transpose(W)
+        t = _event_ms(lambda: alif.input_current_events(h, WT), 5)
+        t_gemm = gemms[f"L{li + 1} I = x W^T ({K} -> {N})"]["ms"]
+        ev_bytes = M * (K * h.element_size() + 4 * N)     # inputs read + current written (HBM)
+        events[f"L{li + 1} ({K} -> {N})"] = {"ms": t, "active_fraction": float((h != 0).float().mean().item()),
+                                             "speedup_vs_bf16_gemm": t_gemm / t,
+                                             "algorithmic_bytes": ev_bytes,
+                                             "hbm_gbps": ev_bytes / (t * 1e-3) / 1e9,
+                                             "frac_of_hbm_peak": ev_bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del gI, WT
     del st["fs"], st["ins"]
     torch.cuda.synchronize()
     return {"workload": "three-layer 700 -> 1024 -> 1024 -> 20, B 128, T 2000, DT 0.5 ms, T_R 4, driven; "
                         "loss = sum of last-layer spikes; BF16 GEMMs (FP32 accumulate), uint8 spikes",
             "ms_per_step": ms, "value": B * T * neurons / (ms * 1e-3), "unit": "neuron-steps/s",
             "steps": steps, "spikes_per_layer": spikes,
-            "gemm_peak_tflops": MFMA_PEAK_TFLOPS["bf16"], "gemms": gemms}
+            "gemm_peak_tflops": MFMA_PEAK_TFLOPS["bf16"], "gemms": gemms, "event_current": events}
 
 
 def shd_like_leg(steps, warmup, seed=3):

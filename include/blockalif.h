@@ -196,8 +196,9 @@ int alif_input_current(const alif_desc *desc, const void *input, const float *W,
 /*
  * The same input current of Eq. 3, I~[b][t][i] = bias[i] + sum_j W[i][j] x[b][t][j],
  * computed from the active inputs only: for each (b, t) row the nonzero entries
- * of x are gathered and their weight columns summed in increasing input order
- * (FP32, value times weight), instead of a dense MFMA GEMM. For sparse spike
+ * of x are found and their weight columns summed (FP32, value times weight; the
+ * order is fixed by n_in, the input kind and the row alignment, so results are
+ * reproducible), instead of a dense MFMA GEMM. For sparse spike
  * trains (a few percent of the entries or fewer) this moves the bytes the
  * result needs instead of doing n_in multiply-adds per output.
  *   desc     B, T, n_in, n_neurons and a spike input_kind (gemm_precision ignored)
@@ -207,7 +208,9 @@ int alif_input_current(const alif_desc *desc, const void *input, const float *W,
  * Pass `current` to alif_forward as ALIF_INPUT_CURRENT_F32 input (with bias NULL
  * in that call's params, or computed here with bias NULL). The dW and dx of the
  * backward are alif_weight_grad and alif_input_grad as for the GEMM path.
- * ALIF_EUNSUPPORTED for n_in > 16384 or B * T >= 2^31.
+ * Entries whose magnitude is zero (+0 and -0) are skipped. Buffers must be aligned
+ * to their element type (ALIF_EINVAL otherwise); rows that start on 4-byte
+ * boundaries are read as 32-bit words. ALIF_EUNSUPPORTED for n_in > 16384.
  *
  * alif_transpose: out[c][r] = in[r][c] for a device float rows x cols matrix
  * (out must not alias in).

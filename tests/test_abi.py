@@ -232,3 +232,26 @@ def test_van_rossum_and_adam_validation_host_side():
     assert adam(10, dummy, dummy, dummy, dummy, 1, 0.1, 0.9, 0.999, 1e-8, 2.0, 1.0, None) == L.ALIF_EINVAL
     assert adam(10, None, dummy, dummy, dummy, 1, 0.1, 0.9, 0.999, 1e-8, 0.0, 1.0, None) == L.ALIF_EINVAL
     assert adam(0, None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, 0.0, 1.0, None) == L.ALIF_OK
+
+
+def test_event_current_and_transpose_validation_host_side():
+    """alif_input_current_events and alif_transpose reject bad arguments before any
+    device call."""
+    lib = L.load()
+    by = ctypes.byref
+    dummy = ctypes.c_void_p(256)
+    ev = lib.alif_input_current_events
+    assert ev(None, dummy, dummy, None, dummy, None) == L.ALIF_EINVAL
+    assert ev(by(_desc()), dummy, dummy, None, dummy, None) == L.ALIF_EINVAL          # current input kind
+    assert b"spike input_kind" in lib.alif_last_error()
+    assert ev(by(_desc(input_kind=1, n_in=20000)), dummy, dummy, None, dummy, None) == L.ALIF_EUNSUPPORTED
+    assert ev(by(_desc(input_kind=1, n_in=16)), None, dummy, None, dummy, None) == L.ALIF_EINVAL
+    bf16 = _desc(input_kind=L.INPUT_SPIKES_BF16, n_in=16)
+    assert ev(by(bf16), ctypes.c_void_p(257), dummy, None, dummy, None) == L.ALIF_EINVAL   # odd bf16 address
+    assert b"aligned" in lib.alif_last_error()
+    assert ev(by(_desc(input_kind=1, n_in=16)), dummy, ctypes.c_void_p(258), None, dummy, None) == L.ALIF_EINVAL
+    assert ev(by(_desc(input_kind=1, n_in=16, batch=0)), None, None, None, None, None) == L.ALIF_OK
+    tr = lib.alif_transpose
+    assert tr(-1, 4, dummy, dummy, None) == L.ALIF_EINVAL
+    assert tr(4, 4, dummy, dummy, None) == L.ALIF_EINVAL                                  # aliasing
+    assert tr(0, 4, None, None, None) == L.ALIF_OK

@@ -37,7 +37,8 @@ def test_transpose(rows, cols):
 @pytest.mark.parametrize("kind", ["u8", "bf16", "f32"])
 @pytest.mark.parametrize("B,T,n_in,N,p", [(2, 301, 700, 260, 0.01), (1, 500, 1024, 20, 0.05),
                                           (3, 70, 37, 19, 0.3), (2, 64, 256, 1024, 0.0),
-                                          (1, 40, 300, 130, 1.0)])
+                                          (1, 40, 300, 130, 1.0), (1, 30, 2100, 1500, 0.02),
+                                          (1, 1_100_000, 8, 4, 0.2)])
 def test_input_current_events_matches_oracle(kind, B, T, n_in, N, p):
     import torch
 
@@ -91,3 +92,28 @@ def test_events_layer_equals_gemm_layer_spikes():
     rep_gm = check_forward(s_gm, oracle.input_current(x, W.astype(np.float64), None), prm, dt, 2.0)
     log(f"    spikes {int(s_ev.sum())} / {int(s_gm.sum())}, excused {rep_ev['excused']} / {rep_gm['excused']}, "
         f"differing {int((s_ev != s_gm).sum())}")
+
+
+@pytest.mark.parametrize("kind,off", [("u8", 1), ("u8", 2), ("u8", 3), ("bf16", 1)])
+def test_input_current_events_unaligned_rows(kind, off):
+    """Input views that do not start on a 4-byte boundary (element loads instead of
+    word loads) give the oracle's current within the same FP32 bound."""
+    import torch
+
+    from paper_2311_11390_amd import alif
+    B, T, n_in, N, p = 2, 90, 130, 70, 0.05
+    g = rng(400 + off)
+    x = bernoulli_spikes(g, (B, T, n_in), p)
+    W = normal_weights(g, N, n_in)
+    flat = _as_torch_spikes(x, kind).reshape(-1)
+    buf = torch.zeros(flat.numel() + off, dtype=flat.dtype, device="cuda")
+    buf[off:] = flat
+    xv = buf[off:].view(B, T, n_in)
+    assert xv.data_ptr() % 4 != 0
+    log(f"[events] unaligned {kind} offset {off}")
+    out = alif.input_current_events(xv, alif.transpose(torch.as_tensor(W, device="cuda")))
+    torch.cuda.synchronize()
+    ref = oracle.input_current(x, W.astype(np.float64), None)
+    absum = x.astype(np.float64) @ np.abs(W.astype(np.float64)).T
+    bound = ((x != 0).sum(axis=2, keepdims=True) + 1) * 2.0 ** -24 * absum + 1e-30
+    assert (np.abs(np_(out) - ref) <= bound).all()
