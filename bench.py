@@ -193,6 +193,35 @@ def three_layer_leg(steps, warmup, seed=4):
     ms = (time.perf_counter() - t0) / steps * 1e3
     neurons = sum(W.shape[0] for W in Ws)
     spikes = [int(f["spikes"].sum().item()) for f in st["fs"]]
+    # the same step with each forward current from the active inputs (event kernel, FP32 weights; W transposed
+    # in the step, as after every optimiser update); the backward is the block backward to gI and the same BF16
+    # dW / dx GEMMs
+    def step_events():
+        h, fs, ins, curs = x, [], [], []
+        for W, P in zip(Ws, Ps):
+            cur = alif.input_current_events(h, alif.transpose(W))
+            f = alif.forward(cur, P, w.dt, w.arp, spike_dtype=L.SPIKES_U8, save=True)
+            fs.append(f)
+            ins.append(h)
+            curs.append(cur)
+            h = f["spikes"]
+        g = torch.ones(h.shape, dtype=torch.float32, device=dev)
+        for li in reversed(range(len(Ws))):
+            gI = alif.backward(fs[li], curs[li], Ps[li], grad_spikes=g, want_grad_current=True)["grad_current"]
+            alif.weight_grad(gI, ins[li], gemm_precision=prec)
+            g = alif.input_grad(gI, Ws[li], L.INPUT_SPIKES_U8, gemm_precision=prec) if li > 0 else None
+        st["ev_fs"] = fs
+
+    for _ in range(warmup):
+        step_events()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step_events()
+    torch.cuda.synchronize()
+    ms_ev = (time.perf_counter() - t0) / steps * 1e3
+    st["ev_spikes"] = [int(f["spikes"].sum().item()) for f in st.pop("ev_fs")]
+
     gemms, events = {}, {}
     for li, (W, h) in enumerate(zip(Ws, st["ins"])):
         N, K = W.shape
@@ -224,7 +253,10 @@ def three_layer_leg(steps, warmup, seed=4):
                         "loss = sum of last-layer spikes; BF16 GEMMs (FP32 accumulate), uint8 spikes",
             "ms_per_step": ms, "value": B * T * neurons / (ms * 1e-3), "unit": "neuron-steps/s",
             "steps": steps, "spikes_per_layer": spikes,
-            "gemm_peak_tflops": MFMA_PEAK_TFLOPS["bf16"], "gemms": gemms, "event_current": events}
+            "gemm_peak_tflops": MFMA_PEAK_TFLOPS["bf16"], "gemms": gemms, "event_current": events,
+            "event_forward_step": {"ms_per_step": ms_ev, "value": B * T * neurons / (ms_ev * 1e-3),
+                                   "spikes_per_layer": st["ev_spikes"],
+                                   "kind": "forward currents by the event kernel (FP32 W), backward as above"}}
 
 
 def shd_like_leg(steps, warmup, seed=3):
