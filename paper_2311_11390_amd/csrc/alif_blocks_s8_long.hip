@@ -5,5 +5,6 @@
 namespace alif {
 ALIF_INSTANTIATE(8, 10)
 ALIF_INSTANTIATE(8, 12)
+ALIF_INSTANTIATE(8, 13)
 ALIF_INSTANTIATE(8, 16)
 }  // namespace alif
