@@ -109,6 +109,16 @@ def input_current(x: np.ndarray, W: np.ndarray, bias=None) -> np.ndarray:
     return out.reshape(*lead, n)
 
 
+def input_current_values(x: np.ndarray, W: np.ndarray, bias=None) -> np.ndarray:
+    """Eq. 3's projection b + W x with real-valued inputs x[..., n_in] in place of binary
+    spikes (spike counts per step, or graded values): one FP64 matrix product. For 0/1
+    inputs it is the spike sum of input_current."""
+    out = np.asarray(x, dtype=np.float64) @ _c64(W).T
+    if bias is not None:
+        out = out + _c64(bias)
+    return out
+
+
 def weight_grad(gI: np.ndarray, x: np.ndarray) -> np.ndarray:
     """Gradient with respect to W of the Eq. 3 projection I = b + W x, given the
     current gradient gI[..., n]: dL/dW[n][i] = sum over (b, t) of gI[n] x[i]

@@ -117,3 +117,36 @@ def test_input_current_events_unaligned_rows(kind, off):
     absum = x.astype(np.float64) @ np.abs(W.astype(np.float64)).T
     bound = ((x != 0).sum(axis=2, keepdims=True) + 1) * 2.0 ** -24 * absum + 1e-30
     assert (np.abs(np_(out) - ref) <= bound).all()
+
+
+@pytest.mark.parametrize("kind", ["u8", "bf16", "f32"])
+def test_input_current_events_weights_values(kind):
+    """Non-binary inputs are weighted by their value: spike counts 0-3 (u8), graded
+    values exact in bfloat16, and FP32 values with -0.0 entries (skipped), against the
+    oracle's real-valued projection within the FP32 bound."""
+    import torch
+
+    from paper_2311_11390_amd import alif
+    B, T, n_in, N = 2, 150, 300, 200
+    g = rng(500 + len(kind))
+    on = g.random((B, T, n_in)) < 0.05
+    if kind == "u8":
+        x = (on * g.integers(1, 4, (B, T, n_in))).astype(np.uint8)
+        xt = torch.as_tensor(x, device="cuda")
+    elif kind == "bf16":
+        x = (on * g.choice([0.5, -1.25, 3.0, 0.375], (B, T, n_in))).astype(np.float32)
+        xt = torch.as_tensor(x, device="cuda").to(torch.bfloat16)
+    else:
+        x = (on * g.standard_normal((B, T, n_in))).astype(np.float32)
+        x[~on & (g.random((B, T, n_in)) < 0.5)] = -0.0
+        xt = torch.as_tensor(x, device="cuda")
+    W = normal_weights(g, N, n_in)
+    b = g.standard_normal(N).astype(np.float32)
+    log(f"[events] values {kind}")
+    out = alif.input_current_events(xt.contiguous(), alif.transpose(torch.as_tensor(W, device="cuda")),
+                                    torch.as_tensor(b, device="cuda"))
+    torch.cuda.synchronize()
+    ref = oracle.input_current_values(x, W, b)
+    absum = np.abs(x.astype(np.float64)) @ np.abs(W.astype(np.float64)).T + np.abs(b)
+    bound = ((x != 0).sum(axis=2, keepdims=True) + 1) * 2.0 ** -24 * absum + 1e-30
+    assert (np.abs(np_(out) - ref) <= bound).all()
