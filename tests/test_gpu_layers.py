@@ -55,7 +55,7 @@ def test_input_current_gemm(kind, prec, shape):
 # three-layer output layer); a narrow input with 7 K splits of unequal use; a
 # 25-way split; n_in not a multiple of 4 (the general kernel)
 _GRAD_SHAPES = [(2, 301, 700, 260), (1, 500, 1024, 20), (3, 700, 36, 132), (4, 2000, 200, 100),
-                (2, 77, 37, 19)]
+                (2, 77, 37, 19), (1, 90, 300, 1), (1, 64, 130, 32), (1, 64, 130, 33), (3, 41, 1, 7)]
 
 
 def _gemm_bound(a, b, n):
