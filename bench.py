@@ -53,8 +53,8 @@ def algorithmic_bytes(TR):
 HERE = os.path.dirname(os.path.abspath(__file__))
 COUNTERS = os.path.join(HERE, "profiles", "block_fwd_bwd_fine_dt_hbm_counters.md")
 KERNEL_SOURCES = ["alif_blocks.hip", "alif_blocks_impl.h", "alif_blocks_s1.hip", "alif_blocks_s2.hip",
-                  "alif_blocks_s4.hip", "alif_blocks_s8.hip", "alif_blocks_s8_long.hip", "alif_common.h",
-                  "alif_kernels.h"]
+                  "alif_blocks_s4.hip", "alif_blocks_s8.hip", "alif_blocks_s8_long.hip", "alif_blocks_s8_xl.hip",
+                  "alif_common.h", "alif_kernels.h"]
 
 
 def kernel_sources_digest():
@@ -306,7 +306,7 @@ def speedup_sweep(steps=5, warmup=2):
     dataset (rate per batch element ~ U[0, 200] Hz, one step = 1 ms), 200 inputs,
     ALIF layers with loss = total last-layer spike count, forward and backward
     (FP32 GEMMs, dW for every layer, dx between layers), B 64.
-      * T in {512, 2048} x T_R in {2, 5, 10, 20, 40, 64, 80, 100} (the sequential
+      * T in {512, 2048} x T_R in {2, 5, 10, 20, 40, 64, 80, 100, 120} (the sequential
         backward stages a block in LDS, which fits T_R <= 121), one layer of 256;
       * T = 1024, T_R = 40: 1-3 layers of 128, 256 or 512 units;
       * the supplementary's single-layer forward shape: 200 -> 100, T 1000, B 128, T_R 50.
@@ -319,7 +319,7 @@ def speedup_sweep(steps=5, warmup=2):
     from paper_2311_11390_amd import alif
     from paper_2311_11390_amd.synth import speed_benchmark
     dev = "cuda"
-    configs = [(T, TR, (256,), 64) for T in (512, 2048) for TR in (2, 5, 10, 20, 40, 64, 80, 100)]
+    configs = [(T, TR, (256,), 64) for T in (512, 2048) for TR in (2, 5, 10, 20, 40, 64, 80, 100, 120)]
     configs += [(1024, 40, (h,) * n, 64) for n in (1, 2, 3) for h in (128, 256, 512)]
     configs += [(1000, 50, (100,), 128)]   # the single-layer forward timing shape of the supplementary
     rows = []

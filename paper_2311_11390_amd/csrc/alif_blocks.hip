@@ -74,12 +74,14 @@ BlockConfig block_config(int TR) {
     if (TR <= 80) return {8, 10};
     if (TR <= 96) return {8, 12};
     if (TR <= 104) return {8, 13};
+    if (TR <= 112) return {8, 14};
+    if (TR <= 120) return {8, 15};
     return {8, 16};
 }
 int block_neurons_per_wg(int seg) { return 64 * (seg >= 4 ? 1 : 4 / seg); }
 
 #define ALIF_CONFIGS(X) X(1, 2) X(1, 3) X(1, 4) X(2, 3) X(2, 4) X(4, 3) X(4, 4) X(4, 5) X(4, 6) \
-    X(4, 8) X(8, 5) X(8, 6) X(8, 8) X(8, 10) X(8, 12) X(8, 13) X(8, 16)
+    X(4, 8) X(8, 5) X(8, 6) X(8, 8) X(8, 10) X(8, 12) X(8, 13) X(8, 14) X(8, 15) X(8, 16)
 
 #define ALIF_EXTERN(S, L)                                                                  \
     extern template hipError_t blocks_fwd_launch<S, L>(const FwdArgs &, hipStream_t);     \

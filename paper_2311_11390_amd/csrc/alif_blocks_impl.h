@@ -968,7 +968,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     // i + 1 (mod DEPTH) block nb - 1; DEPTH >= 3 keeps a whole iteration between
     // a slot's prefetch and its first use by the masked scan.
     // Depth 2 is still correct (the masked scan then waits on a load issued one
-    // block earlier); it is used only for 13- and 16-step segments, whose per-block work
+    // block earlier); it is used only for 13-16-step segments, whose per-block work
     // covers more of the latency and whose registers cannot hold a third slot.
     static_assert(!PIPE || DEPTH >= 3 || L >= 13, "the backward pipeline reads the next block's slot one iteration early");
     wait_vmem_all();
@@ -1030,8 +1030,8 @@ constexpr int fwd_depth() {   // <= 64 prefetched floats per lane
 }
 template <int SEG, int L>
 constexpr int bwd_depth() {   // <= 12 prefetched steps (x, dL/dS and maybe dL/dV, dL/dtheta) per lane
-    // 13- and 16-step segments: two slots (a third would spill; measured 0.84 against
-    // 1.46 ms at T_R = 128 on 4 x 2048 x 20000). 10-12 steps keep three (0.63 against 0.71 ms).
+    // 13-16-step segments: two slots (a third would spill; measured 0.84 against 1.46 ms
+    // at T_R = 128 on 4 x 2048 x 20000). 10-12 steps keep three (0.63 against 0.71 ms).
     return L >= 13 ? 2 : clamp_depth((ALIF_BWD_AHEAD + SEG * L - 1) / (SEG * L), ALIF_BWD_MIN_DEPTH, 12 / L);
 }
 

@@ -44,13 +44,13 @@ def _run(TR, dt, algo, seed, B=2, N=67, T=None, gv=True, bias=True):
 
 @pytest.mark.parametrize("TR,dt", [(2, 1.0), (3, 2.0 / 3.0), (4, 0.5), (5, 0.4), (8, 0.25), (11, 2.0 / 11),
                                    (16, 0.125), (20, 0.1), (23, 2.0 / 23), (31, 2.0 / 31), (40, 0.05),
-                                   (47, 2.0 / 47), (64, 2.0 / 64), (80, 0.025), (100, 0.02), (104, 2.0 / 104),
+                                   (47, 2.0 / 47), (64, 2.0 / 64), (80, 0.025), (100, 0.02), (104, 2.0 / 104), (110, 0.02), (120, 2.0 / 120),
                                    (128, 2.0 / 128)])
 def test_blocks_backward_matches_oracle(TR, dt):
     _run(TR, dt, 0, 500 + TR)
 
 
-@pytest.mark.parametrize("TR,dt", [(2, 1.0), (40, 0.05), (80, 0.025), (100, 0.02), (104, 2.0 / 104),
+@pytest.mark.parametrize("TR,dt", [(2, 1.0), (40, 0.05), (80, 0.025), (100, 0.02), (104, 2.0 / 104), (110, 0.02), (120, 2.0 / 120),
                                    (128, 2.0 / 128)])
 def test_blocks_backward_spike_grad_only(TR, dt):
     _run(TR, dt, 0, 600 + TR, gv=False, bias=False)

@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 # (T_R, DT) pairs covering every (segments, steps-per-segment) kernel variant
 TR_CASES = [(2, 1.0), (3, 2.0 / 3.0), (4, 0.5), (5, 0.4), (8, 0.25), (11, 2.0 / 11), (16, 0.125),
             (20, 0.1), (23, 2.0 / 23), (31, 2.0 / 31), (40, 0.05), (47, 2.0 / 47), (64, 2.0 / 64),
-            (80, 0.025), (100, 0.02), (104, 2.0 / 104), (128, 2.0 / 128)]
+            (80, 0.025), (100, 0.02), (104, 2.0 / 104), (110, 0.02), (120, 2.0 / 120), (128, 2.0 / 128)]
 
 
 @pytest.mark.parametrize("TR,dt", TR_CASES)
