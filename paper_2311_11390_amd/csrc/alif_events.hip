@@ -16,7 +16,8 @@
 // row of one input is contiguous. Word loads matter: with one byte per lane the
 // input read is bound by requests in flight, not by bytes. The HBM bytes per row
 // are the row's inputs and the N floats written; the active rows of WT come from
-// L2 (a layer-sized W fits).
+// L2 (a layer-sized W fits), and the current is written with non-temporal stores
+// so that streaming it out does not evict WT.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -130,9 +131,10 @@ __global__ __launch_bounds__(64 * EV_WAVES) void k_events_current(long long M, i
 #pragma unroll
                 for (int q = 0; q < CT; q++) acc[q] = fmaf(held_v, ok[q] ? wa[64 * q] : 0.0f, acc[q]);
             }
+            // the current streams out once: non-temporal stores keep WT's rows in L2
 #pragma unroll
             for (int q = 0; q < CT; q++)
-                if (ok[q]) crow[c0 + lane + 64 * q] = acc[q];
+                if (ok[q]) __builtin_nontemporal_store(acc[q], crow + c0 + lane + 64 * q);
         }
     }
 }
