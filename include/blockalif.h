@@ -210,10 +210,10 @@ int alif_input_current(const alif_desc *desc, const void *input, const float *W,
  * backward are alif_weight_grad and alif_input_grad as for the GEMM path.
  * Entries whose magnitude is zero (+0 and -0) are skipped. Buffers must be aligned
  * to their element type (ALIF_EINVAL otherwise); rows that start on 4-byte
- * boundaries are read as 32-bit words. ALIF_EUNSUPPORTED for n_in > 16384.
+ * boundaries are read as 32-bit words.
  *
  * alif_transpose: out[c][r] = in[r][c] for a device float rows x cols matrix
- * (out must not alias in).
+ * (out must not alias in; ALIF_EUNSUPPORTED for rows > 65535 * 32).
  */
 int alif_transpose(int32_t rows, int32_t cols, const float *in, float *out, void *stream);
 int alif_input_current_events(const alif_desc *desc, const void *input, const float *WT, const float *bias,

@@ -30,7 +30,6 @@ namespace {
 
 constexpr int EV_WAVES = 4;        // waves (rows in flight) per workgroup
 constexpr int EV_KW = 4;           // words per lane per chunk
-constexpr int EV_MAX_IN = 16384;
 constexpr long long EV_MAX_GROUPS = 1 << 18;
 
 template <int KIND>
@@ -209,7 +208,6 @@ int alif_input_current_events(const alif_desc *desc, const void *input, const fl
         return alif::set_error(ALIF_EINVAL, "alif_input_current_events needs a spike input_kind");
     if (desc->batch < 0 || desc->T < 0 || desc->n_neurons < 0 || desc->n_in < 0)
         return alif::set_error(ALIF_EINVAL, "negative size");
-    if (desc->n_in > EV_MAX_IN) return alif::set_error(ALIF_EUNSUPPORTED, "event current: n_in > 16384");
     const long long M = (long long)desc->batch * desc->T;
     const int n_in = desc->n_in, N = desc->n_neurons;
     if (M == 0 || N == 0) return ALIF_OK;

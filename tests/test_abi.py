@@ -244,7 +244,7 @@ def test_event_current_and_transpose_validation_host_side():
     assert ev(None, dummy, dummy, None, dummy, None) == L.ALIF_EINVAL
     assert ev(by(_desc()), dummy, dummy, None, dummy, None) == L.ALIF_EINVAL          # current input kind
     assert b"spike input_kind" in lib.alif_last_error()
-    assert ev(by(_desc(input_kind=1, n_in=20000)), dummy, dummy, None, dummy, None) == L.ALIF_EUNSUPPORTED
+    assert ev(by(_desc(input_kind=1, n_in=-1)), dummy, dummy, None, dummy, None) == L.ALIF_EINVAL
     assert ev(by(_desc(input_kind=1, n_in=16)), None, dummy, None, dummy, None) == L.ALIF_EINVAL
     bf16 = _desc(input_kind=L.INPUT_SPIKES_BF16, n_in=16)
     assert ev(by(bf16), ctypes.c_void_p(257), dummy, None, dummy, None) == L.ALIF_EINVAL   # odd bf16 address

@@ -38,7 +38,7 @@ def test_transpose(rows, cols):
 @pytest.mark.parametrize("B,T,n_in,N,p", [(2, 301, 700, 260, 0.01), (1, 500, 1024, 20, 0.05),
                                           (3, 70, 37, 19, 0.3), (2, 64, 256, 1024, 0.0),
                                           (1, 40, 300, 130, 1.0), (1, 30, 2100, 1500, 0.02),
-                                          (1, 1_100_000, 8, 4, 0.2)])
+                                          (1, 1_100_000, 8, 4, 0.2), (1, 6, 20000, 70, 0.01)])
 def test_input_current_events_matches_oracle(kind, B, T, n_in, N, p):
     import torch
 
