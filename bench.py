@@ -238,7 +238,7 @@ def three_layer_leg(steps, warmup, seed=4):
             gemms[name] = {"ms": t, "tflops": tf, "frac_of_peak": tf / MFMA_PEAK_TFLOPS["bf16"]}
         # the same current from the active inputs only (FP32 weights, W transposed once)
         WT = alif.transpose(W)
-        t = _event_ms(lambda: alif.input_current_events(h, WT), 5)
+        t = _event_ms(lambda: alif.input_current_events(h, WT), 20)
         t_gemm = gemms[f"L{li + 1} I = x W^T ({K} -> {N})"]["ms"]
         ev_bytes = M * (K * h.element_size() + 4 * N)     # inputs read + current written (HBM)
         events[f"L{li + 1} ({K} -> {N})"] = {"ms": t, "active_fraction": float((h != 0).float().mean().item()),
