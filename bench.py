@@ -14,14 +14,17 @@ gradient dL/dS is the gradient of a Gaussian-smoothed (sigma 2 ms) MSE against
 target trains simulated with perturbed parameters; it is computed once before
 timing (the loss is not part of the ALIF path).
 
-Printed JSON (last stdout line): whole-job neuron-steps/s (B * N * T / step
-time), the sequential GPU kernels on the same work, per-kernel HIP event
-durations, the HBM roofline of the dominant kernel, the FP64 oracle on host
-cores over the same workload, a serving leg (p50 / p99 latency and
-throughput of a Poisson stream of uneven requests under continuous batching),
-and two spike-input training legs: the three-layer 700 -> 1024 -> 1024 -> 20
-network with BF16 GEMMs (each GEMM also timed alone against the MFMA peak) and
-the SHD-shaped 700 -> 512 -> readout step with FP32 GEMMs.
+Output. The last stdout line is a compact JSON headline (under 2 KB): whole-job
+neuron-steps/s (B * N * T / step time), ms per step, the HBM roofline of the
+dominant kernel (HIP events on the launch stream), the FP64 oracle on the host's
+cores over the same workload, the fused sequential GPU kernels on the same work,
+the serving leg's p50 / p99 latency and throughput (a Poisson stream of 2000
+uneven requests under continuous batching) and the latency-bound single-layer
+forward (200 -> 100, batch 1, T 1000: time and sequential depth). Every leg's
+full results go to --detail-out: per-kernel durations, the three-layer BF16
+and SHD-shaped training legs (each GEMM timed alone against the MFMA peak), the
+recurrent leg, the block-vs-sequential speedup sweep and the speed-accuracy
+sweeps. Progress and one-line summaries go to stderr.
 """
 from __future__ import annotations
 
@@ -652,6 +655,56 @@ def recurrent_leg(w, I, P, gS, steps=3):
             "value": B * N * T / ((graph_ms or eager) + bwd) * 1e3, "unit": "neuron-steps/s (fwd + bwd)"}
 
 
+def single_layer_leg(reps=50, seed=0):
+    """The single-layer forward as specified: 200 Bernoulli(0.02) channels -> 100
+    ALIF neurons, batch 1, T 1000, DT 1 ms, ARP 2 ms (T_R 2), FP32 input GEMM;
+    and its driven variant (bias b ~ U[1, 2]), which fires. 100 neurons cannot
+    fill the GPU: the time is the latency of 500 dependent blocks (1000 dependent
+    steps for the sequential kernels), so no roofline applies. Each forward
+    (GEMM + block kernel, or GEMM + sequential kernel) is timed with HIP events
+    over ``reps`` calls."""
+    import torch
+
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif
+    from paper_2311_11390_amd.synth import single_layer
+    out = {}
+    for driven in (False, True):
+        w = single_layer(seed=seed, driven=driven)
+        x = torch.as_tensor(w.inputs["x"], device="cuda")
+        W = torch.as_tensor(w.weights[0], device="cuda")
+        P = alif.Params.from_numpy(w.layers[0], "cuda")
+        B, T, N = w.B, w.T, W.shape[0]
+        TR = alif.refractory_steps(w.dt, w.arp)
+        row = {"blocks_in_sequence": -(-T // TR), "steps_in_sequence": T, "T_R": TR}
+        sp = {}
+        for name, algo in (("block", L.ALGO_BLOCKS), ("sequential", L.ALGO_SEQUENTIAL)):
+            o = {"spikes": torch.empty(B, T, N, dtype=torch.uint8, device="cuda"),
+                 "current": torch.empty(B, T, N, dtype=torch.float32, device="cuda")}
+            row[name + "_fwd_ms"] = _event_ms(lambda: alif.forward(x, P, w.dt, w.arp, W, algo=algo, out=o), reps)
+            sp[name] = o["spikes"]
+        row["spikes"] = int(sp["block"].sum().item())
+        row["block_equals_sequential"] = bool(torch.equal(sp["block"], sp["sequential"]))
+        row["block_us_per_dependent_block"] = row["block_fwd_ms"] * 1e3 / row["blocks_in_sequence"]
+        row["speedup_vs_sequential"] = row["sequential_fwd_ms"] / row["block_fwd_ms"]
+        out["driven" if driven else "as_specified"] = row
+        log(f"[bench] single layer{' (driven)' if driven else ''}: block fwd {row['block_fwd_ms'] * 1e3:.1f} us "
+            f"({row['blocks_in_sequence']} blocks in sequence), sequential fwd {row['sequential_fwd_ms'] * 1e3:.1f} us "
+            f"({T} steps), {row['spikes']} spikes")
+    out["workload"] = ("single layer 200 -> 100, batch 1, T 1000, DT 1 ms, ARP 2 ms (T_R 2), Bernoulli(0.02) "
+                       "input, FP32 input GEMM; latency-bound, time and sequential depth only")
+    return out
+
+
+def cgroup_cpu_quota():
+    """CPUs the process's cgroup may use (cpu.max quota / period), or None."""
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        return None if q == "max" else float(q) / float(per)
+    except (OSError, ValueError):
+        return None
+
+
 def cpu_baseline(w, cpu_seconds, threads):
     """FP64 oracle fwd + bwd over the whole workload (every (batch, neuron) row, all
     T steps), repeated in whole passes until `cpu_seconds` of CPU time (summed
@@ -678,7 +731,8 @@ def cpu_baseline(w, cpu_seconds, threads):
 
 
 def cpu_baseline_one_core(w, rows):
-    """The same oracle on one thread over the first `rows` (batch, neuron) rows."""
+    """The same oracle on one thread over the first `rows` (batch, neuron) rows
+    (all of them by default), one forward + backward pass."""
     import oracle
     from oracle import _to_rows
     I = w.inputs["I"]
@@ -762,6 +816,47 @@ def serve_leg(n_requests, rate_hz, max_slots, budget_gib, output="events", seed=
     return out
 
 
+def headline(res):
+    """The compact result line (well under 2 KB): the contract's keys, the roofline
+    and CPU baseline of the timed step, the sequential comparator, and one-line
+    summaries of the serving and single-layer legs. Everything else stays in the
+    detail file."""
+    r3 = lambda v: None if v is None else float(f"{v:.4g}")
+    out = {k: res[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                               "higher_is_better", "scaling", "vs_baseline", "dtype", "data")}
+    c = res["config"]
+    out["config"] = {"workload": c["workload"], "global_batch": c["batch"], "neurons": c["neurons"],
+                     "seq_len": c["T"], "T_R": c["T_R"], "parallelism": "single GPU"}
+    rf = res["roofline"]
+    out["roofline"] = {"bound": rf["bound"], "kernel": rf["kernel"], "achieved": r3(rf["achieved"]),
+                       "peak": rf["peak"], "unit": rf["unit"], "frac": r3(rf["frac"]),
+                       "traffic": rf["traffic"]}
+    out["kernels_ms"] = {k: r3(v["avg_ms"]) for k, v in res["kernels"].items()}
+    cpu = res.get("cpu_baseline")
+    if cpu:
+        out["cpu_baseline"] = {"value": r3(cpu["value"]), "unit": cpu["unit"], "cores": cpu["cores"],
+                               "kind": cpu["kind"], "sample": cpu["sample"],
+                               "one_core": r3(cpu["one_core"]["value"])}
+    seq = res.get("sequential")
+    if seq:
+        out["sequential"] = {"value": r3(seq["value"]), "ms_per_step": r3(seq["ms_per_step"]),
+                             "speedup": r3(res["speedup_vs_sequential"])}
+    sv = res.get("serving")
+    if sv:
+        out["serving"] = {"requests": sv["requests"], "rate_hz": sv["arrival_rate_hz"]}
+        for mode in ("realtime", "saturated"):
+            m = sv.get(mode)
+            if m:
+                out["serving"][mode] = {"p50_ms": r3(m["p50_ms"]), "p99_ms": r3(m["p99_ms"]),
+                                        "neuron_steps_per_s": r3(m["neuron_steps_per_s"]), "failed": m["failed"]}
+    sl = res.get("single_layer")
+    if sl:
+        out["single_layer"] = {k: {"block_fwd_ms": r3(v["block_fwd_ms"]), "sequential_fwd_ms": r3(v["sequential_fwd_ms"]),
+                                   "blocks_in_sequence": v["blocks_in_sequence"], "spikes": v["spikes"]}
+                               for k, v in sl.items() if isinstance(v, dict)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -784,7 +879,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU time (summed over threads) the oracle baseline runs for, in whole passes")
-    ap.add_argument("--serve-requests", type=int, default=300,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests in the serving leg (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -793,6 +888,11 @@ def main():
     ap.add_argument("--B", type=int, default=64)
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--T", type=int, default=20000)
+    ap.add_argument("--no-single-layer", action="store_true",
+                    help="skip the latency-bound single-layer forward (200 -> 100, B 1, T 1000)")
+    ap.add_argument("--detail-out", default=os.path.join(HERE, "gpurun_out", "bench_detail.json"),
+                    help="file the full per-leg results are written to (the last stdout line is a compact "
+                         "headline); empty to skip")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB (a kernel of known "
                          "traffic, for scaling HBM byte counters under a profiler)")
@@ -925,19 +1025,28 @@ def main():
         fits["neuron_fit"] = fit_sweep(args.fit_epochs, args.fit_seq_epochs, configs=cfgs)
         torch.cuda.empty_cache()
 
+    single = None
+    if not args.no_single_layer:
+        log("[bench] single-layer forward (latency-bound)")
+        single = single_layer_leg()
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = len(os.sched_getaffinity(0))
-        threads = min(threads, 16)
-        log(f"[bench] oracle CPU baseline: whole workload, {threads} threads, >= {args.cpu_seconds} CPU-s")
+        quota = cgroup_cpu_quota()
+        log(f"[bench] oracle CPU baseline: whole workload, {threads} threads (every core in the affinity "
+            f"mask; cgroup CPU quota {quota}), >= {args.cpu_seconds} CPU-s")
         rate, el, cpu_s, passes, rows = cpu_baseline(w, args.cpu_seconds, threads)
-        r1, el1, rows1 = cpu_baseline_one_core(w, 512)
+        log(f"[bench] oracle on {threads} threads: {rate:.3e} neuron-steps/s")
+        r1, el1, rows1 = cpu_baseline_one_core(w, rows)
+        log(f"[bench] oracle on one core: {r1:.3e} neuron-steps/s")
         cpu = {"value": rate, "unit": "neuron-steps/s", "cores": threads, "kind": "oracle",
+               "cgroup_cpu_quota": quota,
                "sample": f"the whole workload ({rows} (batch, neuron) rows x {T} steps), forward + "
-                         f"backward, {passes} passes: {el:.2f} s wall, {cpu_s:.1f} CPU-s",
+                         f"backward, {passes} passes on {threads} threads: {el:.2f} s wall, {cpu_s:.1f} CPU-s",
                "one_core": {"value": r1, "cores": 1,
-                            "sample": f"the first {rows1} (batch, neuron) rows x {T} steps, forward + "
-                                      f"backward: {el1:.2f} s"}}
+                            "sample": f"the whole workload ({rows1} rows x {T} steps), forward + backward, "
+                                      f"one pass on one thread: {el1:.2f} s"}}
 
     serve = None
     if args.serve_requests > 0:
@@ -978,8 +1087,17 @@ def main():
         "speedup_sweep": sweep,
         "fits": fits,
         "serving": serve,
+        "single_layer": single,
     }
-    print(json.dumps(res), flush=True)
+    if args.detail_out:
+        try:
+            os.makedirs(os.path.dirname(os.path.abspath(args.detail_out)), exist_ok=True)
+            with open(args.detail_out, "w") as f:
+                json.dump(res, f, indent=1)
+            log(f"[bench] full results written to {args.detail_out}")
+        except OSError as e:
+            log(f"[bench] could not write {args.detail_out}: {e}")
+    print(json.dumps(headline(res)), flush=True)
 
 
 if __name__ == "__main__":

@@ -361,7 +361,10 @@ class BlockALIF(torch.autograd.Function):
         prm = Params(tau_mem.contiguous(), tau_adapt.contiguous(), d.contiguous(), theta0.contiguous(),
                      None if bias is None else bias.contiguous())
         traces = cfg.get("traces", False)
-        f = forward(inp.contiguous(), prm, cfg["dt"], cfg["arp"], W, gemm_precision=cfg.get("gemm", L.GEMM_FP32),
+        # the kernels read dense [B][T][*] rows: the forward and the backward both get the same contiguous copy
+        x = inp.contiguous()
+        Wc = None if W is None else W.contiguous()
+        f = forward(x, prm, cfg["dt"], cfg["arp"], Wc, gemm_precision=cfg.get("gemm", L.GEMM_FP32),
                     spike_dtype=cfg.get("spike_dtype", L.SPIKES_F32), algo=cfg.get("algo", L.ALGO_BLOCKS),
                     want_v=traces, want_theta=traces, save=True, slope=cfg.get("slope", 10.0),
                     surrogate=cfg.get("surrogate", L.SG_FAST_SIGMOID))
@@ -369,7 +372,7 @@ class BlockALIF(torch.autograd.Function):
         ctx.fwd = {k: f[k] for k in ("current", "carries", "desc")}
         ctx.prm = prm
         ctx.has_bias = bias is not None
-        ctx.save_for_backward(inp, W)
+        ctx.save_for_backward(x, Wc)
         empty = inp.new_empty(0, dtype=torch.float32)
         return f["spikes"], (f["v"] if traces else empty), (f["theta"] if traces else empty)
 

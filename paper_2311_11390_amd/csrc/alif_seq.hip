@@ -11,9 +11,13 @@
 //    adjoint recurrence runs backwards over it step by step, under the detached
 //    gradient policy or the attached one (supplementary "Detaching gradients").
 //
-// The membrane and adaptation state are FP64 (FP64 vector math runs at the FP32
-// rate on CDNA4, and an FP32 per-step recurrence drifts by ~1e-5 over
-// thousands of small steps, which would flip near-threshold spikes).
+// The membrane and adaptation state are FP64. That is a parity requirement, not
+// a speed choice: an FP32 per-step recurrence drifts by ~1e-5 over thousands of
+// small steps (DT = 0.05 ms, beta ~ 0.9975), enough to flip crossings well outside
+// the 1e-6 band the parity tests excuse. FP64 vector arithmetic costs this kernel
+// about half the FP32 vector rate (78.6 against 157.3 TFLOP/s on MI355X); at the
+// fine-DT size the 16384 (batch, neuron) rows are 256 waves, one per CU, so the
+// per-step dependence chain rather than the arithmetic rate sets the time.
 #include <type_traits>
 
 #include "alif_common.h"

@@ -3,7 +3,7 @@ the FP64 oracle, through the C ABI."""
 import numpy as np
 import pytest
 
-from gpu_helpers import driven_current, gpu_forward, log, np_, random_params
+from gpu_helpers import driven_current, gpu_forward, log, np_, random_params, to_dev
 from parity import check_forward, coincidence
 
 pytestmark = pytest.mark.gpu
@@ -160,3 +160,34 @@ def test_blocks_vs_sequential_coincidence():
     a, _, _ = gpu_forward(I, prm, 0.05, 2.0, algo=0)
     b, _, _ = gpu_forward(I, prm, 0.05, 2.0, algo=1)
     assert coincidence(np_(a["spikes"]), np_(b["spikes"])) > 0.99
+
+
+@pytest.mark.parametrize("TR,dt", [(2, 1.0), (40, 0.05), (128, 2.0 / 128)])
+def test_decay_tables_are_fp64_powers_rounded_once(TR, dt):
+    """alif_decay_tables: beta^k = exp(-k DT / tau_mem) and p^k = exp(-k DT /
+    tau_adapt) evaluated in FP64 and rounded once to FP32 (supplementary "Weight
+    initialisation" for beta and p; Props. 1 and 5 use the powers), for k = 0..T_R.
+    Against numpy's float64 exp of the same argument rounded once: within one FP32
+    ulp everywhere, and equal except where the FP64 value sits at a rounding
+    boundary (a handful of entries at most)."""
+    import torch
+
+    from paper_2311_11390_amd import alif
+    N = 300
+    g = np.random.default_rng(TR)
+    tm = g.uniform(1.0, 200.0, N).astype(np.float32)
+    ta = g.uniform(5.0, 2000.0, N).astype(np.float32)
+    tm[:3] = [1e-3, 0.05, 1e6]                      # near-zero and near-one decays
+    prm = random_params(TR, N)
+    prm.tau_mem, prm.tau_adapt = tm, ta
+    log(f"[tables] T_R={TR} dt={dt} N={N}")
+    bp, pp = alif.decay_tables(to_dev(prm), N, dt, 2.0)
+    torch.cuda.synchronize()
+    k = np.arange(TR + 1, dtype=np.float64)
+    for got, tau in ((np_(bp), tm), (np_(pp), ta)):
+        ref = np.exp(-dt / tau.astype(np.float64)[:, None] * k[None, :]).astype(np.float32)
+        assert got.shape == (N, TR + 1) and got.dtype == np.float32
+        ulps = np.abs(got.view(np.int32).astype(np.int64) - ref.view(np.int32).astype(np.int64))
+        assert ulps.max() <= 1, ulps.max()
+        assert (ulps != 0).sum() <= max(2, got.size // 1000)
+        assert (got[:, 0] == 1.0).all()

@@ -213,8 +213,8 @@ def test_three_layer_precision_form_full_size(driven):
                      f"mean {dvbf.mean():.2e}")
         orcs.append(orc)
         h = orc["S"]
-        if driven:
-            assert co_bf > 0.8
+        # BF16 rounds W (relative 2^-9): measured 0.993-0.998 driven, 1.0 (no spikes) as specified
+        assert co_bf >= 0.98
     # backward chain: loss = sum of the last layer's spikes
     gS = np.ones(orcs[-1]["S"].shape)
     for li in reversed(range(len(Ws))):
@@ -225,6 +225,11 @@ def test_three_layer_precision_form_full_size(driven):
         rw = float(np.linalg.norm(dWbf[li] - dW32[li]) / (np.linalg.norm(dW32[li]) or 1.0))
         lines.append(f"L{li + 1} grad: fp32 rel L2 {e32['rel_l2']:.1e}; bf16 rel L2 {ebf:.1e}; "
                      f"bf16 vs fp32 dW (full batch) {rw:.1e}")
+        # dW sums gI (rounded to bfloat16, relative 2^-9) against exact 0/1 inputs; the measured
+        # differences are 2-4 x 2^-9, bounded at 8 x 2^-9. The BF16 path's gI also carries the
+        # trajectory changes of its moved crossings: measured <= 1.6e-2, bounded at 5e-2.
+        assert rw <= 8 * 2.0 ** -9
+        assert ebf <= 5e-2
         gS = (ob["gI"].reshape(-1, ob["gI"].shape[2]) @ Ws[li].astype(np.float64)).reshape(
             ob["gI"].shape[0], ob["gI"].shape[1], -1)
     log(f"[report] three-layer full driven={driven}: " + "; ".join(lines))

@@ -255,6 +255,54 @@ def test_shd_like_training_step_autograd():
     check_grad("grad_bias", P["bias"].grad.cpu().numpy(), ob["gI"].sum(axis=(0, 1)))
 
 
+@pytest.mark.parametrize("spike_input", [True, False])
+def test_block_alif_non_contiguous_inputs(spike_input):
+    """BlockALIF applied to non-contiguous views (the input a transposed [B][n][T]
+    tensor, W a transposed [n_in][N] tensor) gives the same spikes and the same
+    gradients for the input, W and the parameters as the contiguous call: the
+    backward must read the same dense copy the forward read."""
+    import torch
+    from paper_2311_11390_amd import alif
+    g = rng(41)
+    B, T, n_in, N = 2, 203, 37, 45
+    lp = random_params(41, N, bias=(1.0, 2.0))
+    if spike_input:
+        x = bernoulli_spikes(g, (B, T, n_in), 0.1).astype(np.float32)
+        W = normal_weights(g, N, n_in)
+    else:
+        x = driven_current(41, B, T, N)
+        W = None
+    log(f"[autograd] non-contiguous views, spike_input={spike_input}")
+    dev = "cuda"
+    gS = torch.as_tensor(g.standard_normal((B, T, N)).astype(np.float32), device=dev)
+    cfg = {"dt": 0.5, "arp": 2.0}
+
+    def run(contiguous):
+        xt = torch.as_tensor(x, device=dev)
+        xin = xt if contiguous else xt.transpose(1, 2).contiguous().transpose(1, 2)
+        xin = xin.clone().requires_grad_() if contiguous else xin.detach().requires_grad_()
+        Wt = None
+        if W is not None:
+            Wd = torch.as_tensor(W, device=dev)
+            Wt = (Wd.clone() if contiguous else Wd.t().contiguous().t()).detach().requires_grad_()
+        P = {k: torch.as_tensor(getattr(lp, k), device=dev).requires_grad_()
+             for k in ("tau_mem", "tau_adapt", "d", "theta0", "bias")}
+        assert xin.is_contiguous() == contiguous
+        S, _, _ = alif.BlockALIF.apply(xin, Wt, P["tau_mem"], P["tau_adapt"], P["d"], P["theta0"], P["bias"], cfg)
+        (S * gS).sum().backward()
+        torch.cuda.synchronize()
+        out = {"S": np_(S), "x": np_(xin.grad)}
+        if Wt is not None:
+            out["W"] = np_(Wt.grad)
+        out.update({k: np_(v.grad) for k, v in P.items()})
+        return out
+
+    a, b = run(True), run(False)
+    assert a["S"].sum() > 0
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
 def _three_layer_forward(x, Ws, lps, dt, arp, prec):
     import torch
     from paper_2311_11390_amd import alif
@@ -289,4 +337,6 @@ def test_three_layer_precision_form():
         h = orc["S"]
         co = coincidence(np_(bf[li]["spikes"]), gpu_S)
         log(f"    layer {li}: spikes {int(gpu_S.sum())}, excused {exc}, bf16 coincidence {co:.4f}")
-        assert co > 0.8
+        # BF16 rounds W (relative 2^-9), so a few crossings move by a step or flip; the
+        # full-size run measures 0.993-0.998
+        assert co >= 0.98
