@@ -300,6 +300,32 @@ int alif_backward(const alif_desc *desc, const alif_params *prm,
                   void *workspace, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving or training loops, harnesses that forbid hipMalloc): the same
+ * backward as alif_backward, same arguments and results, without the workspace
+ * argument. Its scratch (the FP64 partial sums, 40 bytes per (b, neuron), plus the
+ * weight-gradient GEMM's split-K tiles when grad_W is requested for spike input)
+ * lives in a static device array of ALIF_NOALLOC_SCRATCH_BYTES inside the library,
+ * one per device, held until the process ends. This call allocates nothing: no
+ * hipMalloc, hipFree or allocating library routine. A problem whose scratch
+ * exceeds the array (alif_backward_workspace_bytes without the GEMM part, unless
+ * grad_W is requested) is rejected with ALIF_EUNSUPPORTED before any work is
+ * queued. Every call on one device shares that device's array and leaves the
+ * last call's contents in it, so calls that overlap on one device (on different
+ * streams, or from different threads) race and give wrong gradients; serialise
+ * them on one stream. Each call writes every scratch byte it reads, so nothing
+ * needs clearing between calls.
+ */
+#define ALIF_NOALLOC_SCRATCH_BYTES (16u << 20)
+int alif_backward_noalloc(const alif_desc *desc, const alif_params *prm,
+                          const void *input, const float *W, const float *current,
+                          const void *carries, const float *grad_spikes,
+                          const float *grad_v, const float *grad_theta,
+                          float *grad_current, float *grad_input, float *grad_W,
+                          float *grad_bias, float *grad_tau_mem, float *grad_tau_adapt,
+                          float *grad_d, float *grad_theta0, void *stream);
+
+/*
  * Recurrent layer: Eq. 3's input current with the recurrent term
  * sum_j W_rec[i][j] S_j[t - D] and transmission delay D (Section 2 takes
  * D = T_R, which Prop. 3 turns into block n + 1 receiving W_rec times the

@@ -81,6 +81,8 @@ _SIGNATURES = {
                              POINTER(AlifState), POINTER(AlifState), _P, _P, _P, _P, _P]),
     "alif_backward": (c_int, [POINTER(AlifDesc), POINTER(AlifParams), _P, _P, _P, _P,
                               _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "alif_backward_noalloc": (c_int, [POINTER(AlifDesc), POINTER(AlifParams), _P, _P, _P, _P,
+                                      _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "alif_readout_workspace_bytes": (c_int, [c_int32, c_int32, c_int32, c_int32, POINTER(c_size_t)]),
     "alif_readout_forward": (c_int, [c_int32, c_int32, c_int32, c_int32, c_double, c_int32,
                                      _P, _P, _P, _P, _P, _P]),

@@ -140,8 +140,11 @@ def forward(inp: torch.Tensor, params: Params, dt: float, arp: float, W: torch.T
 
 def backward(fwd: dict, inp: torch.Tensor, params: Params, W: torch.Tensor | None = None, *,
              grad_spikes=None, grad_v=None, grad_theta=None, want_grad_current=False,
-             want_grad_input=False, want_grad_W=False, want_param_grads=True, workspace=None) -> dict:
-    """Surrogate-gradient backward (alif_backward) of a ``forward(..., save=True)``."""
+             want_grad_input=False, want_grad_W=False, want_param_grads=True, workspace=None,
+             noalloc=False) -> dict:
+    """Surrogate-gradient backward (alif_backward) of a ``forward(..., save=True)``.
+    ``noalloc`` calls alif_backward_noalloc instead, whose scratch is the library's
+    static device array (no workspace is allocated or passed)."""
     desc = fwd["desc"]
     B, T, N = desc.batch, desc.T, desc.n_neurons
     dev = inp.device
@@ -152,17 +155,19 @@ def backward(fwd: dict, inp: torch.Tensor, params: Params, W: torch.Tensor | Non
     g_in = f32(B, T, desc.n_in) if (spikes_in and want_grad_input) else None
     g_W = f32(N, desc.n_in) if (spikes_in and want_grad_W) else None
     pg = {k: f32(N) for k in ("bias", "tau_mem", "tau_adapt", "d", "theta0")} if want_param_grads else {}
-    if workspace is None:
+    if workspace is None and not noalloc:
         workspace = torch.empty(max(1, backward_workspace_bytes(desc)), dtype=torch.uint8, device=dev)
     cp = params.c()
     for g in (grad_spikes, grad_v, grad_theta):
         if g is not None:
             assert g.dtype == torch.float32 and g.is_contiguous() and g.shape == (B, T, N)
-    L.check(L.load().alif_backward(ctypes.byref(desc), ctypes.byref(cp), _p(inp), _p(W), _p(fwd["current"]),
-                                   _p(fwd["carries"]), _p(grad_spikes), _p(grad_v), _p(grad_theta),
-                                   _p(g_cur), _p(g_in), _p(g_W), _p(pg.get("bias")), _p(pg.get("tau_mem")),
-                                   _p(pg.get("tau_adapt")), _p(pg.get("d")), _p(pg.get("theta0")),
-                                   _p(workspace), _stream(dev)))
+    args = [ctypes.byref(desc), ctypes.byref(cp), _p(inp), _p(W), _p(fwd["current"]), _p(fwd["carries"]),
+            _p(grad_spikes), _p(grad_v), _p(grad_theta), _p(g_cur), _p(g_in), _p(g_W), _p(pg.get("bias")),
+            _p(pg.get("tau_mem")), _p(pg.get("tau_adapt")), _p(pg.get("d")), _p(pg.get("theta0"))]
+    if noalloc:
+        L.check(L.load().alif_backward_noalloc(*args, _stream(dev)))
+    else:
+        L.check(L.load().alif_backward(*args, _p(workspace), _stream(dev)))
     out = {"grad_current": g_cur, "grad_input": g_in if spikes_in else g_cur, "grad_W": g_W}
     out.update({"grad_" + k: v for k, v in pg.items()})
     return out

@@ -15,6 +15,13 @@
 
 using namespace alif;
 
+// Device scratch of alif_backward_noalloc: the block backward's FP64 partial sums
+// and the weight-gradient GEMM's split-K partial tiles. One copy per device (a
+// module-scope device array exists on every device the library runs on). Host code
+// never uses the name itself, which is only a host-side stand-in: it asks the
+// runtime for the array's address on the current device (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[ALIF_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -51,6 +58,28 @@ int status_word(unsigned **out) {
         g_status[dev] = p;
     }
     *out = g_status[dev];
+    return ALIF_OK;
+}
+
+// The address of `scratch` on the current device, looked up once per device with
+// that device current (each device holds its own copy at its own address).
+std::mutex g_scratch_mu;
+void *g_scratch[64] = {nullptr};
+
+int noalloc_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(ALIF_EINVAL, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(ALIF_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
     return ALIF_OK;
 }
 
@@ -455,6 +484,32 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
         }
     }
     return ALIF_OK;
+}
+
+int alif_backward_noalloc(const alif_desc *desc, const alif_params *prm, const void *input, const float *W,
+                          const float *current, const void *carries, const float *grad_spikes,
+                          const float *grad_v, const float *grad_theta, float *grad_current,
+                          float *grad_input, float *grad_W, float *grad_bias, float *grad_tau_mem,
+                          float *grad_tau_adapt, float *grad_d, float *grad_theta0, void *stream) {
+    Prob p;
+    int rc = check_desc(desc, &p);
+    if (rc) return rc;
+    // the scratch alif_backward would take as its workspace: the partial sums, and
+    // the split-K tiles only when the weight gradient is asked for
+    const size_t need = align256((size_t)5 * p.B * p.N * sizeof(double)) +
+                        ((p.spikes_in && grad_W) ? gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.n_in) : 0);
+    if (need > (size_t)ALIF_NOALLOC_SCRATCH_BYTES)
+        return fail(ALIF_EUNSUPPORTED,
+                    "alif_backward_noalloc: this problem needs %zu bytes of scratch, more than the %u-byte "
+                    "static scratch; use alif_backward with a workspace",
+                    need, (unsigned)ALIF_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    if ((rc = noalloc_scratch(&ws))) return rc;
+    // every scratch byte the kernels read they have written earlier in the same call
+    // (the partial sums of every (b, neuron), every split's tile), so nothing is cleared
+    return alif_backward(desc, prm, input, W, current, carries, grad_spikes, grad_v, grad_theta, grad_current,
+                         grad_input, grad_W, grad_bias, grad_tau_mem, grad_tau_adapt, grad_d, grad_theta0, ws,
+                         stream);
 }
 
 // ---------------------------------------------------------------------------
