@@ -285,10 +285,14 @@ int alif_forward(const alif_desc *desc, const alif_params *prm,
  *   grad_bias, grad_tau_mem, grad_tau_adapt, grad_d, grad_theta0
  *            device float [N], summed over the batch; each nullable
  *   workspace device scratch of alif_backward_workspace_bytes() bytes
- * desc->grad_policy ALIF_GRAD_ATTACHED needs desc->algo ALIF_ALGO_SEQUENTIAL. The
- * sequential backward stages one block in LDS and takes T_R <= 121 (<= 88 with
- * grad_v or grad_theta). The per-step-launch algorithm has no backward. All of
- * these are ALIF_EUNSUPPORTED, reported before any work is queued.
+ * desc->grad_policy ALIF_GRAD_ATTACHED keeps the spike's reset and adaptation uses
+ * in the gradient (supplementary "Detaching gradients"): the block backward then
+ * composes the per-step adjoint as 2 x 2 affine maps of (lambda_V, lambda_a) in
+ * FP64 (the coupled recurrence can amplify rounding by many orders of magnitude);
+ * the sequential backward evaluates it step by step in FP64. The sequential
+ * backward stages one block in LDS and takes T_R <= 121 (<= 88 with grad_v or
+ * grad_theta). The per-step-launch algorithm has no backward. Both limits are
+ * ALIF_EUNSUPPORTED, reported before any work is queued.
  */
 int alif_backward(const alif_desc *desc, const alif_params *prm,
                   const void *input, const float *W, const float *current,

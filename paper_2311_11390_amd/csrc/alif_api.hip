@@ -389,8 +389,6 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
     if ((rc = check_params(prm))) return rc;
     if (desc->algo == ALIF_ALGO_SEQUENTIAL_STEP)
         return fail(ALIF_EUNSUPPORTED, "the per-step-launch baseline is forward only");
-    if (desc->grad_policy == ALIF_GRAD_ATTACHED && desc->algo != ALIF_ALGO_SEQUENTIAL)
-        return fail(ALIF_EUNSUPPORTED, "attached gradients: the sequential backward only");
     if (desc->algo == ALIF_ALGO_SEQUENTIAL && p.TR > seq_bwd_max_tr(grad_v || grad_theta))
         return fail(ALIF_EUNSUPPORTED, "sequential backward supports T_R <= %d here",
                     seq_bwd_max_tr(grad_v || grad_theta));
@@ -432,6 +430,7 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
         a.dt = desc->dt_ms;
         a.slope = desc->sg_slope;
         a.surrogate = desc->surrogate;
+        a.attached = desc->grad_policy == ALIF_GRAD_ATTACHED;
         a.I = I;
         a.bias_k = bias_k;
         a.tau_m = prm->tau_mem_ms; a.tau_a = prm->tau_adapt_ms; a.d = prm->d; a.theta0 = prm->theta0;

@@ -1009,6 +1009,308 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// backward, attached gradient policy
+// ---------------------------------------------------------------------------
+// Supplementary "Detaching gradients" sets the detached policy against one where
+// the spike's own effects stay in the gradient: its reset of the next step's
+// membrane, dV[t+1]/dS[t] = -(beta V[t] + (1 - beta) Im[t+1]) = -c[t] (Im: the
+// gated input), and its adaptation jump, da[t+1]/dS[t] = 1. The adjoint of the
+// spike then collects lamS[t] = dL/dS[t] - c[t] lamV[t+1] + lamA[t+1], and with
+// s = the surrogate derivative at V[t] - theta[t]:
+//   lamV[t]  = dL/dV[t] + s lamS[t] + beta (1 - S[t]) lamV[t+1]
+//   lamTh[t] = dL/dtheta[t] - s lamS[t],   lamA[t] = d lamTh[t] + p lamA[t+1],
+// an affine map of the pair (lamV, lamA)[t+1]:
+//   (lamV, lamA)[t] = r[t] + M[t] (lamV, lamA)[t+1],
+//   M[t] = [[beta (1 - S[t]) - s c[t], s], [d s c[t], p - d s]],
+//   r[t] = (dL/dV + s dL/dS, d (dL/dtheta - s dL/dS)).
+// The ARP gate counts steps and passes no gradient under either policy.
+//
+// Block form: as in the detached backward, each block is recomputed from its saved
+// carry-in with the forward's helpers (so V~ and theta are the forward's FP32
+// values) and the spike step is read from the next block's carry. Each
+// segment-wave composes its steps' maps from zero (P = M[t0+1] ... M[t0+L],
+// R the matching offset), the (P, R) pairs meet in LDS, and every wave composes
+// them from the block end, starting from the lambdas at step 1 of the block after.
+// The coupled recurrence can amplify rounding by orders of magnitude (the
+// multi-Gaussian surrogate at T_R = 2 grows gradients by 1e9 over a few hundred
+// steps), so the surrogate, the maps, the lambdas and the sums are FP64; only V,
+// theta and a are the forward's FP32 values. Two barriers per block, two-block
+// register prefetch. dL/dV, dL/dtheta may be absent (their buffers then read 0) and
+// so may dL/dI (its stores are dropped).
+template <int SEG>
+__host__ __device__ constexpr int att_exch_doubles() { return 6 * SEG * Geo<SEG>::NWG; }
+
+template <int SEG, int L>
+size_t bwd_att_smem_bytes(int TR) {
+    constexpr int NWG = Geo<SEG>::NWG;
+    return (size_t)att_exch_doubles<SEG>() * sizeof(double) + (size_t)NWG * ptab_row(TR, L) * sizeof(float) +
+           (size_t)2 * SEG * NWG * sizeof(float);
+}
+
+template <int SEG, int L, bool EVEN, int SG>
+__global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd_att(BwdArgs a) {
+    constexpr int NWG = Geo<SEG>::NWG;
+    constexpr int SN = SEG * NWG;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int TR = a.TR, N = a.N, T = a.T, RL = ptab_row(TR, L);
+    double *exP = reinterpret_cast<double *>(smem);             // [6][SEG][NWG]: P00 P01 P10 P11 R0 R1
+    float *pf_tab = reinterpret_cast<float *>(exP + att_exch_doubles<SEG>());
+    float *exX = pf_tab + (size_t)NWG * RL;                       // [SEG][NWG] segment ends of the scan
+    float *exVL = exX + SN;                                       // [SEG][NWG] V at each segment's last step
+
+    const int work = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = work / a.n_groups, g = work - b * a.n_groups;
+    const int n0 = g * NWG;
+    build_p_tables<SEG, L>(nullptr, pf_tab, n0, N, TR, a.dt, a.tau_a);
+    Lane<SEG, L, EVEN> c;
+    lane_setup(c, N, TR, a.dt, n0, a.tau_m, a.tau_a, a.d, a.theta0, a.bias_k);
+    const int pfrow = c.nl * RL + TR + c.t0;
+    const float bias = (a.bias_k && c.valid) ? a.bias_k[c.n] : 0.0f;
+    const int nc = c.valid ? c.n : N - 1;
+    const double beta = exp(-a.dt / (double)a.tau_m[nc]);
+    const double omb = 1.0 - beta;
+    const double p = exp(-a.dt / (double)a.tau_a[nc]);
+    const double dd = (double)c.dd;
+    const double slope = (double)a.slope;
+    // FP64 powers for the adaptation variable at this segment's start (step t0)
+    const double lpd = -a.dt / (double)a.tau_a[nc];
+    const double pt0 = exp(lpd * (double)c.t0), pt0m1 = c.t0 > 0 ? exp(lpd * (double)(c.t0 - 1)) : 0.0;
+
+    const size_t TN = (size_t)T * N;
+    const rsrc_t rI = make_rsrc(a.I + b * TN, (uint32_t)(TN * 4));
+    const rsrc_t rGS = make_rsrc(a.gS ? a.gS + b * TN : nullptr, a.gS ? (uint32_t)(TN * 4) : 0u);
+    const rsrc_t rGV = make_rsrc(a.gV ? a.gV + b * TN : nullptr, a.gV ? (uint32_t)(TN * 4) : 0u);
+    const rsrc_t rGT = make_rsrc(a.gTH ? a.gTH + b * TN : nullptr, a.gTH ? (uint32_t)(TN * 4) : 0u);
+    const rsrc_t rGI = make_rsrc(a.gI ? a.gI + b * TN : nullptr, a.gI ? (uint32_t)(TN * 4) : 0u);
+    const size_t CN = (size_t)(a.NB + 1) * N;
+    const rsrc_t rCv = make_rsrc(a.ck.v + b * CN, (uint32_t)(CN * 4));
+    const rsrc_t rCa = make_rsrc(a.ck.a + b * CN, (uint32_t)(CN * 4));
+    const rsrc_t rCt = make_rsrc(a.ck.ts + b * CN, (uint32_t)CN);
+    const uint32_t ck4 = c.valid ? (uint32_t)c.n * 4u : ALIF_OOB;
+    const uint32_t ck1 = c.valid ? (uint32_t)c.n : ALIF_OOB;
+    const uint32_t blk4 = (uint32_t)(TR * N) * 4u;
+    const uint32_t TN4 = (uint32_t)(TN * 4);
+    // The step after this segment's last valid one: the next segment's first step,
+    // or, for the block's last non-empty segment, step 1 of the next block.
+    const int lastw = (TR - 1) / L;
+    const uint32_t xn_own = (c.valid && c.w < lastw) ? (uint32_t)((c.t0 + L) * N + c.n) * 4u : ALIF_OOB;
+    const uint32_t xn_nxt = (c.valid && c.w == lastw) ? (uint32_t)c.n * 4u : ALIF_OOB;
+
+    struct Slot {
+        float x[L], gs[L], gv[L], gt[L];
+        float xn;       // input at the step after the segment
+        float cv, ca;
+        int cts, tsn;
+    };
+    auto load_block = [&](Slot &dst, int nb) {   // nb < 0: everything out of range
+        const uint32_t bo = nb >= 0 ? (uint32_t)nb * blk4 : TN4;
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            const uint32_t o = c.off(k, bo);
+            dst.x[k] = ld_f32(rI, o);
+            dst.gs[k] = ld_f32(rGS, o);
+            dst.gv[k] = ld_f32(rGV, o);
+            dst.gt[k] = ld_f32(rGT, o);
+        }
+        const uint32_t bn = nb >= 0 ? (uint32_t)min((size_t)(nb + 1) * blk4, TN * 4) : TN4;
+        dst.xn = ld_f32(rI, c.w < lastw ? xn_own + bo : xn_nxt + bn);
+        const uint32_t e = nb >= 0 ? (uint32_t)(nb * N) : (uint32_t)CN;
+        dst.cv = ld_f32(rCv, ck4 + e * 4u);
+        dst.ca = ld_f32(rCa, ck4 + e * 4u);
+        dst.cts = ld_u8(rCt, ck1 + e);
+        dst.tsn = ld_u8(rCt, ck1 + (nb >= 0 ? e + (uint32_t)N : (uint32_t)CN));
+    };
+    Slot buf[2];
+    load_block(buf[0], a.NB - 1);
+    load_block(buf[1], a.NB - 2);
+
+    double lamVc = 0.0, lamAc = 0.0;   // lambdas at step 1 of the block after the current one
+    double acc_b = 0.0, acc_p = 0.0, acc_d = 0.0, acc_th = 0.0, acc_bias = 0.0;
+
+    auto do_block = [&](Slot &cur, int nb) __attribute__((always_inline)) {
+        const int cts = min(cur.cts, TR);
+        const int mpre = cts > 0 ? cts - 1 : 0;
+        const float a1 = fmaf(c.pf, cur.ca, cts == TR ? 1.0f : 0.0f);
+        float uu[L];
+        seg_scan(c, cur.x, mpre, uu);
+        float E = 0.0f, U = 0.0f;
+        if constexpr (SEG > 1) {
+            exX[c.w * NWG + c.nl] = uu[L - 1];
+            __syncthreads();
+            seg_horner(c, exX, E, U);
+        }
+        float vt[L], th[L];
+        seg_membrane(c, cur.cv, E, a1, uu, vt, th);
+        const int ts = cur.tsn > 0 ? min(cur.tsn, TR) : ALIF_NO_SPIKE;
+        const int tsc = min(ts, TR);
+
+        // The adaptation variable in FP64, Eq. 5 run from the block's saved carry-in:
+        // a[t0] in closed form, then a[t] = p a[t-1] + S[t-1] over the segment. It
+        // enters the d and p sums, which the attached adjoint can make ill-conditioned.
+        double A0 = (double)cur.ca;
+        if (c.t0 > 0) {
+            A0 = pt0 * A0 + (cts == TR ? pt0m1 : 0.0);
+            if (ts < c.t0) A0 += exp(lpd * (double)(c.t0 - 1 - ts));
+        }
+        double a64[L];
+        {
+            double av = A0;
+#pragma unroll
+            for (int k = 0; k < L; k++) {
+                const int t = c.t0 + k + 1;
+                const bool sp = (t == 1) ? (cts == TR) : (t - 1 == ts);
+                av = fma(p, av, sp ? 1.0 : 0.0);
+                a64[k] = av;
+            }
+        }
+        // corrected traces (reset after t_s, Eqs. 2 and 5), gate, surrogate and c[t]
+        float Vk[L];
+        bool gk[L];
+        double sk[L], ckk[L];
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            const int t = c.t0 + k + 1;
+            const bool after = t > ts;
+            const float pa = pf_tab[pfrow - tsc + k];   // p^(t - 1 - t_s)
+            Vk[k] = after ? 0.0f : vt[k];
+            const float thk = after ? fmaf(c.dd, pa, th[k]) : th[k];
+            gk[k] = (t > mpre) && !after;
+            sk[k] = c.kvalid(k) ? surrogate_grad_f64<SG>((double)Vk[k] - (double)thk, slope) : 0.0;
+        }
+        {   // gate at the step after the segment: inside the block, or step 1 of the next
+            // block, which a spike at t_s >= 2 masks (Prop. 3)
+            const int tn = c.t0 + L + 1;
+            const bool gn = c.w == lastw ? !(ts <= TR && ts >= 2) : (tn > mpre && !(tn > ts));
+            const double imn = gn ? (double)(cur.xn + bias) : 0.0;
+#pragma unroll
+            for (int k = 0; k < L; k++) {
+                const double im = (k + 1 < c.len) ? (gk[k + 1 < L ? k + 1 : k] ? (double)(cur.x[k + 1 < L ? k + 1 : k] + bias) : 0.0)
+                                                  : imn;
+                ckk[k] = fma(beta, (double)Vk[k], omb * im);
+            }
+        }
+
+        // this segment's maps composed from zero: lam_start = R + P lam_after
+        double P00 = 1.0, P01 = 0.0, P10 = 0.0, P11 = 1.0, R0 = 0.0, R1 = 0.0;
+#pragma unroll
+        for (int k = L - 1; k >= 0; k--) {
+            if (c.kvalid(k)) {
+                const int t = c.t0 + k + 1;
+                const double s = sk[k], sc = s * ckk[k];
+                const double m00 = (t == ts ? 0.0 : beta) - sc, m01 = s, m10 = dd * sc, m11 = p - dd * s;
+                const double gs = cur.gs[k];
+                const double r0 = fma(s, gs, (double)cur.gv[k]);
+                const double r1 = dd * ((double)cur.gt[k] - s * gs);
+                const double nR0 = r0 + m00 * R0 + m01 * R1, nR1 = r1 + m10 * R0 + m11 * R1;
+                const double n00 = m00 * P00 + m01 * P10, n01 = m00 * P01 + m01 * P11;
+                const double n10 = m10 * P00 + m11 * P10, n11 = m10 * P01 + m11 * P11;
+                R0 = nR0; R1 = nR1; P00 = n00; P01 = n01; P10 = n10; P11 = n11;
+            }
+        }
+        float VLast = 0.0f;   // V at this segment's last valid step
+#pragma unroll
+        for (int k = 0; k < L; k++) VLast = (k == c.len - 1) ? Vk[k] : VLast;
+        double lVin, lAin, lv, la;
+        float Vprev0;
+        if constexpr (SEG > 1) {
+            const int q = c.w * NWG + c.nl;
+            exP[q] = P00; exP[SN + q] = P01; exP[2 * SN + q] = P10; exP[3 * SN + q] = P11;
+            exP[4 * SN + q] = R0; exP[5 * SN + q] = R1;
+            exVL[q] = VLast;
+            __syncthreads();
+            lv = lamVc; la = lamAc;
+            lVin = lv; lAin = la;
+#pragma unroll
+            for (int s2 = SEG - 1; s2 >= 0; s2--) {
+                const int o = s2 * NWG + c.nl;
+                lVin = (s2 == c.w) ? lv : lVin;
+                lAin = (s2 == c.w) ? la : lAin;
+                const double nv = exP[4 * SN + o] + exP[o] * lv + exP[SN + o] * la;
+                const double na = exP[5 * SN + o] + exP[2 * SN + o] * lv + exP[3 * SN + o] * la;
+                lv = nv; la = na;
+            }
+            Vprev0 = c.w > 0 ? exVL[(c.w - 1) * NWG + c.nl] : cur.cv;
+        } else {
+            lVin = lamVc; lAin = lamAc;
+            lv = R0 + P00 * lamVc + P01 * lamAc;
+            la = R1 + P10 * lamVc + P11 * lamAc;
+            Vprev0 = cur.cv;
+        }
+
+        // the lambdas step by step from the segment end, and the gradient terms:
+        //   dI += (1 - beta) gate lamV;  d/dbeta += (1 - S[t-1]) (V[t-1] - Im[t]) lamV
+        //   d/dp += a[t-1] lamA;  d/dd += a[t] lamTh;  d/dtheta0 += lamTh
+        const uint32_t bo = (uint32_t)nb * blk4;
+        double lV1 = lVin, lA1 = lAin;
+        double pb = 0.0, pp = 0.0, pdd = 0.0, pth = 0.0, pbias = 0.0;
+#pragma unroll
+        for (int k = L - 1; k >= 0; k--) {
+            if (c.kvalid(k)) {
+                const int t = c.t0 + k + 1;
+                const double s = sk[k];
+                const double gs = cur.gs[k];
+                const double lamS = gs - ckk[k] * lV1 + lA1;
+                const double lamV = (double)cur.gv[k] + s * lamS + (t == ts ? 0.0 : beta) * lV1;
+                const double lamTh = (double)cur.gt[k] - s * lamS;
+                const double lamA = dd * lamTh + p * lA1;
+                const bool sprev = (t == 1) ? (cts == TR) : (t - 1 == ts);
+                const float Vprev = (k == 0) ? Vprev0 : Vk[k > 0 ? k - 1 : 0];
+                const double aprev = (k == 0) ? A0 : a64[k > 0 ? k - 1 : 0];
+                const double im = gk[k] ? (double)(cur.x[k] + bias) : 0.0;
+                pb += sprev ? 0.0 : ((double)Vprev - im) * lamV;
+                pp += aprev * lamA;
+                pdd += a64[k] * lamTh;
+                pth += lamTh;
+                const double glV = gk[k] ? omb * lamV : 0.0;
+                pbias += glV;
+                st_f32(rGI, c.off(k, bo), (float)glV);
+                lV1 = lamV;
+                lA1 = lamA;
+            }
+        }
+        acc_b += pb; acc_p += pp; acc_d += pdd; acc_th += pth; acc_bias += pbias;
+        lamVc = lv;
+        lamAc = la;
+        load_block(cur, nb - 2);   // after the last use of this slot
+    };
+
+    wait_vmem_all();
+    int r0 = 0;
+    for (; r0 + 2 <= a.NB; r0 += 2) {
+        do_block(buf[0], a.NB - 1 - r0);
+        do_block(buf[1], a.NB - 2 - r0);
+    }
+    if (r0 < a.NB) do_block(buf[0], a.NB - 1 - r0);   // uniform over the workgroup
+    // per-(b, n) sums over this neuron's segment-waves, in a fixed order
+    if constexpr (SEG > 1) {
+        double *red = exP;
+        __syncthreads();
+        const int q = c.w * NWG + c.nl;
+        double vals[5] = {acc_b, acc_p, acc_d, acc_th, acc_bias};
+#pragma unroll
+        for (int j = 0; j < 5; j++) {
+            red[q] = vals[j];
+            __syncthreads();
+            if (c.w == 0) {
+                double sm = 0.0;
+                for (int w = 0; w < SEG; w++) sm += red[w * NWG + c.nl];
+                vals[j] = sm;
+            }
+            __syncthreads();
+        }
+        acc_b = vals[0]; acc_p = vals[1]; acc_d = vals[2]; acc_th = vals[3]; acc_bias = vals[4];
+    }
+    if (c.valid && c.w == 0) {
+        const size_t BN = (size_t)a.B * N, i = (size_t)b * N + c.n;
+        a.part[i] = acc_b;
+        a.part[BN + i] = acc_p;
+        a.part[2 * BN + i] = acc_d;
+        a.part[3 * BN + i] = acc_th;
+        a.part[4 * BN + i] = acc_bias;
+    }
+}
+
 // Register prefetch depth, in blocks. Between two blocks a wave does only the
 // block's arithmetic and the carry update, so short blocks need more of them in
 // flight to cover the HBM latency: the depth targets a number of time steps
@@ -1068,8 +1370,23 @@ template <int SEG, int L>
 hipError_t blocks_bwd_launch(const BwdArgs &a, hipStream_t st) {
     const int grid = a.B * a.n_groups;
     if (grid == 0) return hipSuccess;
-    const size_t sm = bwd_smem_bytes<SEG, L>(a.TR);
     constexpr int TH = Geo<SEG>::THREADS;
+    if (a.attached) {
+        const size_t sma = bwd_att_smem_bytes<SEG, L>(a.TR);
+#define ALIF_LA(SG)                                                                                     \
+    do {                                                                                                \
+        if (a.TR == SEG * L)                                                                            \
+            hipLaunchKernelGGL((k_blocks_bwd_att<SEG, L, true, SG>), dim3(grid), dim3(TH), sma, st, a); \
+        else                                                                                            \
+            hipLaunchKernelGGL((k_blocks_bwd_att<SEG, L, false, SG>), dim3(grid), dim3(TH), sma, st, a);\
+    } while (0)
+        if (a.surrogate == 1) ALIF_LA(1);
+        else if (a.surrogate == 2) ALIF_LA(2);
+        else ALIF_LA(0);
+#undef ALIF_LA
+        return hipGetLastError();
+    }
+    const size_t sm = bwd_smem_bytes<SEG, L>(a.TR);
     const bool gvt = a.gV || a.gTH, gi = a.gI != nullptr;
 #define ALIF_LB3(G1, G2, SG)                                                                      \
     do {                                                                                          \

@@ -51,6 +51,7 @@ struct BwdArgs {
     int B, T, N, TR, NB, n_groups;
     double dt;
     int surrogate;  // enum alif_surrogate
+    int attached;   // gradient policy: 1 = attached (reset and adaptation uses of the spike carry gradient)
     float slope;
     const float *I;
     const float *bias_k;
