@@ -186,6 +186,22 @@ SeqCarryView seq_carry_view(void *base, size_t cn) {
 
 namespace alif {
 int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+// Backward workspace: FP64 partial sums [5][B][N]; for spike input the weight-gradient
+// GEMM's split partials; with BF16 GEMMs, W transposed and rounded to bfloat16 once
+// for the input gradient.
+struct BwdWs {
+    size_t part, gemm, wt, total;
+};
+BwdWs bwd_ws_layout(const alif_desc *desc, const Prob &p) {
+    BwdWs w;
+    w.part = 0;
+    w.gemm = align256((size_t)5 * p.B * p.N * sizeof(double));
+    w.wt = w.gemm + (p.spikes_in ? align256(gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.n_in)) : 0);
+    const bool wt = p.spikes_in && desc->gemm_precision == ALIF_GEMM_BF16;
+    w.total = w.wt + (wt ? align256(gemm_wbf16_bytes(p.N, p.n_in)) : 0);
+    return w;
+}
+
 }  // namespace alif
 
 extern "C" {
@@ -214,8 +230,7 @@ int alif_backward_workspace_bytes(const alif_desc *desc, size_t *bytes) {
     int rc = check_desc(desc, &p);
     if (rc) return rc;
     if (!bytes) return fail(ALIF_EINVAL, "bytes is NULL");
-    *bytes = align256((size_t)5 * p.B * p.N * sizeof(double)) +
-             (p.spikes_in ? gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.n_in) : 0);
+    *bytes = bwd_ws_layout(desc, p).total;
     return ALIF_OK;
 }
 
@@ -318,8 +333,11 @@ int alif_forward(const alif_desc *desc, const alif_params *prm, const void *inpu
         GemmIn in;
         in.kind = desc->input_kind;
         in.ptr = input;
+        // the spike output, written only after the GEMM, holds the bfloat16 weights meanwhile
+        const size_t sbytes = (size_t)p.B * p.T * p.N *
+                              (desc->spike_dtype == ALIF_SPIKES_U8 ? 1 : (desc->spike_dtype == ALIF_SPIKES_BF16 ? 2 : 4));
         hipError_t e = gemm_input_current((size_t)p.B * p.T, p.N, p.n_in, in, W, prm->bias, current,
-                                          desc->gemm_precision == ALIF_GEMM_BF16, st);
+                                          desc->gemm_precision == ALIF_GEMM_BF16, st, spikes, sbytes);
         if (e != hipSuccess) return hip_fail(e, "input-current GEMM");
         I = current;
         bias_k = nullptr;
@@ -470,7 +488,8 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
         GemmIn in;
         in.kind = desc->input_kind;
         in.ptr = input;
-        void *gws = (char *)workspace + align256((size_t)5 * p.B * p.N * sizeof(double));
+        const BwdWs lay = bwd_ws_layout(desc, p);
+        void *gws = (char *)workspace + lay.gemm;
         if (grad_W) {
             e = gemm_weight_grad((size_t)p.B * p.T, p.N, p.n_in, grad_current, in, grad_W,
                                  desc->gemm_precision == ALIF_GEMM_BF16, gws, st);
@@ -478,7 +497,8 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
         }
         if (grad_input) {
             e = gemm_input_grad((size_t)p.B * p.T, p.N, p.n_in, grad_current, W, grad_input,
-                                desc->gemm_precision == ALIF_GEMM_BF16, st);
+                                desc->gemm_precision == ALIF_GEMM_BF16, st, (char *)workspace + lay.wt,
+                                lay.total - lay.wt);
             if (e != hipSuccess) return hip_fail(e, "input-gradient GEMM");
         }
     }
@@ -495,8 +515,8 @@ int alif_backward_noalloc(const alif_desc *desc, const alif_params *prm, const v
     if (rc) return rc;
     // the scratch alif_backward would take as its workspace: the partial sums, and
     // the split-K tiles only when the weight gradient is asked for
-    const size_t need = align256((size_t)5 * p.B * p.N * sizeof(double)) +
-                        ((p.spikes_in && grad_W) ? gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.n_in) : 0);
+    const BwdWs lay = bwd_ws_layout(desc, p);
+    const size_t need = (grad_input && lay.total > lay.wt) ? lay.total : (grad_W ? lay.wt : lay.gemm);
     if (need > (size_t)ALIF_NOALLOC_SCRATCH_BYTES)
         return fail(ALIF_EUNSUPPORTED,
                     "alif_backward_noalloc: this problem needs %zu bytes of scratch, more than the %u-byte "
@@ -581,7 +601,9 @@ int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm, const 
         GemmIn in;
         in.kind = desc->input_kind;
         in.ptr = input;
-        e = gemm_input_current((size_t)p.B * p.T, p.N, p.n_in, in, W, prm->bias, current, bf16, st);
+        // the spike output, written only at the end, holds the bfloat16 weights meanwhile
+        e = gemm_input_current((size_t)p.B * p.T, p.N, p.n_in, in, W, prm->bias, current, bf16, st, spikes,
+                               BTN * (size_t)spike_elem_bytes(desc->spike_dtype));
         if (e != hipSuccess) return hip_fail(e, "input-current GEMM");
         bias_k = nullptr;
     } else {

@@ -12,15 +12,22 @@ struct GemmIn {
     const void *ptr;  // [M][K] row-major
 };
 
-// out[M][N] = bias[N] + x[M][K] . W[N][K]^T
+// out[M][N] = bias[N] + x[M][K] . W[N][K]^T. With bf16, a scratch of at least
+// gemm_wbf16_bytes(N, K) bytes (16-byte aligned; nullptr: none) receives W rounded
+// to bfloat16 once, so that the GEMM streams half the weight bytes and converts
+// only x.
 hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, const float *bias,
-                              float *out, bool bf16, hipStream_t st);
+                              float *out, bool bf16, hipStream_t st, void *scratch = nullptr,
+                              size_t scratch_bytes = 0);
+// bytes of the bfloat16 copy of a [N][K] weight matrix
+size_t gemm_wbf16_bytes(int N, int K);
 // gW[N][K] = sum_m gI[m][n] x[m][k]   (split over m, reduced in a fixed order)
 hipError_t gemm_weight_grad(size_t M, int N, int K, const float *gI, GemmIn x, float *gW, bool bf16,
                             void *ws, hipStream_t st);
-// gx[M][K] = gI[M][N] . W[N][K]
+// gx[M][K] = gI[M][N] . W[N][K]. With bf16, a scratch of gemm_wbf16_bytes(N, K)
+// bytes (as above) receives W transposed and rounded to bfloat16 once.
 hipError_t gemm_input_grad(size_t M, int N, int K, const float *gI, const float *W, float *gx,
-                           bool bf16, hipStream_t st);
+                           bool bf16, hipStream_t st, void *scratch = nullptr, size_t scratch_bytes = 0);
 // scratch bytes gemm_weight_grad needs for its split partial sums
 size_t gemm_workspace_bytes(size_t M, int N, int K);
 

@@ -15,6 +15,7 @@
 #include "../../include/blockalif.h"
 #include "alif_common.h"
 #include "alif_gemm.h"
+#include "alif_gemm_big.h"
 
 namespace alif {
 
@@ -580,6 +581,7 @@ __global__ void k_split_reduce(long long MN, int N, int splits, const float *P, 
 
 hipError_t gemm_launch(const GemmArgs &g, bool bf16, hipStream_t st) {
     if (g.M == 0 || g.N == 0) return hipSuccess;
+    if (bf16 && gemm_big_ok(g)) return gemm_big_launch(g, st);
     if (tiled_ok(g, bf16)) {
         int splits = 1;
         hipError_t e = bf16 ? tiled_launch<true>(g, st, &splits) : tiled_launch<false>(g, st, &splits);
@@ -605,13 +607,51 @@ static int dt_of(int kind) {
     return kind == ALIF_INPUT_SPIKES_U8 ? 1 : (kind == ALIF_INPUT_SPIKES_BF16 ? 2 : 0);
 }
 
+// W [N][K] float -> bfloat16 (round to nearest even), the same layout (TRANS = false)
+// or transposed to [K][N] (TRANS = true, through a 32 x 32 LDS tile)
+template <bool TRANS>
+__global__ __launch_bounds__(256) void k_w_bf16(int N, int K, const float *W, __bf16 *out) {
+    if constexpr (!TRANS) {
+        const long long n = (long long)N * K;
+        for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+            out[i] = (__bf16)W[i];
+    } else {
+        __shared__ float t[32][33];
+        const int k0 = blockIdx.x * 32, n0 = blockIdx.y * 32;
+        const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+        for (int r = ty; r < 32; r += 8)
+            t[r][tx] = (n0 + r < N && k0 + tx < K) ? W[(size_t)(n0 + r) * K + k0 + tx] : 0.0f;
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8)
+            if (k0 + r < K && n0 + tx < N) out[(size_t)(k0 + r) * N + n0 + tx] = (__bf16)t[tx][r];
+    }
+}
+
+size_t gemm_wbf16_bytes(int N, int K) { return (size_t)N * K * 2; }
+
+static bool scratch_fits(const void *scratch, size_t bytes, int N, int K) {
+    return scratch && bytes >= gemm_wbf16_bytes(N, K) && (reinterpret_cast<uintptr_t>(scratch) & 15) == 0;
+}
+
 hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, const float *bias,
-                              float *out, bool bf16, hipStream_t st) {
+                              float *out, bool bf16, hipStream_t st, void *scratch, size_t scratch_bytes) {
     GemmArgs g{};
     g.M = (long long)M; g.N = N; g.K = K;
     g.A = x.ptr; g.a_dt = dt_of(x.kind); g.lda = K; g.a_kc = 1;
     g.B = W; g.b_dt = 0; g.ldb = K; g.b_kc = 1;
     g.C = out; g.ldc = N; g.bias = bias; g.splits = 1;
+    if (bf16 && M > 0 && N > 0 && scratch_fits(scratch, scratch_bytes, N, K)) {
+        GemmArgs h = g;
+        h.B = scratch; h.b_dt = 2;
+        if (gemm_big_ok(h)) {
+            const long long n = (long long)N * K;
+            const unsigned grid = (unsigned)((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048);
+            hipLaunchKernelGGL(k_w_bf16<false>, dim3(grid), dim3(256), 0, st, N, K, W, static_cast<__bf16 *>(scratch));
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            return gemm_big_launch(h, st);
+        }
+    }
     return gemm_launch(g, bf16, st);
 }
 
@@ -644,13 +684,24 @@ hipError_t gemm_weight_grad(size_t M, int N, int K, const float *gI, GemmIn x, f
 }
 
 hipError_t gemm_input_grad(size_t M, int N, int K, const float *gI, const float *W, float *gx,
-                           bool bf16, hipStream_t st) {
+                           bool bf16, hipStream_t st, void *scratch, size_t scratch_bytes) {
     // C[m][k] = sum_n gI[m][n] W[n][k]
     GemmArgs g{};
     g.M = (long long)M; g.N = K; g.K = N;
     g.A = gI; g.a_dt = 0; g.lda = N; g.a_kc = 1;
     g.B = W; g.b_dt = 0; g.ldb = K; g.b_kc = 0;
     g.C = gx; g.ldc = K; g.bias = nullptr; g.splits = 1;
+    if (bf16 && M > 0 && K > 0 && scratch_fits(scratch, scratch_bytes, N, K)) {
+        GemmArgs h = g;   // B(k, n) = W^T[k][n]: k-contiguous in the transposed copy
+        h.B = scratch; h.b_dt = 2; h.ldb = N; h.b_kc = 1;
+        if (gemm_big_ok(h)) {
+            hipLaunchKernelGGL(k_w_bf16<true>, dim3((unsigned)((K + 31) / 32), (unsigned)((N + 31) / 32)), dim3(256), 0,
+                               st, N, K, W, static_cast<__bf16 *>(scratch));
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            return gemm_big_launch(h, st);
+        }
+    }
     return gemm_launch(g, bf16, st);
 }
 

@@ -111,6 +111,56 @@ def test_input_grad_gemm(prec, shape):
     assert (err <= bound).all(), float((err / bound).max())
 
 
+@pytest.mark.parametrize("kind", ["u8", "bf16"])
+@pytest.mark.parametrize("shape", [(2, 301, 300, 260), (1, 700, 1024, 512)])
+def test_bf16_layer_gemms_with_weight_copies(kind, shape):
+    """A spike-input layer with BF16 GEMMs through alif_forward / alif_backward, at
+    shapes the large-tile kernel takes (ragged tiles and k). The forward rounds W to
+    bfloat16 once into the spike output before the block kernel fills it; the
+    backward's input gradient uses W transposed and rounded into its workspace.
+    The current and dL/dx against the oracle's FP64 products of the same rounded
+    operands, within the FP32 accumulation bound; the layer's spikes equal those of
+    the same layer fed the oracle-checked current."""
+    import torch
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif
+    B, T, n_in, N = shape
+    g = rng(sum(shape) + 77)
+    x = bernoulli_spikes(g, (B, T, n_in), 0.1)
+    W = normal_weights(g, N, n_in) * 4.0
+    prm = random_params(sum(shape), N, bias=(0.5, 1.5))
+    log(f"[bf16 layer] {kind} B={B} T={T} n_in={n_in} N={N}")
+    xt = _as_torch_spikes(x, kind)
+    Wt = torch.as_tensor(W, device="cuda")
+    P = to_dev(prm)
+    f = alif.forward(xt, P, 0.5, 2.0, Wt, gemm_precision=L.GEMM_BF16, save=True)
+    gS = torch.as_tensor(g.standard_normal((B, T, N)).astype(np.float32), device="cuda")
+    out = alif.backward(f, xt, P, Wt, grad_spikes=gS, want_grad_input=True, want_grad_W=True)
+    torch.cuda.synchronize()
+    Wr = _bf16_round(W)
+    cur = np_(f["current"])
+    ref = oracle.input_current(x, Wr, prm.bias)
+    bound = _gemm_bound(x.reshape(-1, n_in).astype(np.float64), np.abs(Wr).T, n_in).reshape(ref.shape) \
+        + 2.0 ** -24 * np.abs(ref)
+    err = np.abs(cur - ref)
+    assert (err <= bound).all(), float((err / bound).max())
+    # the same layer on the checked current gives the same spikes (the weight copy in the
+    # spike buffer was overwritten by the block kernel)
+    f2 = alif.forward(f["current"].contiguous(), alif.Params(P.tau_mem, P.tau_adapt, P.d, P.theta0), 0.5, 2.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(np_(f2["spikes"]), np_(f["spikes"]))
+    gI = np_(out["grad_current"])
+    gr = _bf16_round(gI)
+    dref = oracle.input_grad(gr, Wr)
+    dbound = _gemm_bound(gr.reshape(-1, N), Wr, N).reshape(dref.shape)
+    derr = np.abs(np_(out["grad_input"]).astype(np.float64) - dref)
+    assert (derr <= dbound).all(), float((derr / dbound).max())
+    wref = oracle.weight_grad(gr, x)
+    wbound = _gemm_bound(gr.reshape(-1, N).T, x.reshape(-1, n_in).astype(np.float64), B * T)
+    werr = np.abs(np_(out["grad_W"]) - wref)
+    assert (werr <= wbound).all(), float((werr / wbound).max())
+
+
 def _spike_layer_case(seed, B, T, n_in, N, dt, rate=0.05, bias=(1.0, 2.0)):
     g = rng(seed)
     x = bernoulli_spikes(g, (B, T, n_in), rate)
