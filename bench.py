@@ -594,7 +594,8 @@ def fit_sweep(epochs=100, seq_epochs=5, N=2048, seed=31, configs=FIT_CONFIGS):
 def recurrent_leg(w, I, P, gS, steps=3):
     """The fine-DT workload as a recurrent network: the OU current plus
     W_rec S[t - T_R] (W_rec ~ N(0, 0.5^2 / N)), T_R = 40, so 500 blocks run one
-    after another, each a recurrent GEMM and a one-block kernel launch. Times the
+    after another inside one launch (a workgroup per batch element gathers each
+    block's recurrent input from the previous block's spikes). Times the
     forward eagerly and as a captured HIP graph replay (torch.cuda.CUDAGraph on
     the library's launches), and the detached backward with dW_rec, next to the
     feedforward forward of the same shape."""

@@ -597,6 +597,7 @@ int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm, const 
     hipError_t e;
     // the current without its recurrent part: b + W x (spike input) or the input
     // itself (current input; the bias is then added in-kernel, as alif_forward does)
+    const bool fused = recurrent_fused_ok(p.N, p.TR, D);
     if (p.spikes_in) {
         GemmIn in;
         in.kind = desc->input_kind;
@@ -606,7 +607,7 @@ int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm, const 
                                BTN * (size_t)spike_elem_bytes(desc->spike_dtype));
         if (e != hipSuccess) return hip_fail(e, "input-current GEMM");
         bias_k = nullptr;
-    } else {
+    } else if (!fused) {   // the one-launch layer reads the input and writes the whole current itself
         e = hipMemcpyAsync(current, input, BTN * sizeof(float), hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "current copy");
     }
@@ -621,6 +622,26 @@ int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm, const 
     float *wrt = (float *)(stb + L.state);
     e = launch_transpose(p.N, W_rec, wrt, st);
     if (e != hipSuccess) return hip_fail(e, "W_rec transpose launch");
+    if (fused) {   // the whole block loop in one launch
+        RecArgs r{};
+        r.B = p.B; r.T = p.T; r.N = p.N; r.TR = p.TR; r.NB = p.NB; r.D = D;
+        r.ring = recurrent_ring_slots(p.TR, D);
+        r.dt = desc->dt_ms;
+        r.I_ff = p.spikes_in ? current : (const float *)input;
+        r.I = current;
+        r.bias_k = bias_k;
+        r.tau_m = prm->tau_mem_ms; r.tau_a = prm->tau_adapt_ms; r.d = prm->d; r.theta0 = prm->theta0;
+        r.WrecT = wrt;
+        r.spikes = spikes;
+        r.spike_dtype = desc->spike_dtype;
+        r.V = v;
+        r.TH = theta;
+        if (carries) r.ck = carry_view(carries, p);
+        r.status = status;
+        e = launch_recurrent_fused(r, st);
+        if (e != hipSuccess) return hip_fail(e, "recurrent layer launch");
+        return ALIF_OK;
+    }
     const int nwg = block_neurons_per_wg(block_config(p.TR).seg);
     const size_t TN = (size_t)p.T * p.N, TRN = (size_t)p.TR * p.N;
     const int sb = spike_elem_bytes(desc->spike_dtype);

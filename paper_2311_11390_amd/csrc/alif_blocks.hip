@@ -105,6 +105,59 @@ hipError_t launch_blocks_bwd(const BwdArgs &a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// one-launch recurrent layer (alif_recurrent_impl.h)
+// ---------------------------------------------------------------------------
+template <int S, int L, int NG>
+hipError_t recurrent_fused_launch(const RecArgs &, hipStream_t);
+#define ALIF_REC_G2(X) X(1, 2) X(1, 3) X(1, 4) X(2, 3) X(2, 4) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(4, 8) X(8, 5) \
+    X(8, 6) X(8, 8) X(8, 10) X(8, 12) X(8, 13) X(8, 14) X(8, 15) X(8, 16)
+#define ALIF_REC_G4(X) X(1, 2) X(1, 3) X(1, 4) X(2, 3) X(2, 4) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(4, 8) X(4, 9) \
+    X(4, 10) X(4, 11) X(4, 12) X(4, 13) X(4, 14) X(4, 15) X(4, 16)
+#define ALIF_REC_EXT2(S, L) extern template hipError_t recurrent_fused_launch<S, L, 2>(const RecArgs &, hipStream_t);
+#define ALIF_REC_EXT4(S, L) extern template hipError_t recurrent_fused_launch<S, L, 4>(const RecArgs &, hipStream_t);
+ALIF_REC_G2(ALIF_REC_EXT2)
+ALIF_REC_G4(ALIF_REC_EXT4)
+
+// (neuron groups, segments, steps per segment) of the one-launch recurrent layer:
+// the block forward's segmentation, capped at four segments for four groups
+// (1024 threads); {0, 0, 0} if not covered.
+struct RecConfig {
+    int ng, seg, len;
+};
+static RecConfig rec_config(int N, int TR) {
+    if (N < 1 || N > 256) return {0, 0, 0};
+    const BlockConfig bc = block_config(TR);
+    if (N <= 128) return {2, bc.seg, bc.len};
+    if (bc.seg <= 4) return {4, bc.seg, bc.len};
+    if (TR > 64) return {0, 0, 0};
+    return {4, 4, (TR + 3) / 4};
+}
+
+int recurrent_ring_slots(int TR, int D) { return D > TR ? (D + TR - 1) / TR : 0; }
+
+static size_t rec_smem_bytes(const RecConfig &c, int TR, int D) {
+    const size_t nwg = (size_t)64 * c.ng;
+    return nwg * TR * sizeof(double) + (size_t)3 * c.seg * nwg * 4 + (size_t)recurrent_ring_slots(TR, D) * nwg;
+}
+
+bool recurrent_fused_ok(int N, int TR, int D) {
+    const RecConfig c = rec_config(N, TR);
+    return c.ng != 0 && D >= TR && rec_smem_bytes(c, TR, D) <= (size_t)160 * 1024;
+}
+
+hipError_t launch_recurrent_fused(const RecArgs &a, hipStream_t st) {
+    if (!recurrent_fused_ok(a.N, a.TR, a.D) || a.ring != recurrent_ring_slots(a.TR, a.D)) return hipErrorInvalidValue;
+    const RecConfig c = rec_config(a.N, a.TR);
+#define ALIF_RL2(S, L) if (c.ng == 2 && c.seg == S && c.len == L) return recurrent_fused_launch<S, L, 2>(a, st);
+#define ALIF_RL4(S, L) if (c.ng == 4 && c.seg == S && c.len == L) return recurrent_fused_launch<S, L, 4>(a, st);
+    ALIF_REC_G2(ALIF_RL2)
+    ALIF_REC_G4(ALIF_RL4)
+#undef ALIF_RL2
+#undef ALIF_RL4
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
 // layout moves of the recurrent layer (grid-stride loops over the output)
 // ---------------------------------------------------------------------------
 // Recurrent current of one block from earlier spikes, event-driven (a neuron

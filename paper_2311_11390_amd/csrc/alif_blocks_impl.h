@@ -124,11 +124,11 @@ struct Lane {
     }
 };
 
-template <int SEG, int L, bool EVEN>
+// NG: neuron groups of 64 per workgroup (wave = segment * NG + group)
+template <int SEG, int L, bool EVEN, int NG = Geo<SEG>::NG>
 __device__ __forceinline__ void lane_setup(Lane<SEG, L, EVEN> &c, int N, int TR, double dt, int n0,
                                            const float *tau_m, const float *tau_a, const float *d,
                                            const float *theta0, const float *bias) {
-    constexpr int NG = Geo<SEG>::NG;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // uniform over the wave (and the constant 0 with one segment per block)
     c.w = SEG == 1 ? 0 : __builtin_amdgcn_readfirstlane(wave / NG);
@@ -184,10 +184,9 @@ __device__ __forceinline__ void lane_setup(Lane<SEG, L, EVEN> &c, int N, int TR,
 
 // Tables for data-dependent exponents: pd[j][k] = p^k (FP64, k < T_R) for the
 // carry; pfp[j][T_R + e] = p^e (FP32, e >= 0; 0 for e < 0) for post-spike values.
-template <int SEG, int L>
+template <int SEG, int L, int NWG = Geo<SEG>::NWG>
 __device__ __forceinline__ void build_p_tables(double *pd, float *pfp, int n0, int N, int TR,
                                                double dt, const float *tau_a) {
-    constexpr int NWG = Geo<SEG>::NWG;
     const int RL = ptab_row(TR, L);
     if (pd) {
         for (int idx = threadIdx.x; idx < NWG * TR; idx += blockDim.x) {
@@ -195,9 +194,11 @@ __device__ __forceinline__ void build_p_tables(double *pd, float *pfp, int n0, i
             pd[idx] = exp(-dt / (double)tau_a[min(n0 + jj, N - 1)] * (double)k);
         }
     }
-    for (int idx = threadIdx.x; idx < NWG * RL; idx += blockDim.x) {
-        const int jj = idx / RL, e = idx - jj * RL - TR;
-        pfp[idx] = e < 0 ? 0.0f : (float)exp(-dt / (double)tau_a[min(n0 + jj, N - 1)] * (double)e);
+    if (pfp) {
+        for (int idx = threadIdx.x; idx < NWG * RL; idx += blockDim.x) {
+            const int jj = idx / RL, e = idx - jj * RL - TR;
+            pfp[idx] = e < 0 ? 0.0f : (float)exp(-dt / (double)tau_a[min(n0 + jj, N - 1)] * (double)e);
+        }
     }
     __syncthreads();
 }
@@ -230,9 +231,8 @@ __device__ __forceinline__ void seg_scan(const Lane<SEG, L, EVEN> &c, const floa
 // From the segment ends X[s] of one block (each lane's own neuron): the input
 // part of the membrane at this lane's segment start (E) and at the block end (U),
 // combined in segment order (Horner).
-template <int SEG, int L, bool EVEN>
+template <int SEG, int L, bool EVEN, int NWG = Geo<SEG>::NWG>
 __device__ __forceinline__ void seg_horner(const Lane<SEG, L, EVEN> &c, const float *X, float &E, float &U) {
-    constexpr int NWG = Geo<SEG>::NWG;
     float e = 0.0f, u = 0.0f;
 #pragma unroll
     for (int s = 0; s < SEG; s++) {

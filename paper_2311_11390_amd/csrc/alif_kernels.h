@@ -62,6 +62,24 @@ struct BwdArgs {
     double *part;  // [5][B][N]
 };
 
+// Recurrent layer in one launch (one workgroup per batch element)
+struct RecArgs {
+    int B, T, N, TR, NB;
+    int D;                // recurrent delay in steps, >= T_R
+    int ring;             // slots of the LDS ring of older blocks' spike steps (0 when D == T_R)
+    double dt;
+    const float *I_ff;    // [B][T][N] feed-forward current (may equal I)
+    float *I;             // [B][T][N] the whole current (every row written)
+    const float *bias_k;  // added in-kernel, nullable
+    const float *tau_m, *tau_a, *d, *theta0;
+    const float *WrecT;   // [N][N], WrecT[j][i] = W_rec[i][j]
+    void *spikes;         // [B][T][N]
+    int spike_dtype;
+    float *V, *TH;
+    CarryView ck;
+    unsigned *status;
+};
+
 struct SeqArgs {
     int B, T, N, TR, NB;
     double dt;
@@ -114,6 +132,11 @@ hipError_t launch_blocks_to_bt(int B, int T, int N, int TR, int elem, const void
 hipError_t launch_recurrent_events(int B, int TR, int rows, int N, long long bstride, int t0, int D, int elem,
                                    const void *blocks, size_t blk_bytes, const float *WrecT, float *C,
                                    hipStream_t st);
+// Whether the one-launch recurrent layer covers (N, T_R, D) (N <= 256 and the
+// workgroup's LDS); launch it (alif_forward_recurrent's whole block loop).
+bool recurrent_fused_ok(int N, int TR, int D);
+int recurrent_ring_slots(int TR, int D);
+hipError_t launch_recurrent_fused(const RecArgs &a, hipStream_t st);
 // out[j][i] = in[i][j], N x N float
 hipError_t launch_transpose(int N, const float *in, float *out, hipStream_t st);
 // out[b][t][i] = in[b][t - D][i] for t >= D, else 0 (elements of `elem` bytes)

@@ -129,6 +129,71 @@ def test_recurrent_longer_delay(TR, dt, D):
     log(f"    D={D}: excused {excused}, max|dV| {dV:.1e}")
 
 
+# (N, T_R, dt, D): layers up to 256 neurons run the whole block loop in one launch
+# (one workgroup per batch element; 129-256 neurons with four segments: T_R 37 and
+# 40 take 10 steps a segment, 37 with padding, 64 takes 16); D > T_R reads older
+# blocks' spike steps from the ring (D 53: two source blocks per target block; D
+# 120: three blocks back); N 300 and (200, T_R 80) keep the per-block launches.
+# (DT = ARP / T_R with ARP 2 ms.)
+_WIDE = [(200, 20, 0), (256, 40, 0), (160, 37, 0), (256, 64, 0), (256, 40, 53), (200, 40, 120), (100, 8, 19),
+         (300, 5, 0), (200, 80, 0)]
+
+
+def _dt_for(TR):
+    from paper_2311_11390_amd import alif
+    dt = 2.0 / TR
+    assert alif.refractory_steps(dt, 2.0) == TR
+    return dt
+
+
+@pytest.mark.parametrize("N,TR,D", _WIDE)
+def test_recurrent_wide_layers(N, TR, D):
+    B = 2
+    dt = _dt_for(TR)
+    T = 9 * TR + TR // 3 + 1            # a ragged last block
+    f, orc, excused, prm, *_ = _case(1200 + N + TR + D, B, T, N, TR, dt, gain=1.5, D=D)
+    S = np_(f["spikes"])
+    assert S.sum() > 50
+    dV = np.abs(np_(f["v"]) - orc["V"]).max()
+    dTH = np.abs(np_(f["theta"]) - orc["TH"]).max()
+    dI = np.abs(np_(f["current"]) + prm.bias[None, None, :] - orc["Itot"]).max()
+    log(f"    spikes {int(S.sum())}, excused {excused}, max|dV| {dV:.1e}, max|dTH| {dTH:.1e}, max|dI| {dI:.1e}")
+    assert dV <= TRACE_TOL and dTH <= TRACE_TOL and dI <= 1e-4
+    assert np.abs(orc["Itot"] - (driven_input(1200 + N + TR + D, B, T, N) + prm.bias)).max() > 0.1
+
+
+@pytest.mark.parametrize("N,TR,D", [(67, 5, 0), (200, 20, 0), (130, 4, 9), (256, 32, 0), (120, 40, 0), (64, 100, 0)])
+def test_recurrent_whole_current_replays_as_feedforward(N, TR, D):
+    """The whole current the recurrent layer returns, fed to alif_forward, gives
+    the same spikes bit for bit and the same traces and carries (where the
+    one-launch layer uses the block forward's segmentation of T_R): the recurrent
+    term is the only difference between the two kernels."""
+    import torch
+
+    from paper_2311_11390_amd import alif
+    B = 3
+    T = 11 * TR + 2
+    dt = _dt_for(TR)
+    f, orc, excused, prm, P, inp, Wt = _case(1300 + N + TR, B, T, N, TR, dt, gain=1.5, D=D)
+    ff = alif.forward(f["current"].contiguous(), P, dt, 2.0, want_v=True, want_theta=True, save=True)
+    torch.cuda.synchronize()
+    log(f"    spikes {int(np_(f['spikes']).sum())}")
+    np.testing.assert_array_equal(np_(ff["spikes"]), np_(f["spikes"]))
+    np.testing.assert_array_equal(np_(ff["v"]), np_(f["v"]))
+    np.testing.assert_array_equal(np_(ff["theta"]), np_(f["theta"]))
+    np.testing.assert_array_equal(_carry_planes(ff["carries"], B, T, N, TR),
+                                  _carry_planes(f["carries"], B, T, N, TR))
+
+
+def _carry_planes(carries, B, T, N, TR):
+    """The saved carries as bytes, padding left out: [B][NB + 1][N] floats of V,
+    then (256-byte aligned) of a, then uint8 spike steps."""
+    raw = np_(carries).tobytes()
+    cn = B * (-(-T // TR) + 1) * N
+    o = (cn * 4 + 255) // 256 * 256
+    return np.frombuffer(raw[:cn * 4] + raw[o:o + cn * 4] + raw[2 * o:2 * o + cn], np.uint8)
+
+
 def test_recurrent_without_reach_equals_feedforward():
     """D >= T (and a run shorter than one block): the recurrent term never
     applies, so the block-by-block run must equal alif_forward on the same
