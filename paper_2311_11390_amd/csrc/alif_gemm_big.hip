@@ -35,17 +35,19 @@ __device__ __forceinline__ uint32_t pk_bf16(float lo, float hi) {
     return __builtin_bit_cast(uint32_t, v);
 }
 
-// one load: per-lane offset voff plus a wave-uniform offset soff (an SGPR operand)
+// One load at byte offset voff. The whole offset goes in the VGPR operand: the
+// buffer range check covers the VGPR offset and the instruction's immediate but
+// not the SGPR offset, so an offset carried there could read past the operand.
 template <int BYTES>
-__device__ __forceinline__ void ld_raw(rsrc_t r, uint32_t voff, uint32_t soff, uint32_t *w) {
+__device__ __forceinline__ void ld_raw(rsrc_t r, uint32_t voff, uint32_t *w) {
     if constexpr (BYTES == 16) {
-        const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
         w[0] = x[0];
         w[1] = x[1];
         w[2] = x[2];
         w[3] = x[3];
     } else {
-        w[0] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+        w[0] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0);
     }
 }
 
@@ -98,7 +100,10 @@ struct Op {
             const long long nr = rows - rbase < TM ? rows - rbase : TM;
             const int row0 = tid >> 3;
             base = p + ((size_t)rbase * ld + kb) * ES;
-            ext = (uint32_t)(((size_t)(nr - 1) * ld + (size_t)(ke - kb)) * ES);
+            // rounded up to the load width: a load that straddles the last valid k keeps its
+            // valid part (the range check drops whole dwords); the rounding stays inside the
+            // row's padding, as rows are LB-aligned and ld >= K
+            ext = (uint32_t)((((size_t)(nr - 1) * ld + (size_t)(ke - kb)) * ES + LB - 1) / LB * LB);
             sstep = (uint32_t)(TK * ES);
             voff0 = (uint32_t)(((size_t)row0 * ld + (size_t)kc0 * 8) * ES);
             ustep = (uint32_t)((size_t)32 * ld * ES);
@@ -107,7 +112,8 @@ struct Op {
         } else {
             const int rg0 = tid >> 3;
             base = p + ((size_t)kb * ld + rbase) * ES;
-            ext = (uint32_t)(((size_t)(ke - kb - 1) * ld + (size_t)(rows - rbase)) * ES);
+            // rounded up as above (rows are LB-aligned and ld >= rows)
+            ext = (uint32_t)((((size_t)(ke - kb - 1) * ld + (size_t)(rows - rbase)) * ES + LB - 1) / LB * LB);
             sstep = (uint32_t)((size_t)TK * ld * ES);
             voff0 = (uint32_t)(((size_t)kc0 * 8 * ld + (size_t)rg0 * Q) * ES);
             ustep = (uint32_t)(32 * Q * ES);
@@ -131,7 +137,8 @@ struct Op {
         for (int u = U0; u < U1; u++)
 #pragma unroll
             for (int l = 0; l < LOADS; l++)
-                ld_raw<LB>(r, voff0, __builtin_amdgcn_readfirstlane(u * ustep + l * lstep), &w[(u * LOADS + l) * LW]);
+                ld_raw<LB>(r, voff0 + (uint32_t)__builtin_amdgcn_readfirstlane(u * ustep + l * lstep),
+                           &w[(u * LOADS + l) * LW]);
     }
 
     // convert units [U0, U1) of stage s from w and store them to the LDS buffer at buf
@@ -349,10 +356,12 @@ __global__ __launch_bounds__(THREADS, 1) void k_gemm_big(BigArgs ba) {
         for (int i = 0; i < 4; i++)
 #pragma unroll
             for (int r = 0; r < 16; r++) {
-                // uniform part of the row: i * 32 + 8 (r / 4) + r % 4 rows
+                // uniform part of the row: i * 32 + 8 (r / 4) + r % 4 rows. It is added to the
+                // VGPR offset (rows past M then fall past the descriptor's end; an SGPR offset
+                // would not be range-checked)
                 const uint32_t so = (uint32_t)(i * 32 + 8 * (r >> 2) + (r & 3)) * ldc4;
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[i][j][r] + bias), rc, cb,
-                                                      __builtin_amdgcn_readfirstlane(so), 2);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[i][j][r] + bias), rc,
+                                                      cb + (uint32_t)__builtin_amdgcn_readfirstlane(so), 0, 2);
             }
     }
 }
@@ -401,7 +410,10 @@ bool gemm_big_ok(const GemmArgs &g) {
     const size_t kspan = (size_t)(g.K + (g.splits > 1 ? g.splits : 1) - 1) / (g.splits > 1 ? g.splits : 1) + 4 * TK;
     const size_t ea = g.a_kc ? (size_t)TM * g.lda * elem_size(g.a_dt) : kspan * g.lda * elem_size(g.a_dt);
     const size_t eb = g.b_kc ? (size_t)TN * g.ldb * elem_size(g.b_dt) : kspan * g.ldb * elem_size(g.b_dt);
-    return ea < lim && eb < lim;
+    // the C tile's extent, with the column offset of an out-of-range lane added on top
+    const size_t ldc = (size_t)(g.splits > 1 ? g.N : g.ldc);
+    const size_t ec = (size_t)TM * ldc * 4;
+    return ea < lim && eb < lim && ec < lim;
 }
 
 hipError_t gemm_big_launch(const GemmArgs &g, hipStream_t st) {

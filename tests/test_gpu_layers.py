@@ -161,6 +161,41 @@ def test_bf16_layer_gemms_with_weight_copies(kind, shape):
     assert (werr <= wbound).all(), float((werr / wbound).max())
 
 
+@pytest.mark.parametrize("shape", [(1, 530, 96, 300), (3, 211, 256, 260), (1, 257, 72, 1024)])
+def test_bf16_gemm_ragged_tiles_write_only_their_output(shape):
+    """A BF16 input-current GEMM whose last row and column tiles are ragged, into an
+    output that is a view at the start of a larger buffer: every byte after the view
+    keeps its sentinel (rows and columns past the output are dropped by the store
+    path's range check, not written), and the result matches the oracle."""
+    import ctypes
+
+    import torch
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif
+    B, T, n_in, N = shape
+    g = rng(sum(shape) + 5)
+    x = bernoulli_spikes(g, (B, T, n_in), 0.2)
+    W = normal_weights(g, N, n_in)
+    b = g.standard_normal(N).astype(np.float32)
+    log(f"[gemm guard] B={B} T={T} n_in={n_in} N={N}")
+    xt = _as_torch_spikes(x, "u8")
+    total = B * T * N
+    buf = torch.full((total + 256 * N + 4096,), -7.0, dtype=torch.float32, device="cuda")
+    desc = alif.make_desc(B, T, N, 1.0, 2.0, n_in, L.INPUT_SPIKES_U8, L.GEMM_BF16)
+    Wt = torch.as_tensor(W, device="cuda")
+    bt = torch.as_tensor(b, device="cuda")
+    L.check(L.load().alif_input_current(ctypes.byref(desc), xt.data_ptr(), Wt.data_ptr(), bt.data_ptr(),
+                                        buf.data_ptr(), None))
+    torch.cuda.synchronize()
+    tail = np_(buf[total:])
+    assert (tail == -7.0).all(), int((tail != -7.0).sum())
+    out = np_(buf[:total]).reshape(B, T, N)
+    Wr = _bf16_round(W)
+    ref = oracle.input_current(x, Wr, b)
+    bound = x.astype(np.float64) @ np.abs(Wr).T + np.abs(b)
+    assert (np.abs(out - ref) <= 1e-6 * bound + 1e-7).all()
+
+
 def _spike_layer_case(seed, B, T, n_in, N, dt, rate=0.05, bias=(1.0, 2.0)):
     g = rng(seed)
     x = bernoulli_spikes(g, (B, T, n_in), rate)
