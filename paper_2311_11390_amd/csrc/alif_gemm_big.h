@@ -8,11 +8,12 @@
 // bfloat16; it is rounded to bfloat16 (nearest even; integers up to 256 and 0/1
 // spikes exactly) while it is staged through LDS.
 //
-// Tiling. A 256-thread workgroup (four waves) owns a 256 x 256 tile of C; each
-// wave owns 128 x 128 as 4 x 4 accumulators of v_mfma_f32_32x32x16_bf16, 256
-// FP32 values per lane. K moves through two LDS buffers in stages of 64: per
-// stage a wave reads 8 KiB of operand fragments for 1 MiB-flop of MFMA work (64
-// flops per LDS byte), which keeps the LDS below the matrix cores' demand. LDS
+// Tiling. A workgroup owns a 256 x 256 tile of C. With 512 threads (eight waves,
+// two per SIMD, so one wave's MFMAs run while the other converts, stores to LDS or
+// waits) each wave owns 128 x 64 as 4 x 2 accumulators of
+// v_mfma_f32_32x32x16_bf16; operand pairs that need more registers (float x float,
+// a row-contiguous bfloat16 B) run 256 threads, 128 x 128 per wave. K moves
+// through two LDS buffers in stages of 64 (128 KiB, one workgroup per CU). LDS
 // rows hold 64 k of one operand row in eight 16-byte chunks; chunk c of row r
 // sits at position c ^ ((r ^ (r >> 3)) & 7), so the MFMA fragment reads (32
 // consecutive rows, one chunk each) and the transposing stores of R-major

@@ -14,7 +14,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int TM = 256, TN = 256, TK = 64, THREADS = 256;
+constexpr int TM = 256, TN = 256, TK = 64;
 constexpr uint32_t ROWB = TK * 2;                                // LDS bytes per operand row (64 bf16)
 constexpr uint32_t BUF_A = TM * ROWB, BUF_B = TN * ROWB;         // one LDS buffer of each operand
 constexpr size_t LDS_BYTES = 2 * (size_t)(BUF_A + BUF_B);        // two buffers: 128 KiB
@@ -59,23 +59,27 @@ __device__ __forceinline__ float u8f(uint32_t w, int e) { return (float)((w >> (
 // c ^ (r % 8)).
 //   K-major ([rows][k] in memory): a unit is 8 consecutive k of one row: f32 two
 //     16-byte loads, bf16 one, uint8 two 4-byte loads. Thread t takes chunk t % 8 of
-//     rows t / 8 + 32 u, u < 8: eight threads read a row's 64 k, and the eight
+//     rows t / 8 + (NT / 8) u: eight threads read a row's 64 k, and the eight
 //     chunks they store land on different banks.
 //   R-major ([k][rows] in memory): a unit is Q consecutive rows (16 bytes; 4 bytes
 //     of uint8) at each of 8 consecutive k, transposed in registers into Q rows of
-//     8 k. Thread t takes k chunk t % 8 of row groups t / 8 + 32 u: per load
-//     instruction a wave reads 128 contiguous bytes of each of 8 k rows, and the
-//     eight threads that store one row write its eight different chunks.
+//     8 k. Thread t takes k chunk t % 8 of row groups t / 8 + (NT / 8) u (with
+//     fewer units than threads, the last waves have none): per load instruction a
+//     wave reads 128 contiguous bytes of each of 8 k rows, and the eight threads
+//     that store one row write its eight different chunks.
 // Each stage gets its own buffer descriptor starting at the stage and ending
 // where the operand's valid data ends: K-major rows past the valid ones and
 // R-major k past the range read zeros; K-major k past the range inside a valid
 // row is zeroed after the load; R-major rows past the valid ones may read other
 // data, which reaches only columns of C that are never stored.
-template <int DT, bool RMAJ>
+template <int DT, bool RMAJ, int NT>
 struct Op {
     static constexpr int ES = DT == 0 ? 4 : (DT == 1 ? 1 : 2);
     static constexpr int Q = RMAJ ? (DT == 2 ? 8 : 4) : 1;                   // rows per R-major unit
-    static constexpr int UNITS = RMAJ ? (8 * (256 / Q)) / THREADS : 8;       // units per thread per stage
+    static constexpr int TOTAL = RMAJ ? 8 * (256 / Q) : 8 * 256;              // units per stage
+    static constexpr int UNITS = TOTAL >= NT ? TOTAL / NT : 1;                // units per thread per stage
+    static constexpr bool PARTIAL = TOTAL < NT;                               // the last waves have none
+    static constexpr int RSTEP = NT / 8;                                      // rows (groups) between units
     static constexpr int LB = DT == 1 ? 4 : 16;                               // bytes per load
     static constexpr int LOADS = RMAJ ? 8 : (8 * ES) / LB;                    // loads per unit
     static constexpr int LW = LB / 4;                                          // dwords per load
@@ -90,12 +94,14 @@ struct Op {
     uint32_t lds0;      // LDS byte offset of this thread's first store
     int kspan;          // k steps in this split
     int kc0;            // this thread's k chunk
+    bool active;        // this thread (and its whole wave) has units
 
     __device__ __forceinline__ void init(const void *ptr, long long ld, long long rows, long long rbase, int kb,
                                          int ke, int tid) {
         const char *p = static_cast<const char *>(ptr);
         kspan = ke - kb;
         kc0 = tid & 7;
+        active = !PARTIAL || tid < TOTAL;
         if constexpr (!RMAJ) {
             const long long nr = rows - rbase < TM ? rows - rbase : TM;
             const int row0 = tid >> 3;
@@ -106,17 +112,17 @@ struct Op {
             ext = (uint32_t)((((size_t)(nr - 1) * ld + (size_t)(ke - kb)) * ES + LB - 1) / LB * LB);
             sstep = (uint32_t)(TK * ES);
             voff0 = (uint32_t)(((size_t)row0 * ld + (size_t)kc0 * 8) * ES);
-            ustep = (uint32_t)((size_t)32 * ld * ES);
+            ustep = (uint32_t)((size_t)RSTEP * ld * ES);
             lstep = LB;
-            lds0 = lds_off(row0, kc0);   // rows row0 + 32 u keep the position
+            lds0 = lds_off(row0, kc0);   // rows row0 + RSTEP u keep the position (RSTEP a multiple of 16)
         } else {
             const int rg0 = tid >> 3;
             base = p + ((size_t)kb * ld + rbase) * ES;
             // rounded up as above (rows are LB-aligned and ld >= rows)
             ext = (uint32_t)((((size_t)(ke - kb - 1) * ld + (size_t)(rows - rbase)) * ES + LB - 1) / LB * LB);
             sstep = (uint32_t)((size_t)TK * ld * ES);
-            voff0 = (uint32_t)(((size_t)kc0 * 8 * ld + (size_t)rg0 * Q) * ES);
-            ustep = (uint32_t)(32 * Q * ES);
+            voff0 = active ? (uint32_t)(((size_t)kc0 * 8 * ld + (size_t)rg0 * Q) * ES) : ALIF_OOB;
+            ustep = (uint32_t)(RSTEP * Q * ES);
             lstep = (uint32_t)((size_t)ld * ES);
             lds0 = (uint32_t)(rg0 * Q) * ROWB;
         }
@@ -166,9 +172,10 @@ struct Op {
 #pragma unroll
                     for (int e = 0; e < 4; e++) q[e] = (2 * e + 1 < nv) ? q[e] : (2 * e < nv ? q[e] & 0xffffu : 0u);
                 }
-                *reinterpret_cast<u32x4 *>(buf + lds0 + u * 32 * ROWB) = u32x4{q[0], q[1], q[2], q[3]};
+                *reinterpret_cast<u32x4 *>(buf + lds0 + u * RSTEP * ROWB) = u32x4{q[0], q[1], q[2], q[3]};
             }
         } else {
+            if (!active) return;   // uniform per wave
 #pragma unroll
             for (int u = U0; u < U1; u++) {
                 const uint32_t *x = &w[u * LOADS * LW];   // x[l * LW + ...]: k = 8 kc0 + l
@@ -188,9 +195,9 @@ struct Op {
                             q[h] = pk_bf16(u8f(x[l0], e), u8f(x[l1], e));
                         }
                     }
-                    // row rg Q + e; rows 32 Q u further keep the position
+                    // row rg Q + e; rows RSTEP Q u further keep the position
                     const int r = (int)(lds0 / ROWB) + e;
-                    *reinterpret_cast<u32x4 *>(buf + lds0 + e * ROWB + u * 32 * Q * ROWB +
+                    *reinterpret_cast<u32x4 *>(buf + lds0 + e * ROWB + u * RSTEP * Q * ROWB +
                                                (((uint32_t)kc0 ^ lds_swz(r)) << 4)) = u32x4{q[0], q[1], q[2], q[3]};
                 }
             }
@@ -203,8 +210,11 @@ struct BigArgs {
     int m_tiles, n_tiles, kps, total;
 };
 
-template <int ADT, bool ARM, int BDT, bool BRM>
-__global__ __launch_bounds__(THREADS, 1) void k_gemm_big(BigArgs ba) {
+template <int ADT, bool ARM, int BDT, bool BRM, int NT>
+__global__ __launch_bounds__(NT, 1) void k_gemm_big(BigArgs ba) {
+    constexpr int WN = NT / 128;          // waves along n: 2 (128 x 128 each) or 4 (128 x 64 each)
+    constexpr int WNE = TN / WN;          // columns per wave
+    constexpr int JN = WNE / 32;          // 32-column accumulators per wave
     const GemmArgs &g = ba.g;
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned char *const A0 = lds, *const A1 = lds + BUF_A;
@@ -217,20 +227,20 @@ __global__ __launch_bounds__(THREADS, 1) void k_gemm_big(BigArgs ba) {
     const int n0 = (t % ba.n_tiles) * TN;
     const int kb = z * ba.kps, ke = min(g.K, kb + ba.kps);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;              // this wave's 128 x 128 of the tile
+    const int wm = wave / WN, wn = wave % WN;             // this wave's 128 x WNE of the tile
 
-    using OA = Op<ADT, ARM>;
-    using OB = Op<BDT, BRM>;
+    using OA = Op<ADT, ARM, NT>;
+    using OB = Op<BDT, BRM, NT>;
     OA oa;
     OB ob;
     oa.init(g.A, g.lda, g.M, m0, kb, ke, tid);
     ob.init(g.B, g.ldb, g.N, n0, kb, ke, tid);
 
-    floatx16 acc[4][4];
+    floatx16 acc[4][JN];
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++)
+        for (int j = 0; j < JN; j++)
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[i][j][r] = 0.0f;
 
@@ -239,18 +249,18 @@ __global__ __launch_bounds__(THREADS, 1) void k_gemm_big(BigArgs ba) {
     // offsets. Two register sets: the reads of step kk + 1 are issued before the
     // MFMAs of step kk.
     const int fr = lane & 31, fc = lane >> 5;
-    const uint32_t fa0 = (uint32_t)(wm * 128 + fr) * ROWB, fb0 = (uint32_t)(wn * 128 + fr) * ROWB;
-    bf16x8 fa[2][4], fb[2][4];
+    const uint32_t fa0 = (uint32_t)(wm * 128 + fr) * ROWB, fb0 = (uint32_t)(wn * WNE + fr) * ROWB;
+    bf16x8 fa[2][4], fb[2][JN];
     auto rd = [&](const unsigned char *a, const unsigned char *b, int kk, int set) __attribute__((always_inline)) {
         const uint32_t cpos = ((uint32_t)(2 * kk + fc) ^ lds_swz(fr)) << 4;
 #pragma unroll
         for (int i = 0; i < 4; i++) fa[set][i] = *reinterpret_cast<const bf16x8 *>(a + fa0 + cpos + i * 32 * ROWB);
 #pragma unroll
-        for (int j = 0; j < 4; j++) fb[set][j] = *reinterpret_cast<const bf16x8 *>(b + fb0 + cpos + j * 32 * ROWB);
+        for (int j = 0; j < JN; j++) fb[set][j] = *reinterpret_cast<const bf16x8 *>(b + fb0 + cpos + j * 32 * ROWB);
     };
-    auto mrow = [&](int set, int i) __attribute__((always_inline)) {   // 4 MFMAs: accumulator row i
+    auto mrow = [&](int set, int i) __attribute__((always_inline)) {   // JN MFMAs: accumulator row i
 #pragma unroll
-        for (int j = 0; j < 4; j++)
+        for (int j = 0; j < JN; j++)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[set][i], fb[set][j], acc[i][j], 0, 0, 0);
     };
 
@@ -348,8 +358,8 @@ __global__ __launch_bounds__(THREADS, 1) void k_gemm_big(BigArgs ba) {
     // this lane's first row of its wave's 128 rows; rows step by whole 4-row groups below
     const uint32_t lrow = (uint32_t)(wm * 128 + 4 * fc);
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-        const int n = n0 + wn * 128 + j * 32 + fr;
+    for (int j = 0; j < JN; j++) {
+        const int n = n0 + wn * WNE + j * 32 + fr;
         const float bias = (g.bias && !split && n < g.N) ? g.bias[n] : 0.0f;
         const uint32_t cb = n < g.N ? lrow * ldc4 + (uint32_t)n * 4u : ALIF_OOB;
 #pragma unroll
@@ -376,9 +386,14 @@ __global__ void k_big_split_reduce(long long MN, int splits, const float *P, flo
     C[i] = s;
 }
 
+// 512 threads (two waves per SIMD) unless the operand pair needs more registers than
+// two waves per SIMD can hold: float x float (the input gradient against float W
+// among them) and a row-contiguous bfloat16 B in the weight gradient run with 256
 template <int ADT, bool ARM, int BDT, bool BRM>
 hipError_t go(const BigArgs &ba, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemm_big<ADT, ARM, BDT, BRM>), dim3((unsigned)ba.total), dim3(THREADS), LDS_BYTES, st, ba);
+    constexpr bool wide = !(ADT == 0 && BDT == 0) && !(ARM && BDT == 2);
+    constexpr int NT = wide ? 512 : 256;
+    hipLaunchKernelGGL((k_gemm_big<ADT, ARM, BDT, BRM, NT>), dim3((unsigned)ba.total), dim3(NT), LDS_BYTES, st, ba);
     return hipGetLastError();
 }
 
