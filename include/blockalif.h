@@ -334,11 +334,15 @@ int alif_backward_noalloc(const alif_desc *desc, const alif_params *prm,
  * sum_j W_rec[i][j] S_j[t - D] and transmission delay D (Section 2 takes
  * D = T_R, which Prop. 3 turns into block n + 1 receiving W_rec times the
  * spikes of block n; any D >= T_R keeps the source in a finished block).
- * The blocks run one after another: per block, an event-driven kernel adds the
- * recurrent current (the columns of W_rec of the neurons that spiked in the
- * previous block, summed in FP32 in increasing neuron order) to `current`,
- * then the block kernel runs that block from the previous block's FP64 carry.
- * No initial or final state: the run starts from rest with no earlier spike.
+ * The blocks run one after another. Each block's recurrent current is the sum of
+ * the columns of W_rec of the neurons that spiked D steps earlier, in FP32 and in
+ * increasing neuron order, added to `current`; the block then runs from the
+ * previous block's FP64 carry. Layers of up to 256 neurons whose workgroup state
+ * fits the LDS run the whole block loop in one launch (a workgroup per batch
+ * element, spikes passed between blocks in LDS); others take two launches per
+ * block (the recurrent current, then the block kernel). Both give the same
+ * values. No initial or final state: the run starts from rest with no earlier
+ * spike.
  *   desc, prm   as alif_forward; desc->algo must be ALIF_ALGO_BLOCKS;
  *               desc->gemm_precision applies to the feedforward GEMM
  *   input, W    as alif_forward (current input: float [B][T][N]; spike input:
@@ -353,11 +357,20 @@ int alif_backward_noalloc(const alif_desc *desc, const alif_params *prm,
  *               the recurrent current is a constant of the spike path, so the
  *               ordinary backward applies.
  *   spikes, v, theta, carries   as alif_forward
- *   workspace   device scratch of alif_recurrent_workspace_bytes() bytes
+ *   workspace   device scratch of alif_recurrent_workspace_bytes() bytes,
+ *               256-byte aligned (as hipMalloc returns)
  * alif_recurrent_weight_grad: grad_W_rec[i][j] = sum over b, t >= D of
  * grad_current[b][t][i] S[b][t - D][j] (device float [N][N]), from the spikes
  * alif_forward_recurrent wrote (desc->spike_dtype), the same delay and the same
- * workspace size.
+ * workspace size (ALIF_EINVAL if it is not 256-byte aligned). The spikes are
+ * counted on the device first. With at most one nonzero per 256 entries of the
+ * source steps (B (T - D) N of them) the sum runs over the nonzero spikes only:
+ * each adds its
+ * value times a row of grad_current, in FP32, in increasing (b, t) order per
+ * segment of the run and the segments' sums in order (no GEMM; gemm_precision
+ * does not apply). Otherwise it is the GEMM of desc->gemm_precision over the
+ * shifted spikes. Either way the result is deterministic. Asynchronous on
+ * `stream`; the choice is made on the device.
  */
 int alif_recurrent_workspace_bytes(const alif_desc *desc, size_t *bytes);
 int alif_forward_recurrent(const alif_desc *desc, const alif_params *prm,

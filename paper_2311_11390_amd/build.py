@@ -15,8 +15,10 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libblockalif.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["alif_api.hip", "alif_blocks.hip", "alif_blocks_s1.hip", "alif_blocks_s2.hip",
-           "alif_blocks_s4.hip", "alif_blocks_s8.hip", "alif_blocks_s8_long.hip", "alif_blocks_s8_xl.hip", "alif_recurrent_g2.hip", "alif_recurrent_g4.hip",
-           "alif_seq.hip", "alif_gemm.hip", "alif_gemm_big.hip", "alif_readout.hip", "alif_server.hip", "alif_fit.hip", "alif_events.hip"]
+           "alif_blocks_s4.hip", "alif_blocks_s8.hip", "alif_blocks_s8_long.hip", "alif_blocks_s8_xl.hip",
+           "alif_recurrent_g2.hip", "alif_recurrent_g4.hip", "alif_recurrent_wgrad.hip",
+           "alif_seq.hip", "alif_gemm.hip", "alif_gemm_big.hip", "alif_readout.hip", "alif_server.hip", "alif_fit.hip",
+           "alif_events.hip"]
 ARCH = os.environ.get("ALIF_OFFLOAD_ARCH", "gfx950")
 
 # -ffp-contract=off: every FMA in the kernels is written explicitly, so the forward

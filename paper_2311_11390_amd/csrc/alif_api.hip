@@ -557,8 +557,13 @@ RecLayout rec_layout(const alif_desc *d, const Prob &p) {
     L.state = align256((size_t)p.B * p.N * 8) * 4 + align256((size_t)p.B * p.N * 4) * 2;
     L.wt = align256((size_t)p.N * p.N * 4);
     const size_t fwd = L.spikes + L.state + L.wt;
-    // weight gradient: the spikes shifted by T_R steps, then the GEMM's partial sums
-    const size_t wg = align256((size_t)p.B * p.T * p.N * sb) + gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.N);
+    // weight gradient: the event path's count, masks and partials; the dense path's
+    // shifted spikes and GEMM partial sums from byte 256 on (over the masks: the
+    // two never both run)
+    const size_t ev = recurrent_wgrad_event_bytes(p.B, p.T, p.N);
+    const size_t dense = 256 + align256((size_t)p.B * p.T * p.N * sb) +
+                         gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.N);
+    const size_t wg = ev > dense ? ev : dense;
     L.total = fwd > wg ? fwd : wg;
     return L;
 }
@@ -689,17 +694,23 @@ int alif_recurrent_weight_grad(const alif_desc *desc, int32_t delay, const float
     if (D < p.TR) return fail(ALIF_EINVAL, "recurrent delay %d < T_R = %d", D, p.TR);
     if (!grad_current || !spikes || !grad_W_rec || !workspace)
         return fail(ALIF_EINVAL, "grad_current, spikes, grad_W_rec and workspace are required");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(ALIF_EINVAL, "workspace not 256-byte aligned");
     hipStream_t st = (hipStream_t)stream;
     const int sb = spike_elem_bytes(desc->spike_dtype);
+    // the event path, then the dense path gated on the event count it leaves
+    unsigned long long *count = nullptr, thr = 0;
+    hipError_t e = launch_recurrent_wgrad_events(p.B, p.T, p.N, D, sb, spikes, grad_current, grad_W_rec, workspace,
+                                                 &count, &thr, st);
+    if (e != hipSuccess) return hip_fail(e, "recurrent weight-gradient event launch");
     const size_t shb = align256((size_t)p.B * p.T * p.N * sb);
-    char *shifted = (char *)workspace;
-    hipError_t e = launch_shift_time(p.B, p.T, p.N, D, sb, spikes, shifted, st);
+    char *shifted = (char *)workspace + 256;
+    e = launch_shift_time(p.B, p.T, p.N, D, sb, spikes, shifted, st, count, thr);
     if (e != hipSuccess) return hip_fail(e, "spike shift launch");
     GemmIn x;
     x.kind = spike_gemm_kind(desc->spike_dtype);
     x.ptr = shifted;
     e = gemm_weight_grad((size_t)p.B * p.T, p.N, p.N, grad_current, x, grad_W_rec,
-                         desc->gemm_precision == ALIF_GEMM_BF16, shifted + shb, st);
+                         desc->gemm_precision == ALIF_GEMM_BF16, shifted + shb, st, count, thr);
     if (e != hipSuccess) return hip_fail(e, "recurrent weight-gradient GEMM");
     return ALIF_OK;
 }

@@ -256,7 +256,9 @@ __global__ void k_blocks_to_bt(size_t chunks, int cpr, int T, int TR, const char
 }
 
 template <typename C>
-__global__ void k_shift_time(size_t chunks, int cpr, int T, int D, const C *in, C *out) {
+__global__ void k_shift_time(size_t chunks, int cpr, int T, int D, const C *in, C *out,
+                             const unsigned long long *skip_cnt, unsigned long long skip_le) {
+    if (skip_cnt && *skip_cnt <= skip_le) return;
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < chunks; c += (size_t)gridDim.x * blockDim.x) {
         const size_t row = c / cpr;
         const int t = (int)(row % T);
@@ -295,21 +297,25 @@ hipError_t launch_blocks_to_bt(int B, int T, int N, int TR, int elem, const void
     return hipGetLastError();
 }
 
-hipError_t launch_shift_time(int B, int T, int N, int D, int elem, const void *in, void *out, hipStream_t st) {
+hipError_t launch_shift_time(int B, int T, int N, int D, int elem, const void *in, void *out, hipStream_t st,
+                             const unsigned long long *skip_cnt, unsigned long long skip_le) {
     const size_t rb = (size_t)N * elem, rows = (size_t)B * T;
     if (rows == 0 || rb == 0) return hipSuccess;
     const int cb = chunk_bytes(rb, in, out, 0);
     const int cpr = (int)(rb / cb);
     const size_t chunks = rows * cpr;
+    // a grid-stride loop over at most 2048 workgroups: enough for the copy, and a
+    // gated-off launch retires in a few microseconds
+    const unsigned grid = grid_for(chunks) < 2048u ? grid_for(chunks) : 2048u;
     if (cb == 16)
-        hipLaunchKernelGGL(k_shift_time<uint4>, dim3(grid_for(chunks)), dim3(256), 0, st, chunks, cpr, T, D,
-                           static_cast<const uint4 *>(in), static_cast<uint4 *>(out));
+        hipLaunchKernelGGL(k_shift_time<uint4>, dim3(grid), dim3(256), 0, st, chunks, cpr, T, D,
+                           static_cast<const uint4 *>(in), static_cast<uint4 *>(out), skip_cnt, skip_le);
     else if (cb == 4)
-        hipLaunchKernelGGL(k_shift_time<uint32_t>, dim3(grid_for(chunks)), dim3(256), 0, st, chunks, cpr, T, D,
-                           static_cast<const uint32_t *>(in), static_cast<uint32_t *>(out));
+        hipLaunchKernelGGL(k_shift_time<uint32_t>, dim3(grid), dim3(256), 0, st, chunks, cpr, T, D,
+                           static_cast<const uint32_t *>(in), static_cast<uint32_t *>(out), skip_cnt, skip_le);
     else
-        hipLaunchKernelGGL(k_shift_time<uint8_t>, dim3(grid_for(chunks)), dim3(256), 0, st, chunks, cpr, T, D,
-                           static_cast<const uint8_t *>(in), static_cast<uint8_t *>(out));
+        hipLaunchKernelGGL(k_shift_time<uint8_t>, dim3(grid), dim3(256), 0, st, chunks, cpr, T, D,
+                           static_cast<const uint8_t *>(in), static_cast<uint8_t *>(out), skip_cnt, skip_le);
     return hipGetLastError();
 }
 

@@ -21,9 +21,11 @@ hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, 
                               size_t scratch_bytes = 0);
 // bytes of the bfloat16 copy of a [N][K] weight matrix
 size_t gemm_wbf16_bytes(int N, int K);
-// gW[N][K] = sum_m gI[m][n] x[m][k]   (split over m, reduced in a fixed order)
+// gW[N][K] = sum_m gI[m][n] x[m][k]   (split over m, reduced in a fixed order);
+// skip_cnt / skip_le: the device-side gate of GemmArgs
 hipError_t gemm_weight_grad(size_t M, int N, int K, const float *gI, GemmIn x, float *gW, bool bf16,
-                            void *ws, hipStream_t st);
+                            void *ws, hipStream_t st, const unsigned long long *skip_cnt = nullptr,
+                            unsigned long long skip_le = 0);
 // gx[M][K] = gI[M][N] . W[N][K]. With bf16, a scratch of gemm_wbf16_bytes(N, K)
 // bytes (as above) receives W transposed and rounded to bfloat16 once.
 hipError_t gemm_input_grad(size_t M, int N, int K, const float *gI, const float *W, float *gx,
@@ -48,7 +50,15 @@ struct GemmArgs {
     const float *bias;
     int splits;        // split of K over blockIdx.z; > 1 writes partials to C_part
     float *C_part;     // [splits][M][N]
+    // Device-side gate: with skip_cnt set, every kernel of the launch returns at
+    // entry when *skip_cnt <= skip_le as it starts, and C is left alone (a caller
+    // that picks between this GEMM and another way of computing C on the device).
+    const unsigned long long *skip_cnt;
+    unsigned long long skip_le;
 };
+__device__ __forceinline__ bool gemm_gated_off(const unsigned long long *cnt, unsigned long long le) {
+    return cnt != nullptr && *cnt <= le;
+}
 hipError_t gemm_launch(const GemmArgs &g, bool bf16, hipStream_t st);
 
 }  // namespace alif

@@ -33,6 +33,7 @@ __device__ __forceinline__ float ld_elem(const void *p, int dt, long long i) {
 
 template <bool BF16>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+    if (gemm_gated_off(g.skip_cnt, g.skip_le)) return;
     constexpr int BK = BF16 ? 32 : 16;
     constexpr int APAD = BF16 ? 8 : 16;
     // BF16: [row][k] (k contiguous, 8-element MFMA fragments); FP32: [k][row]
@@ -357,6 +358,7 @@ struct Stage {
 template <int ADT, bool AKM, int BDT, bool BKM, bool BF16>
 __global__ __launch_bounds__(Tile<BF16>::THREADS) void k_gemm_tiled(GemmArgs g, int m_tiles, int n_tiles,
                                                                      int kps, int total) {
+    if (gemm_gated_off(g.skip_cnt, g.skip_le)) return;
     using P = Tile<BF16>;
     using T = typename P::T;
     constexpr int BM = P::BM, BN = P::BN, BK = P::BK, LDK = P::LDK;
@@ -570,7 +572,8 @@ static hipError_t tiled_launch(const GemmArgs &g, hipStream_t st, int *splits_ou
 
 // fixed-order sum of split partials: C[m][n] = sum_z P[z][m][n] (+ bias)
 __global__ void k_split_reduce(long long MN, int N, int splits, const float *P, float *C,
-                               const float *bias) {
+                               const float *bias, const unsigned long long *skip_cnt, unsigned long long skip_le) {
+    if (gemm_gated_off(skip_cnt, skip_le)) return;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= MN) return;
     float s = 0.0f;
@@ -588,7 +591,7 @@ hipError_t gemm_launch(const GemmArgs &g, bool bf16, hipStream_t st) {
         if (e != hipSuccess || splits == 1) return e;
         const long long MN = g.M * (long long)g.N;
         hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st, MN, g.N,
-                           splits, g.C_part, g.C, g.bias);
+                           splits, g.C_part, g.C, g.bias, g.skip_cnt, g.skip_le);
         return hipGetLastError();
     }
     dim3 grid((g.N + GBN - 1) / GBN, (unsigned)((g.M + GBM - 1) / GBM), g.splits);
@@ -599,7 +602,7 @@ hipError_t gemm_launch(const GemmArgs &g, bool bf16, hipStream_t st) {
     if (e != hipSuccess || g.splits == 1) return e;
     const long long MN = g.M * (long long)g.N;
     hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st, MN, g.N,
-                       g.splits, g.C_part, g.C, g.bias);
+                       g.splits, g.C_part, g.C, g.bias, g.skip_cnt, g.skip_le);
     return hipGetLastError();
 }
 
@@ -670,7 +673,8 @@ size_t gemm_workspace_bytes(size_t M, int N, int K) {
 }
 
 hipError_t gemm_weight_grad(size_t M, int N, int K, const float *gI, GemmIn x, float *gW, bool bf16,
-                            void *ws, hipStream_t st) {
+                            void *ws, hipStream_t st, const unsigned long long *skip_cnt,
+                            unsigned long long skip_le) {
     // C[n][k] = sum_m gI[m][n] x[m][k]: reduction over m (split), both operands m-major
     GemmArgs g{};
     g.M = N; g.N = K; g.K = (int)M;
@@ -679,6 +683,8 @@ hipError_t gemm_weight_grad(size_t M, int N, int K, const float *gI, GemmIn x, f
     g.C = gW; g.ldc = K; g.bias = nullptr;
     g.splits = wgrad_splits(M, N, K);
     g.C_part = (float *)ws;
+    g.skip_cnt = skip_cnt;
+    g.skip_le = skip_le;
     if (M > 0x7fffffff) return hipErrorInvalidValue;
     return gemm_launch(g, bf16, st);
 }

@@ -216,6 +216,7 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_big(BigArgs ba) {
     constexpr int WNE = TN / WN;          // columns per wave
     constexpr int JN = WNE / 32;          // 32-column accumulators per wave
     const GemmArgs &g = ba.g;
+    if (gemm_gated_off(g.skip_cnt, g.skip_le)) return;
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned char *const A0 = lds, *const A1 = lds + BUF_A;
     unsigned char *const B0 = lds + 2 * BUF_A, *const B1 = lds + 2 * BUF_A + BUF_B;
@@ -377,7 +378,9 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_big(BigArgs ba) {
 }
 
 // fixed-order sum of split partials: C[m][n] = sum_z P[z][m][n]
-__global__ void k_big_split_reduce(long long MN, int splits, const float *P, float *C, const float *bias, int N) {
+__global__ void k_big_split_reduce(long long MN, int splits, const float *P, float *C, const float *bias, int N,
+                                   const unsigned long long *skip_cnt, unsigned long long skip_le) {
+    if (gemm_gated_off(skip_cnt, skip_le)) return;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= MN) return;
     float s = 0.0f;
@@ -464,7 +467,7 @@ hipError_t gemm_big_launch(const GemmArgs &g, hipStream_t st) {
     if (e != hipSuccess || splits == 1) return e;
     const long long MN = g.M * (long long)g.N;
     hipLaunchKernelGGL(k_big_split_reduce, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st, MN, splits,
-                       g.C_part, g.C, g.bias, g.N);
+                       g.C_part, g.C, g.bias, g.N, g.skip_cnt, g.skip_le);
     return hipGetLastError();
 }
 

@@ -1,0 +1,403 @@
+// Recurrent weight gradient from the spike events: the backward of the recurrent
+// current W_rec S[t - D] of Eq. 3 under the detached policy,
+//   dW_rec[i][j] = sum over b and u < T - D of S[b][u][j] gI[b][u + D][i].
+// A neuron fires at most once per T_R steps (Prop. 3), and at the rates of a fitted
+// network almost every spike row is zero: a dense GEMM spends N^2 multiply-adds on
+// each of the R = B (T - D) source rows for a handful of events. Three kernels:
+//   mask    reads S once: for chunk q = b NC + k (64 steps of one sequence, NC
+//           chunks a sequence) and column j, the bit mask of its nonzero steps
+//           (u64, bit r for step 64 k + r), stored only when nonzero, and one
+//           summary bit a chunk (u16 words over 16 chunks) saying which; the set
+//           bits are counted into E.
+//   reduce  one wave per (column j, segment of consecutive chunks, 256 rows i)
+//           walks the segment's events in step order, each adding its spike value
+//           times gI row u + D into FP32 accumulators: a partial per segment.
+//   sum     dW_rec[i][j] = the segments' partials added in segment order.
+// Every sum runs in a fixed order, so the result does not depend on scheduling.
+// The event path reads E N gI values (one row per event) where the dense product
+// does 2 R N^2 flops over R N of them; above one event per 256 spike entries of
+// the source steps (E > R N / 256) the dense GEMM is the faster one, so reduce and
+// sum return at entry and the dense time shift + GEMM, enqueued behind them with
+// the same device-side test on E, run instead.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "alif_common.h"
+#include "alif_kernels.h"
+
+namespace alif {
+namespace {
+
+constexpr int CH = 64;            // steps per chunk: one u64 mask
+constexpr int QC = 16;            // chunks per quarter: one u16 summary word a column
+constexpr int GQ = 64;            // chunks per group (four quarters)
+constexpr int MASK_WAVES = 2;     // waves of a mask workgroup (one quarter), CPW chunks each
+constexpr int CPW = QC / MASK_WAVES;
+constexpr int WIN = 16;           // groups of a segment at most: 64 quarters, one a lane
+constexpr int CLIST = WIN * GQ;   // chunks of a segment (u16 list entries)
+constexpr int ELIST = GQ * CH;    // the events of 64 listed chunks at most (u16 entries)
+constexpr int BATCH = 8;          // events whose gI rows are loaded together
+
+struct WgArgs {
+    int B, T, TD, N, D;
+    int NC;        // chunks a sequence, ceil(TD / CH)
+    int Q;         // chunks, B NC
+    int Q16;       // quarters, ceil(Q / QC)
+    int QG;        // groups, ceil(Q / GQ)
+    long long QP;  // mask row length in chunks, QG GQ
+    int SG, S;     // groups a segment, segments
+    const void *spikes;
+    const float *gI;
+    unsigned long long *E;   // event count
+    unsigned long long thr;  // this path runs when E <= thr
+    uint16_t *sum16;         // [Q16][N]: bit c set when chunk 16 k + c of column j has an event
+    uint64_t *mask;          // [N][QP]: written (and read) only where the summary bit is set
+    float *part;             // [S][N (j)][N (i)]
+    float *dW;               // [N (i)][N (j)]
+};
+
+__global__ void k_wg_zero(unsigned long long *E) { *E = 0; }
+
+// Bit r of half[c] = (element c of v[r] != 0), for 32 rows. VEC: v holds a dword of
+// a row (4 bytes, 2 bfloat16 or 1 float); else one element in the low bits. The sign
+// bit of a floating-point element is ignored (-0 is no event). For bytes, bit 7 of
+// ((x | 0x80) - 1) | x is set exactly when x != 0, with no borrow across bytes, and
+// the rows of 8 go into the 8 bits of each byte; bfloat16 the same way with
+// (x & 0x7fff) + 0x7fff in 16-bit halves.
+template <int ELEM, bool VEC>
+__device__ __forceinline__ void row_bits(const uint32_t (&v)[32], uint32_t (&half)[VEC ? 4 / ELEM : 1]) {
+    if constexpr (VEC && ELEM == 1) {
+        uint32_t acc[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int r = 0; r < 32; r++) {
+            const uint32_t nz = (((v[r] | 0x80808080u) - 0x01010101u) | v[r]) & 0x80808080u;
+            acc[r >> 3] |= nz >> (7 - (r & 7));
+        }
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            half[c] = ((acc[0] >> (8 * c)) & 0xffu) | (((acc[1] >> (8 * c)) & 0xffu) << 8) |
+                      (((acc[2] >> (8 * c)) & 0xffu) << 16) | (((acc[3] >> (8 * c)) & 0xffu) << 24);
+    } else if constexpr (VEC && ELEM == 2) {
+        uint32_t acc[2] = {0u, 0u};
+#pragma unroll
+        for (int r = 0; r < 32; r++) {
+            const uint32_t nz = ((v[r] & 0x7fff7fffu) + 0x7fff7fffu) & 0x80008000u;
+            acc[r >> 4] |= nz >> (15 - (r & 15));
+        }
+        half[0] = (acc[0] & 0xffffu) | (acc[1] << 16);
+        half[1] = (acc[0] >> 16) | (acc[1] & 0xffff0000u);
+    } else {
+        constexpr uint32_t mag = ELEM == 4 ? 0x7fffffffu : (ELEM == 2 ? 0x7fffu : 0xffu);
+        uint32_t h = 0u;
+#pragma unroll
+        for (int r = 0; r < 32; r++) h |= (uint32_t)((v[r] & mag) != 0u) << r;
+        half[0] = h;
+    }
+}
+
+template <int ELEM, bool VEC>
+__device__ __forceinline__ uint32_t ld_elems(rsrc_t r, uint32_t off) {
+    if constexpr (VEC || ELEM == 4) return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+    else if constexpr (ELEM == 2) return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+    else return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
+
+// Workgroup (quarter k = blockIdx.x, 64 lanes of columns): wave w takes chunks
+// 16 k + CPW w + c, c < CPW; each lane holds CPL columns (one dword of a row when
+// VEC, else one element) and walks a chunk's 64 rows, two halves of 32 loads in
+// flight. Only the nonzero masks are stored (at this path's firing rates almost
+// none: the kernel is bound by the spike reads); the summary words, written for
+// every quarter and column, say which.
+template <int ELEM, bool VEC>
+__global__ __launch_bounds__(64 * MASK_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void k_wg_mask(WgArgs a) {
+    constexpr int CPL = VEC ? 4 / ELEM : 1;
+    __shared__ uint32_t other[64 * CPL];   // the second wave's summary bits
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j0 = (blockIdx.y * 64 + lane) * CPL;
+    const uint32_t rowb = (uint32_t)a.N * ELEM;
+    const bool col_ok = j0 < a.N;
+    unsigned long long cnt = 0;
+    uint32_t sb[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; c++) sb[c] = 0u;
+    for (int w = 0; w < CPW; w++) {
+        const int cq = wave * CPW + w;   // chunk of the quarter
+        const int q = blockIdx.x * QC + cq;
+        if (q >= a.Q) break;   // uniform: past the last sequence
+        const int b = q / a.NC, k = q - b * a.NC;
+        const int u0 = k * CH;
+        const int rows = min(CH, a.TD - u0);
+        const char *base = static_cast<const char *>(a.spikes) + ((size_t)b * a.T + u0) * rowb;
+        const rsrc_t rs = make_rsrc(base, (uint32_t)rows * rowb);
+        uint64_t m[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; c++) m[c] = 0;
+#pragma unroll 1
+        for (int h = 0; h < 2; h++) {
+            uint32_t v[32];
+#pragma unroll
+            for (int r = 0; r < 32; r++)
+                v[r] = ld_elems<ELEM, VEC>(rs, col_ok ? (uint32_t)(h * 32 + r) * rowb + (uint32_t)j0 * ELEM : ALIF_OOB);
+            uint32_t half[CPL];
+            row_bits<ELEM, VEC>(v, half);
+#pragma unroll
+            for (int c = 0; c < CPL; c++) m[c] |= (uint64_t)half[c] << (32 * h);
+        }
+#pragma unroll
+        for (int c = 0; c < CPL; c++) {
+            cnt += (unsigned long long)__popcll(m[c]);
+            if (m[c] != 0ull) {   // (a column past N reads zeros)
+                a.mask[(size_t)(j0 + c) * a.QP + q] = m[c];
+                sb[c] |= 1u << cq;
+            }
+        }
+    }
+    if (wave == 1)
+#pragma unroll
+        for (int c = 0; c < CPL; c++) other[lane * CPL + c] = sb[c];
+    __syncthreads();
+    if (wave == 0)
+#pragma unroll
+        for (int c = 0; c < CPL; c++)
+            if (j0 + c < a.N)
+                a.sum16[(size_t)blockIdx.x * a.N + j0 + c] = (uint16_t)(sb[c] | other[lane * CPL + c]);
+    // event count: wave sum, one atomic a wave (integer: the total is exact)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane == 0 && cnt) atomicAdd(a.E, cnt);
+}
+static_assert(MASK_WAVES == 2 && QC <= 32, "two waves fill one u16 summary word a column");
+
+__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+template <int ELEM>
+__device__ __forceinline__ float spike_value(const void *S, size_t idx) {
+    if constexpr (ELEM == 1) return (float)static_cast<const uint8_t *>(S)[idx];
+    else if constexpr (ELEM == 2)
+        return __uint_as_float((uint32_t) static_cast<const uint16_t *>(S)[idx] << 16);
+    else return static_cast<const float *>(S)[idx];
+}
+
+// One wave: column j = blockIdx.x, segment s = blockIdx.y (at most WIN groups = 64
+// quarters), rows i = 256 blockIdx.z + lane + 64 p (p < 4). The segment's summary
+// words (lane = quarter) give the chunks with events, listed in order in LDS; their
+// masks are loaded 64 at a time (lane = listed chunk) and their set bits listed in
+// (chunk, step) order, which is step order; the event list is consumed BATCH events
+// at a time (first when 64 more chunks could overflow it, then at the end).
+template <int ELEM>
+__global__ __launch_bounds__(64) void k_wg_reduce(WgArgs a) {
+    if (*a.E > a.thr) return;   // the dense path runs
+    __shared__ uint16_t clist[CLIST];   // chunk offsets from the segment's first chunk
+    __shared__ uint16_t elist[ELIST];   // (chunk offset << 6) | step
+    const int lane = threadIdx.x;
+    const int j = blockIdx.x, s = blockIdx.y, i0 = blockIdx.z * 256;
+    uint32_t ioff[4];
+#pragma unroll
+    for (int p = 0; p < 4; p++) {
+        const int i = i0 + lane + 64 * p;
+        ioff[p] = i < a.N ? (uint32_t)i * 4u : ALIF_OOB;
+    }
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const int g0 = s * a.SG;
+    const int k0 = g0 * (GQ / QC), nq = min(a.SG * (GQ / QC), a.Q16 - k0);   // quarters (<= 64)
+    const int qbase = g0 * GQ;                                                // first chunk
+    const uint64_t *mrow = a.mask + (size_t)j * a.QP + qbase;
+
+    const uint32_t sm = lane < nq ? (uint32_t)a.sum16[(size_t)(k0 + lane) * a.N + j] : 0u;
+    if (__ballot(sm != 0u) != 0ull) {   // uniform
+        const int c = __popc(sm);
+        const int pre = wave_incl_scan(c, lane);
+        const int tot = __shfl(pre, 63);
+        {
+            int e = pre - c;
+            uint32_t mm = sm;
+            while (mm) {
+                const int bit = __builtin_ctz(mm);
+                mm &= mm - 1;
+                clist[e++] = (uint16_t)(lane * QC + bit);
+            }
+        }
+        __syncthreads();
+
+        auto consume = [&](int count) {
+            __syncthreads();   // the list entries are written
+            for (int e0 = 0; e0 < count; e0 += BATCH) {
+                float g[BATCH][4], v[BATCH];
+#pragma unroll
+                for (int u = 0; u < BATCH; u++) {
+                    const bool ok = e0 + u < count;   // uniform
+                    const uint32_t ent = (uint32_t)__builtin_amdgcn_readfirstlane((int)elist[ok ? e0 + u : e0]);
+                    const int q = qbase + (int)(ent >> 6);
+                    const int b = q / a.NC, k = q - b * a.NC;
+                    const size_t srow = (size_t)b * a.T + (size_t)k * CH + (ent & 63u);
+                    const float sv = spike_value<ELEM>(a.spikes, srow * a.N + j);   // a valid entry's address
+                    v[u] = ok ? sv : 0.0f;
+                    const rsrc_t rr = make_rsrc(a.gI + (srow + a.D) * a.N, ok ? (uint32_t)a.N * 4u : 0u);
+#pragma unroll
+                    for (int p = 0; p < 4; p++) g[u][p] = ld_f32(rr, ioff[p]);
+                }
+#pragma unroll
+                for (int u = 0; u < BATCH; u++)
+                    if (e0 + u < count)
+#pragma unroll
+                        for (int p = 0; p < 4; p++) acc[p] = fmaf(v[u], g[u][p], acc[p]);
+            }
+            __syncthreads();   // the list is rewritten next
+        };
+
+        int count = 0;
+        for (int c0 = 0; c0 < tot; c0 += 64) {
+            const bool has = c0 + lane < tot;
+            const int off = has ? (int)clist[c0 + lane] : 0;
+            const uint64_t m = has ? mrow[off] : 0ull;
+            const int pc = __popcll(m);
+            const int pp = wave_incl_scan(pc, lane);
+            const int pt = __shfl(pp, 63);
+            if (count + pt > ELIST) {
+                consume(count);
+                count = 0;
+            }
+            int e = count + pp - pc;
+            uint64_t mm = m;
+            while (mm) {
+                const int bit = __builtin_ctzll(mm);
+                mm &= mm - 1;
+                elist[e++] = (uint16_t)((off << 6) | bit);
+            }
+            count += pt;
+        }
+        consume(count);
+    }
+    float *out = a.part + ((size_t)s * a.N + j) * a.N;
+#pragma unroll
+    for (int p = 0; p < 4; p++) {
+        const int i = i0 + lane + 64 * p;
+        if (i < a.N) out[i] = acc[p];
+    }
+}
+
+// dW[i][j] = sum over segments in order of part[s][j][i], through a 16 x 16 LDS tile
+// (a thread per element, eight segments' loads in flight)
+__global__ __launch_bounds__(256) void k_wg_sum(WgArgs a) {
+    if (*a.E > a.thr) return;
+    __shared__ float t[16][17];
+    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int j = j0 + ty, i = i0 + tx;
+    float sum = 0.0f;
+    if (j < a.N && i < a.N) {
+        const size_t NN = (size_t)a.N * a.N;
+        const float *p = a.part + (size_t)j * a.N + i;
+        int s = 0;
+        for (; s + 8 <= a.S; s += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[u] = p[(size_t)(s + u) * NN];
+#pragma unroll
+            for (int u = 0; u < 8; u++) sum += v[u];
+        }
+        for (; s < a.S; s++) sum += p[(size_t)s * NN];
+    }
+    t[ty][tx] = sum;
+    __syncthreads();
+    const int io = i0 + ty, jo = j0 + tx;
+    if (io < a.N && jo < a.N) a.dW[(size_t)io * a.N + jo] = t[tx][ty];
+}
+
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// the shape of the event path; ok = false when it cannot run (index ranges)
+struct Plan {
+    bool ok;
+    int NC, Q, Q16, QG, SG, S;
+    long long QP;
+    size_t sum_bytes, mask_bytes, part_bytes;
+};
+
+Plan plan(int B, int T, int N, int D) {
+    Plan p{};
+    const long long TD = T > D ? T - D : 0;
+    const long long NC = (TD + CH - 1) / CH;
+    const long long Q = (long long)B * NC;
+    const long long QG = (Q + GQ - 1) / GQ;
+    const long long NIS = (N + 255) / 256;
+    // segments: about 8192 reduce waves, at most WIN groups each, gridDim.y <= 65535
+    long long S = (8192 + (long long)N * NIS - 1) / ((long long)N * NIS);
+    if (S > QG) S = QG;
+    if (S < (QG + WIN - 1) / WIN) S = (QG + WIN - 1) / WIN;
+    p.ok = N > 0 && Q < (1LL << 30) && NIS <= 65535 && S <= 65535 && 64LL * N * 4 < (1LL << 31);
+    if (!p.ok) return p;
+    p.NC = (int)NC; p.Q = (int)Q; p.Q16 = (int)((Q + QC - 1) / QC); p.QG = (int)QG;
+    p.QP = QG * GQ;
+    p.SG = S > 0 ? (int)((QG + S - 1) / S) : 1;
+    p.S = S > 0 ? (int)((QG + p.SG - 1) / p.SG) : 0;
+    p.sum_bytes = a256((size_t)p.Q16 * N * 2);
+    p.mask_bytes = a256((size_t)N * (size_t)p.QP * 8);
+    p.part_bytes = a256((size_t)p.S * N * N * 4);
+    return p;
+}
+
+}  // namespace
+
+size_t recurrent_wgrad_event_bytes(int B, int T, int N) {
+    const Plan p = plan(B, T, N, 0);   // D = 0 bounds every D >= 0
+    return p.ok ? 256 + p.sum_bytes + p.mask_bytes + p.part_bytes : 256;
+}
+
+hipError_t launch_recurrent_wgrad_events(int B, int T, int N, int D, int elem, const void *spikes, const float *gI,
+                                         float *dW, void *ws, unsigned long long **count,
+                                         unsigned long long *thr, hipStream_t st) {
+    *count = nullptr;
+    *thr = 0;
+    const Plan p = plan(B, T, N, D);
+    // (naturally aligned elements, and the shape within the index ranges for every D,
+    // as the workspace size assumes; otherwise the dense path runs ungated)
+    if (!p.ok || !plan(B, T, N, 0).ok || (reinterpret_cast<uintptr_t>(spikes) & (uintptr_t)(elem - 1)) != 0)
+        return hipSuccess;
+    WgArgs a{};
+    a.B = B; a.T = T; a.TD = T > D ? T - D : 0; a.N = N; a.D = D;
+    a.NC = p.NC; a.Q = p.Q; a.Q16 = p.Q16; a.QG = p.QG; a.QP = p.QP; a.SG = p.SG; a.S = p.S;
+    a.spikes = spikes;
+    a.gI = gI;
+    char *w = static_cast<char *>(ws);
+    a.E = reinterpret_cast<unsigned long long *>(w);
+    a.thr = (unsigned long long)B * a.TD * (unsigned long long)N / 256;
+    a.sum16 = reinterpret_cast<uint16_t *>(w + 256);
+    a.mask = reinterpret_cast<uint64_t *>(w + 256 + p.sum_bytes);
+    a.part = reinterpret_cast<float *>(w + 256 + p.sum_bytes + p.mask_bytes);
+    a.dW = dW;
+    hipLaunchKernelGGL(k_wg_zero, dim3(1), dim3(1), 0, st, a.E);
+    if (p.Q > 0) {
+        const bool vec = (reinterpret_cast<uintptr_t>(spikes) & 3) == 0 && ((size_t)N * elem) % 4 == 0;
+        const int cpl = vec ? 4 / elem : 1;
+        const dim3 grid((unsigned)p.Q16, (unsigned)((N + 64 * cpl - 1) / (64 * cpl)));
+        const dim3 blk(64 * MASK_WAVES);
+        if (elem == 1) {
+            if (vec) hipLaunchKernelGGL((k_wg_mask<1, true>), grid, blk, 0, st, a);
+            else hipLaunchKernelGGL((k_wg_mask<1, false>), grid, blk, 0, st, a);
+        } else if (elem == 2) {
+            if (vec) hipLaunchKernelGGL((k_wg_mask<2, true>), grid, blk, 0, st, a);
+            else hipLaunchKernelGGL((k_wg_mask<2, false>), grid, blk, 0, st, a);
+        } else {
+            hipLaunchKernelGGL((k_wg_mask<4, true>), grid, blk, 0, st, a);
+        }
+        const dim3 rg((unsigned)N, (unsigned)p.S, (unsigned)((N + 255) / 256));
+        if (elem == 1) hipLaunchKernelGGL(k_wg_reduce<1>, rg, dim3(64), 0, st, a);
+        else if (elem == 2) hipLaunchKernelGGL(k_wg_reduce<2>, rg, dim3(64), 0, st, a);
+        else hipLaunchKernelGGL(k_wg_reduce<4>, rg, dim3(64), 0, st, a);
+    }
+    hipLaunchKernelGGL(k_wg_sum, dim3((unsigned)((N + 15) / 16), (unsigned)((N + 15) / 16)), dim3(256), 0, st, a);
+    *count = a.E;
+    *thr = a.thr;
+    return hipGetLastError();
+}
+
+}  // namespace alif

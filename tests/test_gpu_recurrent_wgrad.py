@@ -1,0 +1,204 @@
+"""GPU parity of alif_recurrent_weight_grad (the gradient of the recurrent term
+W_rec S[t - D] of Eq. 3 under the detached policy) on seeded synthetic spike
+tensors, through the C ABI, against the oracle's FP64 product:
+
+* few nonzero spikes (at most one per 256 entries of the source steps): the
+  event path. Each
+  element is a fixed-order FP32 sum of its column's events, so its error is held
+  to an element-wise rounding bound, (2 n_j + 4) 2^-24 sum |gI| |S| (n_j events in
+  column j), and two calls agree bit for bit;
+* many nonzero spikes: the dense GEMM path, to the GEMM tolerance.
+
+The device-side event count (the first word of the workspace) must equal the
+number of nonzero spikes in the source steps t < T - D, which pins the masks.
+Spike values other than 0/1 (u8 2 and 3, signed floats, -0.0 as no event), u8,
+bfloat16 and float spikes, odd widths (element loads) and widths whose rows are
+whole dwords, two 256-row slices of i, several segments and groups, a group
+whose events overflow the event list, T <= D, and a workspace shared by both
+paths."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import log, np_
+from parity import check_grad
+from paper_2311_11390_amd.synth import rng
+
+pytestmark = pytest.mark.gpu
+
+_DT = {"u8": 0, "bf16": 1, "f32": 2}
+
+
+def _spikes(g, B, T, N, p, kind):
+    """Bernoulli(p) events; u8 values 1-3, bfloat16 / float values from a few
+    exactly representable magnitudes with either sign, plus -0.0 entries
+    (no events) in float."""
+    ev = g.random((B, T, N)) < p
+    if kind == "u8":
+        vals = g.choice(np.array([1, 1, 1, 2, 3], np.float32), size=(B, T, N))
+    else:
+        vals = g.choice(np.array([1.0, 0.5, 2.0, -1.5, -1.0], np.float32), size=(B, T, N))
+    S = np.where(ev, vals, np.float32(0.0)).astype(np.float32)
+    if kind == "f32":
+        S[(g.random((B, T, N)) < p) & ~ev] = np.float32(-0.0)
+    return S
+
+
+def _workspace(desc):
+    import torch
+
+    from paper_2311_11390_amd import _lib as L
+    n = ctypes.c_size_t()
+    L.check(L.load().alif_recurrent_workspace_bytes(ctypes.byref(desc), ctypes.byref(n)))
+    return torch.empty(max(1, n.value), dtype=torch.uint8, device="cuda")
+
+
+def _run(S, gI, D, kind, prec=0, ws=None):
+    import torch
+
+    from paper_2311_11390_amd import alif
+    B, T, N = S.shape
+    desc = alif.make_desc(B, T, N, 1.0, 2.0, gemm_precision=prec, spike_dtype=_DT[kind])
+    tdt = {"u8": torch.uint8, "bf16": torch.bfloat16, "f32": torch.float32}[kind]
+    St = torch.as_tensor(S, device="cuda").to(tdt)
+    if ws is None:
+        ws = _workspace(desc)
+    out = alif.recurrent_weight_grad({"desc": desc, "delay": D, "spikes": St, "workspace": ws},
+                                     torch.as_tensor(gI, device="cuda"))
+    torch.cuda.synchronize()
+    count = int(ws[:8].cpu().numpy().view(np.uint64)[0])
+    return np_(out), count, ws
+
+
+def _shifted(S, D):
+    B, T, N = S.shape
+    Ssh = np.zeros((B, T, N), np.float64)
+    if T > D:
+        Ssh[:, D:] = S[:, :T - D]
+    return Ssh
+
+
+def _reference(gI, S, D):
+    B, T, N = S.shape
+    if T <= D:
+        return np.zeros((N, N))
+    return oracle.recurrent_weight_grad(gI.astype(np.float64), S.astype(np.float64), D)
+
+
+def _events(S, D):
+    T = S.shape[1]
+    return int(np.count_nonzero(S[:, :max(T - D, 0)]))
+
+
+def _check_event_bound(name, got, gI, S, D):
+    N = S.shape[2]
+    ref = _reference(gI, S, D)
+    Ssh = _shifted(S, D).reshape(-1, N)
+    A = np.abs(gI.reshape(-1, N).astype(np.float64)).T @ np.abs(Ssh)
+    n_j = np.count_nonzero(Ssh, axis=0).astype(np.float64)
+    bound = (2.0 * n_j[None, :] + 4.0) * 2.0 ** -24 * A
+    err = np.abs(got.astype(np.float64) - ref)
+    worst = float((err / np.maximum(bound, 1e-300)).max())
+    log(f"    {name}: max |err| {err.max():.2e}, worst err / bound {worst:.3f}")
+    assert (err <= bound).all(), f"{name}: error above the FP32 rounding bound ({worst:.3f} of it)"
+
+
+# (spike kind, B, T, N, D, event probability)
+_SPARSE = [
+    ("u8", 3, 301, 67, 5, 0.003),       # odd width: element loads
+    ("u8", 2, 1501, 256, 40, 0.002),    # dword rows; the fine-DT delay
+    ("u8", 2, 700, 300, 3, 0.002),      # two 256-row slices of i
+    ("bf16", 2, 500, 130, 4, 0.003),
+    ("bf16", 2, 257, 33, 2, 0.003),
+    ("f32", 4, 400, 96, 7, 0.003),
+    ("u8", 1, 12358, 8, 2, 0.003),      # four segments, ragged last chunk
+    ("u8", 2, 66000, 256, 3, 0.001),    # two groups a segment, 17 segments
+]
+
+
+@pytest.mark.parametrize("kind,B,T,N,D,p", _SPARSE)
+def test_event_path_matches_oracle(kind, B, T, N, D, p):
+    g = rng(7000 + N + T)
+    S = _spikes(g, B, T, N, p, kind)
+    gI = g.standard_normal((B, T, N)).astype(np.float32)
+    E = _events(S, D)
+    assert 0 < E <= B * (T - D) * N // 256   # the case is meant for the event path
+    log(f"[wgrad] events {kind} B={B} T={T} N={N} D={D}: {E} events")
+    got, count, ws = _run(S, gI, D, kind)
+    assert count == E
+    _check_event_bound("grad_W_rec", got, gI, S, D)
+    again, _, _ = _run(S, gI, D, kind, ws=ws)
+    assert np.array_equal(got.view(np.uint32), again.view(np.uint32)), "two calls differ"
+    # gemm_precision does not apply to the event path: the same FP32 sums
+    b16, _, _ = _run(S, gI, D, kind, prec=1, ws=ws)
+    assert np.array_equal(got.view(np.uint32), b16.view(np.uint32))
+
+
+def test_event_path_overflowing_list():
+    """A column firing at every step of 4160 consecutive steps: its first group
+    fills the event list (4096 events) and the next group's 64 make it flush
+    before they are listed; 1024 neurons (four slices of i)."""
+    B, T, N, D = 1, 24002, 1024, 2
+    g = rng(7101)
+    S = _spikes(g, B, T, N, 0.00005, "u8")
+    S[0, :4160, 7] = 1.0
+    gI = g.standard_normal((B, T, N)).astype(np.float32)
+    E = _events(S, D)
+    assert E <= B * (T - D) * N // 256
+    log(f"[wgrad] list overflow B={B} T={T} N={N} D={D}: {E} events")
+    got, count, _ = _run(S, gI, D, "u8")
+    assert count == E
+    _check_event_bound("grad_W_rec", got, gI, S, D)
+
+
+# (spike kind, B, T, N, D, event probability, GEMM precision)
+_DENSE = [("u8", 2, 200, 67, 3, 0.4, 0), ("f32", 2, 150, 64, 2, 0.3, 0), ("bf16", 3, 90, 130, 5, 0.5, 0),
+          ("u8", 2, 300, 256, 40, 0.3, 1)]
+
+
+@pytest.mark.parametrize("kind,B,T,N,D,p,prec", _DENSE)
+def test_dense_path_matches_oracle(kind, B, T, N, D, p, prec):
+    g = rng(7200 + N + T)
+    S = _spikes(g, B, T, N, p, kind)
+    gI = g.standard_normal((B, T, N)).astype(np.float32)
+    E = _events(S, D)
+    assert E > B * (T - D) * N // 256   # the case is meant for the dense path
+    log(f"[wgrad] dense {kind} B={B} T={T} N={N} D={D} prec={prec}: {E} events")
+    got, count, _ = _run(S, gI, D, kind, prec=prec)
+    assert count == E
+    check_grad("grad_W_rec", got, _reference(gI, S, D), tol=1e-4 if prec == 0 else 1e-2)
+
+
+def test_no_source_steps():
+    """T <= D leaves no (t, t - D) pair: zeros (written over an uninitialised
+    output); T = D + 1 leaves one source step a sequence."""
+    g = rng(7300)
+    for B, T, N, D in [(2, 5, 10, 7), (2, 7, 10, 7), (3, 8, 12, 7)]:
+        S = _spikes(g, B, T, N, 0.5, "u8")
+        gI = g.standard_normal((B, T, N)).astype(np.float32)
+        log(f"[wgrad] short B={B} T={T} N={N} D={D}")
+        got, count, _ = _run(S, gI, D, "u8")
+        assert count == _events(S, D)
+        if T <= D:
+            assert not got.any()
+        else:
+            check_grad("grad_W_rec", got, _reference(gI, S, D))
+
+
+def test_workspace_shared_by_both_paths():
+    """One workspace, alternating dense and event-path calls: each result as when
+    run alone."""
+    B, T, N, D = 2, 400, 128, 4
+    g = rng(7400)
+    dense = _spikes(g, B, T, N, 0.4, "u8")
+    sparse = _spikes(g, B, T, N, 0.003, "u8")
+    gI = g.standard_normal((B, T, N)).astype(np.float32)
+    log(f"[wgrad] shared workspace B={B} T={T} N={N} D={D}")
+    a, _, ws = _run(sparse, gI, D, "u8")
+    b, _, _ = _run(dense, gI, D, "u8", ws=ws)
+    c, _, _ = _run(sparse, gI, D, "u8", ws=ws)
+    assert np.array_equal(a.view(np.uint32), c.view(np.uint32))
+    _check_event_bound("grad_W_rec (events)", c, gI, sparse, D)
+    check_grad("grad_W_rec (dense)", b, _reference(gI, dense, D))
