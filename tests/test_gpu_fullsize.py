@@ -69,6 +69,63 @@ def test_fine_dt_fit_full_size():
         "grad rel L2 " + " ".join(f"{k} {v:.1e}" for k, v in errs.items()))
 
 
+def test_recurrent_weight_grad_full_size():
+    """alif_recurrent_weight_grad at the recurrent leg's shape and launch (64 x 256
+    neurons, T = 20000, D = T_R = 40): seeded spikes at the leg's firing rate
+    (2.3 Hz at DT 0.05 ms, so the event path runs, 32 segments of 10 groups) and a
+    standard-normal gI. Whole output: the device's event count equals the number
+    of nonzero source entries, and two calls agree bit for bit. 16 sampled columns
+    of dW_rec (every row i) against the oracle's product on the same columns,
+    within the FP32 rounding bound of fixed-order event sums."""
+    import ctypes
+
+    import torch
+
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif
+    B, T, N, dt, arp = 64, 20000, 256, 0.05, 2.0
+    D = alif.refractory_steps(dt, arp)
+    g = rng(91)
+    size = B * T * N
+    idx = np.unique(g.integers(0, size, int(size * 2.3 * dt * 1e-3)))
+    S = np.zeros(size, np.uint8)
+    S[idx] = 1
+    S = S.reshape(B, T, N)
+    gI = g.standard_normal((B, T, N), dtype=np.float32)
+    E = int(np.count_nonzero(S[:, :T - D]))
+    log(f"[full] recurrent weight gradient B={B} T={T} N={N} D={D}: {E} events")
+    desc = alif.make_desc(B, T, N, dt, arp)
+    n = ctypes.c_size_t()
+    L.check(L.load().alif_recurrent_workspace_bytes(ctypes.byref(desc), ctypes.byref(n)))
+    ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+    fwd = {"desc": desc, "delay": D, "spikes": torch.as_tensor(S, device="cuda"), "workspace": ws}
+    gIt = torch.as_tensor(gI, device="cuda")
+    dW = np_(alif.recurrent_weight_grad(fwd, gIt))
+    again = np_(alif.recurrent_weight_grad(fwd, gIt))
+    torch.cuda.synchronize()
+    count = int(ws[:8].cpu().numpy().view(np.uint64)[0])
+    assert count == E and E <= B * (T - D) * N // 256
+    assert np.array_equal(dW.view(np.uint32), again.view(np.uint32))
+    js = np.sort(rng(92).choice(N, 16, replace=False))
+    Sj = S[:, :, js]
+    ref = oracle.recurrent_weight_grad(gI, Sj, D)
+    # |gI|^T |S| over the same columns, from the events (the bound's scale)
+    rows = gI.reshape(-1, N)
+    Ssh = np.zeros((B, T, len(js)), np.float64)
+    Ssh[:, D:] = Sj[:, :T - D]
+    Ssh = Ssh.reshape(-1, len(js))
+    A = np.zeros((N, len(js)))
+    for c in range(len(js)):
+        r = np.nonzero(Ssh[:, c])[0]
+        A[:, c] = np.abs(rows[r].astype(np.float64)).T @ np.abs(Ssh[r, c])
+    n_j = np.count_nonzero(Ssh, axis=0).astype(np.float64)
+    bound = (2.0 * n_j[None, :] + 4.0) * 2.0 ** -24 * A
+    err = np.abs(dW[:, js].astype(np.float64) - ref)
+    log(f"[report] recurrent dW_rec full: {E} events; 16 sampled columns: max |err| {err.max():.2e}, "
+        f"worst err / bound {float((err / np.maximum(bound, 1e-300)).max()):.3f}")
+    assert (err <= bound).all()
+
+
 @pytest.mark.parametrize("driven", [False, True])
 def test_shd_like_training_full_size(driven):
     """700 -> 512 ALIF -> 20 readout, B = 32, T = 1000, DT = 1 ms, cross-entropy
