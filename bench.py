@@ -635,6 +635,9 @@ def recurrent_leg(w, I, P, gS, steps=3):
         del cg, fg
     except Exception as e:   # report, keep the eager numbers
         log(f"[bench] recurrent graph capture failed: {e}")
+    out = alif.backward_recurrent(f, I, P, grad_spikes=gS)   # warm-up (output allocations)
+    del out
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         out = alif.backward_recurrent(f, I, P, grad_spikes=gS)

@@ -126,6 +126,9 @@ def test_projection_and_recurrent_validation_host_side():
     assert lib.alif_recurrent_weight_grad(by(_desc()), 1, None, None, None, None, None) == L.ALIF_EINVAL
     assert lib.alif_recurrent_weight_grad(by(_desc()), 0, None, None, None, None, None) == L.ALIF_EINVAL
     assert b"required" in lib.alif_last_error()
+    # the event count and masks sit at the workspace's start: it must be 256-byte aligned
+    assert lib.alif_recurrent_weight_grad(by(_desc()), 0, 256, 256, 256, 256 + 16, None) == L.ALIF_EINVAL
+    assert b"aligned" in lib.alif_last_error()
 
 
 def _request(N=100, T=1000, dt=0.05, arp=2.0, **kw):
