@@ -820,6 +820,26 @@ def serve_leg(n_requests, rate_hz, max_slots, budget_gib, output="events", seed=
     return out
 
 
+def copy_rate(torch, dev, mib=512, reps=5):
+    """What a plain device-to-device copy reaches on this GPU (torch's copy, timed
+    with HIP events on torch's stream): bytes read plus bytes written per second,
+    in GB/s. Context for the HBM roofline, whose peak stays the published 8 TB/s."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def headline(res):
     """The compact result line (well under 2 KB): the contract's keys, the roofline
     and CPU baseline of the timed step, the sequential comparator, and one-line
@@ -834,7 +854,8 @@ def headline(res):
     rf = res["roofline"]
     out["roofline"] = {"bound": rf["bound"], "kernel": rf["kernel"], "achieved": r3(rf["achieved"]),
                        "peak": rf["peak"], "unit": rf["unit"], "frac": r3(rf["frac"]),
-                       "traffic": rf["traffic"]}
+                       "traffic": rf["traffic"], "copy_GBs": r3(rf.get("copy_GBs")),
+                       "frac_of_copy": r3(rf.get("frac_of_copy"))}
     out["kernels_ms"] = {k: r3(v["avg_ms"]) for k, v in res["kernels"].items()}
     cpu = res.get("cpu_baseline")
     if cpu:
@@ -924,6 +945,8 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {args.calibrate_copy_mib} MiB read + {args.calibrate_copy_mib} MiB written")
         del src, dst
+    copy_gbs = copy_rate(torch, dev)
+    log(f"[bench] device-to-device copy: {copy_gbs:.0f} GB/s (bytes read + written)")
     log("[bench] generating the fine-DT OU workload")
     w = synth.fine_dt_fit(seed=0, B=args.B, N=args.N, T=args.T)
     B, T, N = w.inputs["I"].shape
@@ -1081,7 +1104,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": dom["achieved_GBs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["frac_of_peak"],
                      "traffic": measured_traffic().get(dom_name),
-                     "algorithmic_bytes_per_launch": dom["bytes_per_launch"]},
+                     "algorithmic_bytes_per_launch": dom["bytes_per_launch"],
+                     "copy_GBs": copy_gbs, "frac_of_copy": dom["achieved_GBs"] / copy_gbs},
         "kernels": {"block_fwd": k_fwd, "block_bwd": k_bwd},
         "sequential": seq,
         "speedup_vs_sequential": (value / seq["value"]) if seq else None,
