@@ -1,7 +1,8 @@
 // Leaky non-spiking readout (paper supplementary, "Readout neurons"):
 //   I_r = W_r S,  V_r[t] = beta_r V_r[t-1] + (1 - beta_r) I_r[t],  o = sum_t V_r[t],
 // beta_r = exp(-DT / tau_r). The projection runs on the MFMA GEMM; the
-// integration is one thread per (batch, readout neuron) in FP64.
+// integration is one thread per (batch, readout neuron) in FP64, its loads issued a
+// chunk of steps ahead.
 // Workspace layout (kept by the caller from forward to backward):
 //   I_r [B*T][C] f32 | V_r [B*T][C] f32 | gI_r [B*T][C] f32 | part [B][C] f64 | GEMM split scratch
 #include <hip/hip_runtime.h>
@@ -35,40 +36,94 @@ RoWs ro_ws(void *ws, int B, int T, int C) {
     return w;
 }
 
-__global__ void k_readout_fwd(int B, int T, int C, double dt, const float *tau_r, const float *Ir,
-                              float *Vr, float *o) {
+// One thread per (b, c) runs the recurrence over T in FP64. The loads of I_r (and,
+// backward, of V_r) for the next RU steps are issued before this chunk's
+// arithmetic, so the loop waits for a chunk of loads once instead of one L2 round
+// trip per step; the arithmetic and its order are the plain recurrence's.
+constexpr int RU = 32;
+
+__global__ __launch_bounds__(64) void k_readout_fwd(int B, int T, int C, double dt, const float *__restrict__ tau_r,
+                                                    const float *__restrict__ Ir, float *__restrict__ Vr,
+                                                    float *__restrict__ o) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B * C) return;
     const int b = i / C, c = i - b * C;
     const double lb = -dt / (double)tau_r[c];
     const double beta = exp(lb), omb = -expm1(lb);
+    const float *ir = Ir + (size_t)b * T * C + c;
+    float *vr = Vr + (size_t)b * T * C + c;
     double v = 0.0, sum = 0.0;
-    for (int t = 0; t < T; t++) {
-        const size_t e = ((size_t)b * T + t) * C + c;
-        v = fma(beta, v, omb * (double)Ir[e]);
-        Vr[e] = (float)v;
-        sum += v;
+    float nxt[RU];
+#pragma unroll
+    for (int u = 0; u < RU; u++) nxt[u] = u < T ? ir[(size_t)u * C] : 0.0f;
+    for (int t0 = 0; t0 < T; t0 += RU) {
+        float cur[RU];
+#pragma unroll
+        for (int u = 0; u < RU; u++) cur[u] = nxt[u];
+#pragma unroll
+        for (int u = 0; u < RU; u++) {
+            const int t = t0 + RU + u;
+            nxt[u] = t < T ? ir[(size_t)t * C] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < RU; u++) {
+            const int t = t0 + u;
+            if (t < T) {
+                v = fma(beta, v, omb * (double)cur[u]);
+                vr[(size_t)t * C] = (float)v;
+                sum += v;
+            }
+        }
     }
     o[i] = (float)sum;
 }
 
 // reverse recurrence lam[t] = go + beta lam[t+1]; gI_r[t] = (1 - beta) lam[t];
 // d/dbeta = sum_t (V_r[t-1] - I_r[t]) lam[t]
-__global__ void k_readout_bwd(int B, int T, int C, double dt, const float *tau_r, const float *Ir,
-                              const float *Vr, const float *go, float *gIr, double *part) {
+__global__ __launch_bounds__(64) void k_readout_bwd(int B, int T, int C, double dt, const float *__restrict__ tau_r,
+                                                    const float *__restrict__ Ir, const float *__restrict__ Vr,
+                                                    const float *__restrict__ go, float *__restrict__ gIr,
+                                                    double *__restrict__ part) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B * C) return;
     const int b = i / C, c = i - b * C;
     const double lb = -dt / (double)tau_r[c];
     const double beta = exp(lb), omb = -expm1(lb);
     const double g = go[i];
+    const size_t base = (size_t)b * T * C + c;
+    const float *ir = Ir + base, *vr = Vr + base;
+    float *gi = gIr + base;
     double lam = 0.0, gb = 0.0;
-    for (int t = T - 1; t >= 0; t--) {
-        const size_t e = ((size_t)b * T + t) * C + c;
-        lam = fma(beta, lam, g);
-        gIr[e] = (float)(omb * lam);
-        const double vprev = t > 0 ? (double)Vr[e - C] : 0.0;
-        gb = fma(vprev - (double)Ir[e], lam, gb);
+    // steps t = t0 - u of a chunk, last to first; V_r[t - 1] is 0 at t = 0
+    float ni[RU], nv[RU];
+#pragma unroll
+    for (int u = 0; u < RU; u++) {
+        const int t = T - 1 - u;
+        ni[u] = t >= 0 ? ir[(size_t)t * C] : 0.0f;
+        nv[u] = t > 0 ? vr[(size_t)(t - 1) * C] : 0.0f;
+    }
+    for (int t0 = T - 1; t0 >= 0; t0 -= RU) {
+        float ci[RU], cv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; u++) {
+            ci[u] = ni[u];
+            cv[u] = nv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < RU; u++) {
+            const int t = t0 - RU - u;
+            ni[u] = t >= 0 ? ir[(size_t)t * C] : 0.0f;
+            nv[u] = t > 0 ? vr[(size_t)(t - 1) * C] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < RU; u++) {
+            const int t = t0 - u;
+            if (t >= 0) {
+                lam = fma(beta, lam, g);
+                gi[(size_t)t * C] = (float)(omb * lam);
+                gb = fma((double)cv[u] - (double)ci[u], lam, gb);
+            }
+        }
     }
     part[i] = gb;
 }
@@ -128,7 +183,7 @@ int alif_readout_forward(int32_t B, int32_t T, int32_t n_hidden, int32_t C, doub
     hipError_t e = gemm_launch(g, false, st);
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
     if (B * C == 0) return ALIF_OK;
-    hipLaunchKernelGGL(k_readout_fwd, dim3((B * C + 127) / 128), dim3(128), 0, st, B, T, C, dt_ms, tau_r,
+    hipLaunchKernelGGL(k_readout_fwd, dim3((B * C + 63) / 64), dim3(64), 0, st, B, T, C, dt_ms, tau_r,
                        w.Ir, w.Vr, o);
     e = hipGetLastError();
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
@@ -146,7 +201,7 @@ int alif_readout_backward(int32_t B, int32_t T, int32_t n_hidden, int32_t C, dou
     hipStream_t st = (hipStream_t)stream;
     RoWs w = ro_ws(workspace, B, T, C);
     if (B * C > 0) {
-        hipLaunchKernelGGL(k_readout_bwd, dim3((B * C + 127) / 128), dim3(128), 0, st, B, T, C, dt_ms,
+        hipLaunchKernelGGL(k_readout_bwd, dim3((B * C + 63) / 64), dim3(64), 0, st, B, T, C, dt_ms,
                            tau_r, w.Ir, w.Vr, go, w.gIr, w.part);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
