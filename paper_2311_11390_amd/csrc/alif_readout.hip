@@ -1,8 +1,8 @@
 // Leaky non-spiking readout (paper supplementary, "Readout neurons"):
 //   I_r = W_r S,  V_r[t] = beta_r V_r[t-1] + (1 - beta_r) I_r[t],  o = sum_t V_r[t],
 // beta_r = exp(-DT / tau_r). The projection runs on the MFMA GEMM; the
-// integration is one thread per (batch, readout neuron) in FP64, its loads issued a
-// chunk of steps ahead.
+// integration runs in FP64, each (batch, readout neuron) row on 16 lanes that take
+// a chunk of time each and join their carries with a scan.
 // Workspace layout (kept by the caller from forward to backward):
 //   I_r [B*T][C] f32 | V_r [B*T][C] f32 | gI_r [B*T][C] f32 | part [B][C] f64 | GEMM split scratch
 #include <hip/hip_runtime.h>
@@ -36,46 +36,110 @@ RoWs ro_ws(void *ws, int B, int T, int C) {
     return w;
 }
 
-// One thread per (b, c) runs the recurrence over T in FP64. The loads of I_r (and,
-// backward, of V_r) for the next RU steps are issued before this chunk's
-// arithmetic, so the loop waits for a chunk of loads once instead of one L2 round
-// trip per step; the arithmetic and its order are the plain recurrence's.
-constexpr int RU = 32;
+// Each (b, c) row's recurrence over T is cut into RK chunks of Lc = ceil(T / RK)
+// steps, one lane each (RK consecutive lanes per row). A chunk first runs from zero
+// to get its local end value; a decayed scan across the RK lanes (Hillis-Steele,
+// four shuffle steps, FP64) turns those into every chunk's true carry-in,
+//   V_in(k) = sum over k' < k of beta^(Lc (k - 1 - k')) e(k'),
+// and the chunk then reruns from its carry-in, writing V_r and summing it. Loads go
+// 32 steps at a time. The sum over chunks is a fixed shuffle tree. The backward is
+// the same with the reverse recurrence and a reverse scan. Every chunk before the
+// last non-empty one is full, so beta^Lc is the only decay across chunks.
+constexpr int RK = 16;   // chunks a row (lanes)
+constexpr int RU = 32;   // steps whose loads are issued together
+
+__device__ __forceinline__ double dshfl_up(double x, int d) { return __shfl_up(x, d, RK); }
+__device__ __forceinline__ double dshfl_down(double x, int d) { return __shfl_down(x, d, RK); }
+__device__ __forceinline__ double dshfl_xor(double x, int d) { return __shfl_xor(x, d, RK); }
+
+// fixed-order sum over the RK lanes of a row
+__device__ __forceinline__ double row_sum(double x) {
+#pragma unroll
+    for (int d = RK / 2; d > 0; d >>= 1) x += dshfl_xor(x, d);
+    return x;
+}
+
+// Run v <- beta v + omb I[t] over t in [t0, t1) from v; with STORE, write V_r and sum v.
+template <bool STORE>
+__device__ __forceinline__ double run_fwd(const float *__restrict__ ir, float *__restrict__ vr, int C, int t0,
+                                          int t1, double beta, double omb, double v, double &sum) {
+    for (int tb = t0; tb < t1; tb += RU) {
+        float x[RU];
+#pragma unroll
+        for (int u = 0; u < RU; u++) x[u] = tb + u < t1 ? ir[(size_t)(tb + u) * C] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < RU; u++)
+            if (tb + u < t1) {
+                v = fma(beta, v, omb * (double)x[u]);
+                if constexpr (STORE) {
+                    vr[(size_t)(tb + u) * C] = (float)v;
+                    sum += v;
+                }
+            }
+    }
+    return v;
+}
 
 __global__ __launch_bounds__(64) void k_readout_fwd(int B, int T, int C, double dt, const float *__restrict__ tau_r,
                                                     const float *__restrict__ Ir, float *__restrict__ Vr,
                                                     float *__restrict__ o) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= B * C) return;
-    const int b = i / C, c = i - b * C;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid / RK, k = gid % RK;   // row, chunk
+    const bool row_ok = i < B * C;          // (whole RK-lane groups share it)
+    const int b = row_ok ? i / C : 0, c = row_ok ? i - b * C : 0;
     const double lb = -dt / (double)tau_r[c];
     const double beta = exp(lb), omb = -expm1(lb);
+    const int Lc = (T + RK - 1) / RK;
+    const int t0 = min(T, k * Lc), t1 = min(T, t0 + Lc);
     const float *ir = Ir + (size_t)b * T * C + c;
     float *vr = Vr + (size_t)b * T * C + c;
-    double v = 0.0, sum = 0.0;
-    float nxt[RU];
+    double unused = 0.0;
+    const double e = row_ok ? run_fwd<false>(ir, vr, C, t0, t1, beta, omb, 0.0, unused) : 0.0;
+    // inclusive decayed scan of the local end values, then shift by one chunk
+    double sc = e, dk = exp(lb * (double)Lc);
 #pragma unroll
-    for (int u = 0; u < RU; u++) nxt[u] = u < T ? ir[(size_t)u * C] : 0.0f;
-    for (int t0 = 0; t0 < T; t0 += RU) {
-        float cur[RU];
+    for (int d = 1; d < RK; d <<= 1) {
+        const double y = dshfl_up(sc, d);
+        if (k >= d) sc = fma(dk, y, sc);
+        dk *= dk;
+    }
+    const double prev = dshfl_up(sc, 1);
+    const double vin = k > 0 ? prev : 0.0;
+    double sum = 0.0;
+    if (row_ok) run_fwd<true>(ir, vr, C, t0, t1, beta, omb, vin, sum);
+    sum = row_sum(sum);
+    if (row_ok && k == 0) o[i] = (float)sum;
+}
+
+// Run lam <- g + beta lam over t = t1 - 1 down to t0 from lam; with ACC, write gI_r
+// and accumulate d/dbeta (V_r[t - 1] - I_r[t]) lam.
+template <bool ACC>
+__device__ __forceinline__ double run_bwd(const float *__restrict__ ir, const float *__restrict__ vr,
+                                          float *__restrict__ gi, int C, int t0, int t1, double beta, double omb,
+                                          double g, double lam, double &gb) {
+    for (int tb = t1 - 1; tb >= t0; tb -= RU) {
+        float xi[RU], xv[RU];
+        if constexpr (ACC) {
 #pragma unroll
-        for (int u = 0; u < RU; u++) cur[u] = nxt[u];
-#pragma unroll
-        for (int u = 0; u < RU; u++) {
-            const int t = t0 + RU + u;
-            nxt[u] = t < T ? ir[(size_t)t * C] : 0.0f;
+            for (int u = 0; u < RU; u++) {
+                const int t = tb - u;
+                xi[u] = t >= t0 ? ir[(size_t)t * C] : 0.0f;
+                xv[u] = (t >= t0 && t > 0) ? vr[(size_t)(t - 1) * C] : 0.0f;
+            }
         }
 #pragma unroll
         for (int u = 0; u < RU; u++) {
-            const int t = t0 + u;
-            if (t < T) {
-                v = fma(beta, v, omb * (double)cur[u]);
-                vr[(size_t)t * C] = (float)v;
-                sum += v;
+            const int t = tb - u;
+            if (t >= t0) {
+                lam = fma(beta, lam, g);
+                if constexpr (ACC) {
+                    gi[(size_t)t * C] = (float)(omb * lam);
+                    gb = fma((double)xv[u] - (double)xi[u], lam, gb);
+                }
             }
         }
     }
-    o[i] = (float)sum;
+    return lam;
 }
 
 // reverse recurrence lam[t] = go + beta lam[t+1]; gI_r[t] = (1 - beta) lam[t];
@@ -84,48 +148,35 @@ __global__ __launch_bounds__(64) void k_readout_bwd(int B, int T, int C, double 
                                                     const float *__restrict__ Ir, const float *__restrict__ Vr,
                                                     const float *__restrict__ go, float *__restrict__ gIr,
                                                     double *__restrict__ part) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= B * C) return;
-    const int b = i / C, c = i - b * C;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid / RK, k = gid % RK;
+    const bool row_ok = i < B * C;
+    const int b = row_ok ? i / C : 0, c = row_ok ? i - b * C : 0;
     const double lb = -dt / (double)tau_r[c];
     const double beta = exp(lb), omb = -expm1(lb);
-    const double g = go[i];
+    const double g = row_ok ? (double)go[i] : 0.0;
+    const int Lc = (T + RK - 1) / RK;
+    const int t0 = min(T, k * Lc), t1 = min(T, t0 + Lc);
     const size_t base = (size_t)b * T * C + c;
     const float *ir = Ir + base, *vr = Vr + base;
     float *gi = gIr + base;
-    double lam = 0.0, gb = 0.0;
-    // steps t = t0 - u of a chunk, last to first; V_r[t - 1] is 0 at t = 0
-    float ni[RU], nv[RU];
+    double unused = 0.0;
+    // lambda at this chunk's first step from a zero carry at its end
+    const double ls = row_ok ? run_bwd<false>(ir, vr, gi, C, t0, t1, beta, omb, g, 0.0, unused) : 0.0;
+    // inclusive reverse decayed scan, then shift by one chunk: the carry at this chunk's end
+    double sc = ls, dk = exp(lb * (double)Lc);
 #pragma unroll
-    for (int u = 0; u < RU; u++) {
-        const int t = T - 1 - u;
-        ni[u] = t >= 0 ? ir[(size_t)t * C] : 0.0f;
-        nv[u] = t > 0 ? vr[(size_t)(t - 1) * C] : 0.0f;
+    for (int d = 1; d < RK; d <<= 1) {
+        const double y = dshfl_down(sc, d);
+        if (k + d < RK) sc = fma(dk, y, sc);
+        dk *= dk;
     }
-    for (int t0 = T - 1; t0 >= 0; t0 -= RU) {
-        float ci[RU], cv[RU];
-#pragma unroll
-        for (int u = 0; u < RU; u++) {
-            ci[u] = ni[u];
-            cv[u] = nv[u];
-        }
-#pragma unroll
-        for (int u = 0; u < RU; u++) {
-            const int t = t0 - RU - u;
-            ni[u] = t >= 0 ? ir[(size_t)t * C] : 0.0f;
-            nv[u] = t > 0 ? vr[(size_t)(t - 1) * C] : 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < RU; u++) {
-            const int t = t0 - u;
-            if (t >= 0) {
-                lam = fma(beta, lam, g);
-                gi[(size_t)t * C] = (float)(omb * lam);
-                gb = fma((double)cv[u] - (double)ci[u], lam, gb);
-            }
-        }
-    }
-    part[i] = gb;
+    const double nxt = dshfl_down(sc, 1);
+    const double lin = k + 1 < RK ? nxt : 0.0;
+    double gb = 0.0;
+    if (row_ok) run_bwd<true>(ir, vr, gi, C, t0, t1, beta, omb, g, lin, gb);
+    gb = row_sum(gb);
+    if (row_ok && k == 0) part[i] = gb;
 }
 
 __global__ void k_readout_tau(int B, int C, double dt, const float *tau_r, const double *part, float *g_tau) {
@@ -183,8 +234,8 @@ int alif_readout_forward(int32_t B, int32_t T, int32_t n_hidden, int32_t C, doub
     hipError_t e = gemm_launch(g, false, st);
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
     if (B * C == 0) return ALIF_OK;
-    hipLaunchKernelGGL(k_readout_fwd, dim3((B * C + 63) / 64), dim3(64), 0, st, B, T, C, dt_ms, tau_r,
-                       w.Ir, w.Vr, o);
+    const dim3 grid((unsigned)(((long long)B * C * RK + 63) / 64));
+    hipLaunchKernelGGL(k_readout_fwd, grid, dim3(64), 0, st, B, T, C, dt_ms, tau_r, w.Ir, w.Vr, o);
     e = hipGetLastError();
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
     return ALIF_OK;
@@ -201,8 +252,9 @@ int alif_readout_backward(int32_t B, int32_t T, int32_t n_hidden, int32_t C, dou
     hipStream_t st = (hipStream_t)stream;
     RoWs w = ro_ws(workspace, B, T, C);
     if (B * C > 0) {
-        hipLaunchKernelGGL(k_readout_bwd, dim3((B * C + 63) / 64), dim3(64), 0, st, B, T, C, dt_ms,
-                           tau_r, w.Ir, w.Vr, go, w.gIr, w.part);
+        const dim3 grid((unsigned)(((long long)B * C * RK + 63) / 64));
+        hipLaunchKernelGGL(k_readout_bwd, grid, dim3(64), 0, st, B, T, C, dt_ms, tau_r, w.Ir, w.Vr, go, w.gIr,
+                           w.part);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
     }

@@ -271,10 +271,12 @@ def test_single_layer_driven_workload():
     assert np.abs(np_(f["theta"]) - orc["TH"]).max() < 1e-4
 
 
-@pytest.mark.parametrize("T", [230, 64, 5])
+@pytest.mark.parametrize("T", [230, 64, 5, 17, 1000])
 def test_readout_forward_backward(T):
-    """The readout against the oracle; T covers a ragged last chunk of the
-    recurrence's 32-step load chunks, whole chunks, and a single partial one."""
+    """The readout against the oracle. The recurrence runs as 16 time chunks of
+    ceil(T / 16) steps joined by a carry scan, loading 32 steps at a time: T covers
+    ragged and whole chunks, chunks left empty (T 5, 17), a single step, and the
+    SHD length."""
     import torch
     from paper_2311_11390_amd import alif
     B, H, C, dt = 3, 150, 20, 1.0
