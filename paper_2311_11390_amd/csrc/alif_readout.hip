@@ -1,8 +1,8 @@
 // Leaky non-spiking readout (paper supplementary, "Readout neurons"):
 //   I_r = W_r S,  V_r[t] = beta_r V_r[t-1] + (1 - beta_r) I_r[t],  o = sum_t V_r[t],
 // beta_r = exp(-DT / tau_r). The projection runs on the MFMA GEMM; the
-// integration runs in FP64, each (batch, readout neuron) row on 16 lanes that take
-// a chunk of time each and join their carries with a scan.
+// integration runs in FP64, each (batch, readout neuron) row on 16 threads that take
+// a chunk of time each and join their carries through LDS.
 // Workspace layout (kept by the caller from forward to backward):
 //   I_r [B*T][C] f32 | V_r [B*T][C] f32 | gI_r [B*T][C] f32 | part [B][C] f64 | GEMM split scratch
 #include <hip/hip_runtime.h>
@@ -37,27 +37,20 @@ RoWs ro_ws(void *ws, int B, int T, int C) {
 }
 
 // Each (b, c) row's recurrence over T is cut into RK chunks of Lc = ceil(T / RK)
-// steps, one lane each (RK consecutive lanes per row). A chunk first runs from zero
-// to get its local end value; a decayed scan across the RK lanes (Hillis-Steele,
-// four shuffle steps, FP64) turns those into every chunk's true carry-in,
-//   V_in(k) = sum over k' < k of beta^(Lc (k - 1 - k')) e(k'),
-// and the chunk then reruns from its carry-in, writing V_r and summing it. Loads go
-// 32 steps at a time. The sum over chunks is a fixed shuffle tree. The backward is
-// the same with the reverse recurrence and a reverse scan. Every chunk before the
-// last non-empty one is full, so beta^Lc is the only decay across chunks.
-constexpr int RK = 16;   // chunks a row (lanes)
+// steps. A workgroup holds batch element b = blockIdx.x and CG classes (blockIdx.y
+// picks which): thread (k, cl) = (tid / CG, tid % CG) takes chunk k of class cl,
+// so consecutive threads read consecutive classes of one step. A chunk first runs
+// from zero to get its local end value; through LDS every thread then forms its
+// true carry-in,
+//   V_in(k) = sum over k' < k of beta^(Lc (k - 1 - k')) e(k')   (Horner over k'),
+// and reruns its chunk from it, writing V_r and summing it; the chunk sums are added
+// in chunk order. Loads go 32 steps at a time. The backward is the same with the
+// reverse recurrence (its local pass needs no loads) and the carry from the chunks
+// after. Every chunk before the last non-empty one is full, so beta^Lc is the only
+// decay across chunks.
+constexpr int RK = 16;   // chunks a row
 constexpr int RU = 32;   // steps whose loads are issued together
-
-__device__ __forceinline__ double dshfl_up(double x, int d) { return __shfl_up(x, d, RK); }
-__device__ __forceinline__ double dshfl_down(double x, int d) { return __shfl_down(x, d, RK); }
-__device__ __forceinline__ double dshfl_xor(double x, int d) { return __shfl_xor(x, d, RK); }
-
-// fixed-order sum over the RK lanes of a row
-__device__ __forceinline__ double row_sum(double x) {
-#pragma unroll
-    for (int d = RK / 2; d > 0; d >>= 1) x += dshfl_xor(x, d);
-    return x;
-}
+constexpr int RCG = 32;  // classes a workgroup at most (512 threads: no register spills)
 
 // Run v <- beta v + omb I[t] over t in [t0, t1) from v; with STORE, write V_r and sum v.
 template <bool STORE>
@@ -80,35 +73,37 @@ __device__ __forceinline__ double run_fwd(const float *__restrict__ ir, float *_
     return v;
 }
 
-__global__ __launch_bounds__(64) void k_readout_fwd(int B, int T, int C, double dt, const float *__restrict__ tau_r,
-                                                    const float *__restrict__ Ir, float *__restrict__ Vr,
-                                                    float *__restrict__ o) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = gid / RK, k = gid % RK;   // row, chunk
-    const bool row_ok = i < B * C;          // (whole RK-lane groups share it)
-    const int b = row_ok ? i / C : 0, c = row_ok ? i - b * C : 0;
-    const double lb = -dt / (double)tau_r[c];
+__global__ __launch_bounds__(RK * RCG) void k_readout_fwd(int B, int T, int C, double dt,
+                                                          const float *__restrict__ tau_r,
+                                                          const float *__restrict__ Ir, float *__restrict__ Vr,
+                                                          float *__restrict__ o) {
+    __shared__ double sh[RK][RCG];
+    const int CG = blockDim.x / RK;
+    const int k = threadIdx.x / CG, cl = threadIdx.x - k * CG;
+    const int b = blockIdx.x, c = blockIdx.y * CG + cl;
+    const bool ok = c < C;
+    const double lb = -dt / (double)tau_r[ok ? c : 0];
     const double beta = exp(lb), omb = -expm1(lb);
     const int Lc = (T + RK - 1) / RK;
     const int t0 = min(T, k * Lc), t1 = min(T, t0 + Lc);
     const float *ir = Ir + (size_t)b * T * C + c;
     float *vr = Vr + (size_t)b * T * C + c;
     double unused = 0.0;
-    const double e = row_ok ? run_fwd<false>(ir, vr, C, t0, t1, beta, omb, 0.0, unused) : 0.0;
-    // inclusive decayed scan of the local end values, then shift by one chunk
-    double sc = e, dk = exp(lb * (double)Lc);
-#pragma unroll
-    for (int d = 1; d < RK; d <<= 1) {
-        const double y = dshfl_up(sc, d);
-        if (k >= d) sc = fma(dk, y, sc);
-        dk *= dk;
-    }
-    const double prev = dshfl_up(sc, 1);
-    const double vin = k > 0 ? prev : 0.0;
+    sh[k][cl] = ok ? run_fwd<false>(ir, vr, C, t0, t1, beta, omb, 0.0, unused) : 0.0;
+    __syncthreads();
+    const double dk = exp(lb * (double)Lc);
+    double vin = 0.0;
+    for (int kk = 0; kk < k; kk++) vin = fma(dk, vin, sh[kk][cl]);
     double sum = 0.0;
-    if (row_ok) run_fwd<true>(ir, vr, C, t0, t1, beta, omb, vin, sum);
-    sum = row_sum(sum);
-    if (row_ok && k == 0) o[i] = (float)sum;
+    if (ok) run_fwd<true>(ir, vr, C, t0, t1, beta, omb, vin, sum);
+    __syncthreads();
+    sh[k][cl] = sum;
+    __syncthreads();
+    if (ok && k == 0) {
+        double tot = 0.0;
+        for (int kk = 0; kk < RK; kk++) tot += sh[kk][cl];
+        o[(size_t)b * C + c] = (float)tot;
+    }
 }
 
 // Run lam <- g + beta lam over t = t1 - 1 down to t0 from lam; with ACC, write gI_r
@@ -144,17 +139,19 @@ __device__ __forceinline__ double run_bwd(const float *__restrict__ ir, const fl
 
 // reverse recurrence lam[t] = go + beta lam[t+1]; gI_r[t] = (1 - beta) lam[t];
 // d/dbeta = sum_t (V_r[t-1] - I_r[t]) lam[t]
-__global__ __launch_bounds__(64) void k_readout_bwd(int B, int T, int C, double dt, const float *__restrict__ tau_r,
-                                                    const float *__restrict__ Ir, const float *__restrict__ Vr,
-                                                    const float *__restrict__ go, float *__restrict__ gIr,
-                                                    double *__restrict__ part) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = gid / RK, k = gid % RK;
-    const bool row_ok = i < B * C;
-    const int b = row_ok ? i / C : 0, c = row_ok ? i - b * C : 0;
-    const double lb = -dt / (double)tau_r[c];
+__global__ __launch_bounds__(RK * RCG) void k_readout_bwd(int B, int T, int C, double dt,
+                                                          const float *__restrict__ tau_r,
+                                                          const float *__restrict__ Ir, const float *__restrict__ Vr,
+                                                          const float *__restrict__ go, float *__restrict__ gIr,
+                                                          double *__restrict__ part) {
+    __shared__ double sh[RK][RCG];
+    const int CG = blockDim.x / RK;
+    const int k = threadIdx.x / CG, cl = threadIdx.x - k * CG;
+    const int b = blockIdx.x, c = blockIdx.y * CG + cl;
+    const bool ok = c < C;
+    const double lb = -dt / (double)tau_r[ok ? c : 0];
     const double beta = exp(lb), omb = -expm1(lb);
-    const double g = row_ok ? (double)go[i] : 0.0;
+    const double g = ok ? (double)go[(size_t)b * C + c] : 0.0;
     const int Lc = (T + RK - 1) / RK;
     const int t0 = min(T, k * Lc), t1 = min(T, t0 + Lc);
     const size_t base = (size_t)b * T * C + c;
@@ -162,21 +159,22 @@ __global__ __launch_bounds__(64) void k_readout_bwd(int B, int T, int C, double 
     float *gi = gIr + base;
     double unused = 0.0;
     // lambda at this chunk's first step from a zero carry at its end
-    const double ls = row_ok ? run_bwd<false>(ir, vr, gi, C, t0, t1, beta, omb, g, 0.0, unused) : 0.0;
-    // inclusive reverse decayed scan, then shift by one chunk: the carry at this chunk's end
-    double sc = ls, dk = exp(lb * (double)Lc);
-#pragma unroll
-    for (int d = 1; d < RK; d <<= 1) {
-        const double y = dshfl_down(sc, d);
-        if (k + d < RK) sc = fma(dk, y, sc);
-        dk *= dk;
-    }
-    const double nxt = dshfl_down(sc, 1);
-    const double lin = k + 1 < RK ? nxt : 0.0;
+    sh[k][cl] = ok ? run_bwd<false>(ir, vr, gi, C, t0, t1, beta, omb, g, 0.0, unused) : 0.0;
+    __syncthreads();
+    // the carry at this chunk's end: the later chunks' values, Horner from the last
+    const double dk = exp(lb * (double)Lc);
+    double lin = 0.0;
+    for (int kk = RK - 1; kk > k; kk--) lin = fma(dk, lin, sh[kk][cl]);
     double gb = 0.0;
-    if (row_ok) run_bwd<true>(ir, vr, gi, C, t0, t1, beta, omb, g, lin, gb);
-    gb = row_sum(gb);
-    if (row_ok && k == 0) part[i] = gb;
+    if (ok) run_bwd<true>(ir, vr, gi, C, t0, t1, beta, omb, g, lin, gb);
+    __syncthreads();
+    sh[k][cl] = gb;
+    __syncthreads();
+    if (ok && k == 0) {
+        double tot = 0.0;
+        for (int kk = 0; kk < RK; kk++) tot += sh[kk][cl];
+        part[(size_t)b * C + c] = tot;
+    }
 }
 
 __global__ void k_readout_tau(int B, int C, double dt, const float *tau_r, const double *part, float *g_tau) {
@@ -234,8 +232,9 @@ int alif_readout_forward(int32_t B, int32_t T, int32_t n_hidden, int32_t C, doub
     hipError_t e = gemm_launch(g, false, st);
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
     if (B * C == 0) return ALIF_OK;
-    const dim3 grid((unsigned)(((long long)B * C * RK + 63) / 64));
-    hipLaunchKernelGGL(k_readout_fwd, grid, dim3(64), 0, st, B, T, C, dt_ms, tau_r, w.Ir, w.Vr, o);
+    const int cg = C < RCG ? C : RCG;
+    hipLaunchKernelGGL(k_readout_fwd, dim3((unsigned)B, (unsigned)((C + cg - 1) / cg)), dim3(RK * cg), 0, st, B, T,
+                       C, dt_ms, tau_r, w.Ir, w.Vr, o);
     e = hipGetLastError();
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
     return ALIF_OK;
@@ -252,9 +251,9 @@ int alif_readout_backward(int32_t B, int32_t T, int32_t n_hidden, int32_t C, dou
     hipStream_t st = (hipStream_t)stream;
     RoWs w = ro_ws(workspace, B, T, C);
     if (B * C > 0) {
-        const dim3 grid((unsigned)(((long long)B * C * RK + 63) / 64));
-        hipLaunchKernelGGL(k_readout_bwd, grid, dim3(64), 0, st, B, T, C, dt_ms, tau_r, w.Ir, w.Vr, go, w.gIr,
-                           w.part);
+        const int cg = C < RCG ? C : RCG;
+        hipLaunchKernelGGL(k_readout_bwd, dim3((unsigned)B, (unsigned)((C + cg - 1) / cg)), dim3(RK * cg), 0, st, B,
+                           T, C, dt_ms, tau_r, w.Ir, w.Vr, go, w.gIr, w.part);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
     }
