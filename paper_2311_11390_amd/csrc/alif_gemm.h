@@ -19,7 +19,8 @@ struct GemmIn {
 hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, const float *bias,
                               float *out, bool bf16, hipStream_t st, void *scratch = nullptr,
                               size_t scratch_bytes = 0);
-// bytes of the bfloat16 copy of a [N][K] weight matrix
+// bytes of the bfloat16 copy of a [N][K] weight matrix, as is or transposed, with
+// rows padded to 16 bytes
 size_t gemm_wbf16_bytes(int N, int K);
 // gW[N][K] = sum_m gI[m][n] x[m][k]   (split over m, reduced in a fixed order);
 // skip_cnt / skip_le: the device-side gate of GemmArgs

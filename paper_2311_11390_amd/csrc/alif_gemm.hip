@@ -611,13 +611,16 @@ static int dt_of(int kind) {
 }
 
 // W [N][K] float -> bfloat16 (round to nearest even), the same layout (TRANS = false)
-// or transposed to [K][N] (TRANS = true, through a 32 x 32 LDS tile)
+// or transposed to [K][N] (TRANS = true, through a 32 x 32 LDS tile), with output
+// rows of ldo >= K (resp. N) elements whose padding is zero
 template <bool TRANS>
-__global__ __launch_bounds__(256) void k_w_bf16(int N, int K, const float *W, __bf16 *out) {
+__global__ __launch_bounds__(256) void k_w_bf16(int N, int K, const float *W, __bf16 *out, int ldo) {
     if constexpr (!TRANS) {
-        const long long n = (long long)N * K;
-        for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
-            out[i] = (__bf16)W[i];
+        const long long n = (long long)N * ldo;
+        for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+            const long long r = i / ldo, k = i - r * ldo;
+            out[i] = (__bf16)(k < K ? W[r * K + k] : 0.0f);
+        }
     } else {
         __shared__ float t[32][33];
         const int k0 = blockIdx.x * 32, n0 = blockIdx.y * 32;
@@ -625,12 +628,19 @@ __global__ __launch_bounds__(256) void k_w_bf16(int N, int K, const float *W, __
         for (int r = ty; r < 32; r += 8)
             t[r][tx] = (n0 + r < N && k0 + tx < K) ? W[(size_t)(n0 + r) * K + k0 + tx] : 0.0f;
         __syncthreads();
+        // (the column tiles cover ldo: ldo <= 32 ceil(N / 32))
         for (int r = ty; r < 32; r += 8)
-            if (k0 + r < K && n0 + tx < N) out[(size_t)(k0 + r) * N + n0 + tx] = (__bf16)t[tx][r];
+            if (k0 + r < K && n0 + tx < ldo) out[(size_t)(k0 + r) * ldo + n0 + tx] = (__bf16)t[tx][r];
     }
 }
 
-size_t gemm_wbf16_bytes(int N, int K) { return (size_t)N * K * 2; }
+// bfloat16 rows padded to whole 16-byte chunks, which the large-tile kernel loads
+static int ld16(int n) { return (n + 7) / 8 * 8; }
+
+size_t gemm_wbf16_bytes(int N, int K) {
+    const size_t fwd = (size_t)N * ld16(K), trans = (size_t)K * ld16(N);
+    return (fwd > trans ? fwd : trans) * 2;
+}
 
 static bool scratch_fits(const void *scratch, size_t bytes, int N, int K) {
     return scratch && bytes >= gemm_wbf16_bytes(N, K) && (reinterpret_cast<uintptr_t>(scratch) & 15) == 0;
@@ -645,11 +655,12 @@ hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, 
     g.C = out; g.ldc = N; g.bias = bias; g.splits = 1;
     if (bf16 && M > 0 && N > 0 && scratch_fits(scratch, scratch_bytes, N, K)) {
         GemmArgs h = g;
-        h.B = scratch; h.b_dt = 2;
+        h.B = scratch; h.b_dt = 2; h.ldb = ld16(K);
         if (gemm_big_ok(h)) {
-            const long long n = (long long)N * K;
+            const long long n = (long long)N * h.ldb;
             const unsigned grid = (unsigned)((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048);
-            hipLaunchKernelGGL(k_w_bf16<false>, dim3(grid), dim3(256), 0, st, N, K, W, static_cast<__bf16 *>(scratch));
+            hipLaunchKernelGGL(k_w_bf16<false>, dim3(grid), dim3(256), 0, st, N, K, W, static_cast<__bf16 *>(scratch),
+                               (int)h.ldb);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             return gemm_big_launch(h, st);
@@ -699,10 +710,10 @@ hipError_t gemm_input_grad(size_t M, int N, int K, const float *gI, const float 
     g.C = gx; g.ldc = K; g.bias = nullptr; g.splits = 1;
     if (bf16 && M > 0 && K > 0 && scratch_fits(scratch, scratch_bytes, N, K)) {
         GemmArgs h = g;   // B(k, n) = W^T[k][n]: k-contiguous in the transposed copy
-        h.B = scratch; h.b_dt = 2; h.ldb = N; h.b_kc = 1;
+        h.B = scratch; h.b_dt = 2; h.ldb = ld16(N); h.b_kc = 1;
         if (gemm_big_ok(h)) {
             hipLaunchKernelGGL(k_w_bf16<true>, dim3((unsigned)((K + 31) / 32), (unsigned)((N + 31) / 32)), dim3(256), 0,
-                               st, N, K, W, static_cast<__bf16 *>(scratch));
+                               st, N, K, W, static_cast<__bf16 *>(scratch), (int)h.ldb);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             return gemm_big_launch(h, st);

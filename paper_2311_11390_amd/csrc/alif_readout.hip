@@ -222,6 +222,8 @@ int alif_readout_forward(int32_t B, int32_t T, int32_t n_hidden, int32_t C, doub
         return alif::set_error(ALIF_EINVAL, "unknown spike_dtype");
     if (!spikes || !W_r || !tau_r || !o || !workspace)
         return alif::set_error(ALIF_EINVAL, "NULL readout argument");
+    if ((C + RCG - 1) / RCG > 65535)
+        return alif::set_error(ALIF_EUNSUPPORTED, "too many readout neurons (C / 32 must stay within 65535)");
     hipStream_t st = (hipStream_t)stream;
     RoWs w = ro_ws(workspace, B, T, C);
     GemmArgs g{};
@@ -231,7 +233,7 @@ int alif_readout_forward(int32_t B, int32_t T, int32_t n_hidden, int32_t C, doub
     g.C = w.Ir; g.ldc = C; g.splits = 1;
     hipError_t e = gemm_launch(g, false, st);
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
-    if (B * C == 0) return ALIF_OK;
+    if (B == 0) return ALIF_OK;
     const int cg = C < RCG ? C : RCG;
     hipLaunchKernelGGL(k_readout_fwd, dim3((unsigned)B, (unsigned)((C + cg - 1) / cg)), dim3(RK * cg), 0, st, B, T,
                        C, dt_ms, tau_r, w.Ir, w.Vr, o);
@@ -248,9 +250,11 @@ int alif_readout_backward(int32_t B, int32_t T, int32_t n_hidden, int32_t C, dou
         return alif::set_error(ALIF_EINVAL, "bad readout sizes or dt");
     if (!spikes || !W_r || !tau_r || !go || !workspace)
         return alif::set_error(ALIF_EINVAL, "NULL readout argument");
+    if ((C + RCG - 1) / RCG > 65535)
+        return alif::set_error(ALIF_EUNSUPPORTED, "too many readout neurons (C / 32 must stay within 65535)");
     hipStream_t st = (hipStream_t)stream;
     RoWs w = ro_ws(workspace, B, T, C);
-    if (B * C > 0) {
+    if (B > 0) {
         const int cg = C < RCG ? C : RCG;
         hipLaunchKernelGGL(k_readout_bwd, dim3((unsigned)B, (unsigned)((C + cg - 1) / cg)), dim3(RK * cg), 0, st, B,
                            T, C, dt_ms, tau_r, w.Ir, w.Vr, go, w.gIr, w.part);

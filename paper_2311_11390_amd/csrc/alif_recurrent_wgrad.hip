@@ -333,7 +333,9 @@ Plan plan(int B, int T, int N, int D) {
     long long S = (8192 + (long long)N * NIS - 1) / ((long long)N * NIS);
     if (S > QG) S = QG;
     if (S < (QG + WIN - 1) / WIN) S = (QG + WIN - 1) / WIN;
-    p.ok = N > 0 && Q < (1LL << 30) && NIS <= 65535 && S <= 65535 && 64LL * N * 4 < (1LL << 31);
+    // (grid limits: NIS and S as reduce's y and z, N / 64 as mask's y, N / 16 as sum's)
+    p.ok = N > 0 && Q < (1LL << 30) && NIS <= 65535 && S <= 65535 && 64LL * N * 4 < (1LL << 31) &&
+           (N + 15) / 16 <= 65535;
     if (!p.ok) return p;
     p.NC = (int)NC; p.Q = (int)Q; p.Q16 = (int)((Q + QC - 1) / QC); p.QG = (int)QG;
     p.QP = QG * GQ;
