@@ -278,13 +278,22 @@ int alif_forward(const alif_desc *desc, const alif_params *prm,
  *            each nullable (= 0)
  *   grad_current  device float [B][T][N]: gradient w.r.t. I~ (the input current);
  *            required when grad_W or grad_input (spike input) is requested,
- *            otherwise nullable
+ *            otherwise nullable. Exception: with BF16 GEMMs, the blocks
+ *            algorithm, the detached policy, no grad_v / grad_theta and
+ *            n_neurons a multiple of 8 it may be NULL; the block backward then
+ *            writes the gradient as bfloat16 (round to nearest even, the
+ *            rounding the BF16 GEMMs apply to it) into the workspace, and
+ *            grad_W and grad_input are bit for bit the same as with a float
+ *            grad_current, at half its bytes and with no conversion in the
+ *            GEMMs
  *   grad_input    spike input only: device float [B][T][n_in] = grad_current W;
  *            nullable. (For current input the gradient is grad_current.)
  *   grad_W        device float [N][n_in] = sum_{b,t} grad_current^T x; nullable
  *   grad_bias, grad_tau_mem, grad_tau_adapt, grad_d, grad_theta0
  *            device float [N], summed over the batch; each nullable
- *   workspace device scratch of alif_backward_workspace_bytes() bytes
+ *   workspace device scratch of alif_backward_workspace_bytes() bytes (with
+ *            spike input and BF16 GEMMs it includes 2 B T N bytes for the
+ *            bfloat16 gradient above)
  * desc->grad_policy ALIF_GRAD_ATTACHED keeps the spike's reset and adaptation uses
  * in the gradient (supplementary "Detaching gradients"): the block backward then
  * composes the per-step adjoint as 2 x 2 affine maps of (lambda_V, lambda_a) in
@@ -312,9 +321,10 @@ int alif_backward(const alif_desc *desc, const alif_params *prm,
  * lives in a static device array of ALIF_NOALLOC_SCRATCH_BYTES inside the library,
  * one per device, held until the process ends. This call allocates nothing: no
  * hipMalloc, hipFree or allocating library routine. A problem whose scratch
- * exceeds the array (alif_backward_workspace_bytes without the GEMM part, unless
- * grad_W is requested) is rejected with ALIF_EUNSUPPORTED before any work is
- * queued. Every call on one device shares that device's array and leaves the
+ * exceeds the array (the parts of alif_backward_workspace_bytes the call uses:
+ * the partial sums, the GEMM split tiles with grad_W, the rounded W with BF16
+ * grad_input, the bfloat16 gradient without grad_current) is rejected with
+ * ALIF_EUNSUPPORTED before any work is queued. Every call on one device shares that device's array and leaves the
  * last call's contents in it, so calls that overlap on one device (on different
  * streams, or from different threads) race and give wrong gradients; serialise
  * them on one stream. Each call writes every scratch byte it reads, so nothing

@@ -144,14 +144,21 @@ def backward(fwd: dict, inp: torch.Tensor, params: Params, W: torch.Tensor | Non
              noalloc=False) -> dict:
     """Surrogate-gradient backward (alif_backward) of a ``forward(..., save=True)``.
     ``noalloc`` calls alif_backward_noalloc instead, whose scratch is the library's
-    static device array (no workspace is allocated or passed)."""
+    static device array (no workspace is allocated or passed). ``grad_current`` is
+    returned when asked for, and for spike input whenever grad_W or grad_input is,
+    except under BF16 GEMMs with the detached block backward and a multiple of 8
+    neurons (then None)."""
     desc = fwd["desc"]
     B, T, N = desc.batch, desc.T, desc.n_neurons
     dev = inp.device
     spikes_in = W is not None
     f32 = lambda *s: torch.empty(*s, dtype=torch.float32, device=dev)
-    g_cur = f32(B, T, N) if (want_grad_current or want_grad_W or (spikes_in and want_grad_input) or
-                             (not spikes_in and want_grad_input)) else None
+    # With BF16 GEMMs the detached block backward keeps dL/dI as bfloat16 in its
+    # workspace for dW and dx when no float copy is asked for (the GEMMs round it so).
+    gi16 = (spikes_in and not want_grad_current and (want_grad_W or want_grad_input) and
+            desc.gemm_precision == L.GEMM_BF16 and desc.algo == L.ALGO_BLOCKS and
+            desc.grad_policy != L.GRAD_ATTACHED and grad_v is None and grad_theta is None and N % 8 == 0)
+    g_cur = f32(B, T, N) if (want_grad_current or want_grad_W or want_grad_input) and not gi16 else None
     g_in = f32(B, T, desc.n_in) if (spikes_in and want_grad_input) else None
     g_W = f32(N, desc.n_in) if (spikes_in and want_grad_W) else None
     pg = {k: f32(N) for k in ("bias", "tau_mem", "tau_adapt", "d", "theta0")} if want_param_grads else {}

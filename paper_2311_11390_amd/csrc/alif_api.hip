@@ -188,18 +188,29 @@ namespace alif {
 int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
 // Backward workspace: FP64 partial sums [5][B][N]; for spike input the weight-gradient
 // GEMM's split partials; with BF16 GEMMs, W transposed and rounded to bfloat16 once
-// for the input gradient.
+// for the input gradient, then the input-current gradient as bfloat16 [B][T][N] for
+// a call that passes no grad_current.
 struct BwdWs {
-    size_t part, gemm, wt, total;
+    size_t part, gemm, wt, gi16, total;
 };
 BwdWs bwd_ws_layout(const alif_desc *desc, const Prob &p) {
     BwdWs w;
     w.part = 0;
     w.gemm = align256((size_t)5 * p.B * p.N * sizeof(double));
     w.wt = w.gemm + (p.spikes_in ? align256(gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.n_in)) : 0);
-    const bool wt = p.spikes_in && desc->gemm_precision == ALIF_GEMM_BF16;
-    w.total = w.wt + (wt ? align256(gemm_wbf16_bytes(p.N, p.n_in)) : 0);
+    const bool bf = p.spikes_in && desc->gemm_precision == ALIF_GEMM_BF16;
+    w.gi16 = w.wt + (bf ? align256(gemm_wbf16_bytes(p.N, p.n_in)) : 0);
+    w.total = w.gi16 + (bf ? align256((size_t)p.B * p.T * p.N * 2) : 0);
     return w;
+}
+// Whether a backward call keeps the input-current gradient as bfloat16 in its
+// workspace: spike input, BF16 GEMMs, the detached block backward, no gV / gTheta,
+// the projections' gradients asked for and no grad_current to fill. N % 8 == 0
+// keeps the bfloat16 rows 16-byte aligned, so the GEMMs take the same kernels as
+// from a float gI (and give the same bits).
+bool bwd_gi16(const alif_desc *desc, const Prob &p, bool grad_current, bool grad_vt, bool proj) {
+    return p.spikes_in && desc->gemm_precision == ALIF_GEMM_BF16 && desc->algo == ALIF_ALGO_BLOCKS &&
+           desc->grad_policy != ALIF_GRAD_ATTACHED && !grad_vt && proj && !grad_current && p.N % 8 == 0;
 }
 
 }  // namespace alif
@@ -427,10 +438,13 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
         return ALIF_OK;
     }
     if (!input || !carries || !workspace) return fail(ALIF_EINVAL, "input, carries and workspace are required");
+    const bool gi16 = bwd_gi16(desc, p, grad_current != nullptr, grad_v || grad_theta, grad_W || grad_input);
     if (p.spikes_in) {
         if (!current || !W) return fail(ALIF_EINVAL, "spike input: pass W and the current workspace alif_forward filled");
-        if ((grad_W || grad_input) && !grad_current)
-            return fail(ALIF_EINVAL, "grad_W / grad_input need the grad_current buffer");
+        if ((grad_W || grad_input) && !grad_current && !gi16)
+            return fail(ALIF_EINVAL, "grad_W / grad_input need the grad_current buffer (it may be NULL only with "
+                                     "BF16 GEMMs, the detached block backward, no grad_v / grad_theta and a "
+                                     "multiple of 8 neurons)");
     } else {
         if (grad_input || grad_W) return fail(ALIF_EINVAL, "current input: its gradient is grad_current");
     }
@@ -455,6 +469,7 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
         a.ck = carry_view(const_cast<void *>(carries), p);
         a.gS = grad_spikes; a.gV = grad_v; a.gTH = grad_theta;
         a.gI = grad_current;
+        a.gI16 = gi16 ? reinterpret_cast<uint16_t *>((char *)workspace + bwd_ws_layout(desc, p).gi16) : nullptr;
         a.part = part;
         e = launch_blocks_bwd(a, st);
         if (e != hipSuccess) return hip_fail(e, "block backward launch");
@@ -490,15 +505,16 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
         in.ptr = input;
         const BwdWs lay = bwd_ws_layout(desc, p);
         void *gws = (char *)workspace + lay.gemm;
+        const void *gI = gi16 ? (const void *)((char *)workspace + lay.gi16) : (const void *)grad_current;
         if (grad_W) {
-            e = gemm_weight_grad((size_t)p.B * p.T, p.N, p.n_in, grad_current, in, grad_W,
-                                 desc->gemm_precision == ALIF_GEMM_BF16, gws, st);
+            e = gemm_weight_grad((size_t)p.B * p.T, p.N, p.n_in, gI, in, grad_W,
+                                 desc->gemm_precision == ALIF_GEMM_BF16, gws, st, nullptr, 0, gi16);
             if (e != hipSuccess) return hip_fail(e, "weight-gradient GEMM");
         }
         if (grad_input) {
-            e = gemm_input_grad((size_t)p.B * p.T, p.N, p.n_in, grad_current, W, grad_input,
+            e = gemm_input_grad((size_t)p.B * p.T, p.N, p.n_in, gI, W, grad_input,
                                 desc->gemm_precision == ALIF_GEMM_BF16, st, (char *)workspace + lay.wt,
-                                lay.total - lay.wt);
+                                lay.gi16 - lay.wt, gi16);
             if (e != hipSuccess) return hip_fail(e, "input-gradient GEMM");
         }
     }
@@ -513,10 +529,13 @@ int alif_backward_noalloc(const alif_desc *desc, const alif_params *prm, const v
     Prob p;
     int rc = check_desc(desc, &p);
     if (rc) return rc;
-    // the scratch alif_backward would take as its workspace: the partial sums, and
-    // the split-K tiles only when the weight gradient is asked for
+    // the scratch alif_backward would take as its workspace: the partial sums, the
+    // split-K tiles only when the weight gradient is asked for, the rounded W^T only
+    // for the input gradient, the bfloat16 gI only when it stands in for grad_current
     const BwdWs lay = bwd_ws_layout(desc, p);
-    const size_t need = (grad_input && lay.total > lay.wt) ? lay.total : (grad_W ? lay.wt : lay.gemm);
+    size_t need = grad_W ? lay.wt : lay.gemm;
+    if (grad_input && lay.gi16 > lay.wt) need = lay.gi16;   // W transposed and rounded
+    if (bwd_gi16(desc, p, grad_current != nullptr, grad_v || grad_theta, grad_W || grad_input)) need = lay.total;
     if (need > (size_t)ALIF_NOALLOC_SCRATCH_BYTES)
         return fail(ALIF_EUNSUPPORTED,
                     "alif_backward_noalloc: this problem needs %zu bytes of scratch, more than the %u-byte "

@@ -532,7 +532,16 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_fwd(FwdArgs a) {
 // affine map (lam_start = R + M lam_in) in LDS, and every wave composes the
 // maps from the block end (Horner) to get its own incoming lambda and the
 // block's lambda at step 1 (the carry to the previous block).
-template <int SEG, int L, bool EVEN, int DEPTH, bool GVT, bool GI, int SG>
+// The input-current gradient out of the backward: GI = 1 float, GI = 2 bfloat16
+// (rounded to nearest even, the rounding the BF16 GEMMs apply to it) at half the
+// byte offset; an out-of-range offset stays out of range.
+template <int GI>
+__device__ __forceinline__ void st_gi(rsrc_t r, uint32_t off4, float v) {
+    if constexpr (GI == 1) st_f32(r, off4, v);
+    else st_u16(r, (off4 >> 1) | (off4 & ALIF_OOB), __builtin_bit_cast(uint16_t, (__bf16)v));
+}
+
+template <int SEG, int L, bool EVEN, int DEPTH, bool GVT, int GI, int SG>
 __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     constexpr int NWG = Geo<SEG>::NWG;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -554,7 +563,8 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
     const rsrc_t rGS = make_rsrc(a.gS ? a.gS + b * TN : nullptr, a.gS ? (uint32_t)(TN * 4) : 0u);
     const rsrc_t rGV = make_rsrc(a.gV ? a.gV + b * TN : nullptr, a.gV ? (uint32_t)(TN * 4) : 0u);
     const rsrc_t rGT = make_rsrc(a.gTH ? a.gTH + b * TN : nullptr, a.gTH ? (uint32_t)(TN * 4) : 0u);
-    const rsrc_t rGI = make_rsrc(a.gI ? a.gI + b * TN : nullptr, a.gI ? (uint32_t)(TN * 4) : 0u);
+    const rsrc_t rGI = GI == 2 ? make_rsrc(a.gI16 + b * TN, (uint32_t)(TN * 2))
+                                : make_rsrc(a.gI ? a.gI + b * TN : nullptr, a.gI ? (uint32_t)(TN * 4) : 0u);
     const size_t CN = (size_t)(a.NB + 1) * N;   // carry-in of every block, then the final carry
     const rsrc_t rCv = make_rsrc(a.ck.v + b * CN, (uint32_t)(CN * 4));
     const rsrc_t rCa = make_rsrc(a.ck.a + b * CN, (uint32_t)(CN * 4));
@@ -825,7 +835,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
                     if (k == 0) lA0 = lA;
                     else qp = fmaf(c.pt[k > 0 ? k - 1 : 0], lA, qp);
                     pth += lt[k];
-                    if constexpr (GI) st_f32(rGI, c.off(k, bo), c.omb * lV);
+                    if constexpr (GI != 0) st_gi<GI>(rGI, c.off(k, bo), c.omb * lV);
                 }
                 pb = fmaf(-bias, slV, pb);
                 pp = c.dd * fmaf(a1, qp, aprev0 * lA0);
@@ -850,7 +860,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
                     pdd = fmaf(ak[k], lt[k], pdd);
                     pth += lt[k];
                     sglV += glV;
-                    if constexpr (GI) st_f32(rGI, c.off(k, bo), c.omb * glV);
+                    if constexpr (GI != 0) st_gi<GI>(rGI, c.off(k, bo), c.omb * glV);
                 }
                 pp *= c.dd;
                 pbias = c.omb * sglV;
@@ -883,7 +893,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
                     if (k == 0) lA0 = lA;
                     else qp = fmaf(c.pt[k > 0 ? k - 1 : 0], lA, qp);
                     pth += ltk;
-                    if constexpr (GI) st_f32(rGI, c.off(k, bo), c.omb * lV);
+                    if constexpr (GI != 0) st_gi<GI>(rGI, c.off(k, bo), c.omb * lV);
                 }
                 pb = fmaf(-bias, slV, pb);
                 pp = c.dd * fmaf(a1, qp, aprev0 * lA0);
@@ -938,7 +948,7 @@ __global__ __launch_bounds__(Geo<SEG>::THREADS) void k_blocks_bwd(BwdArgs a) {
                     pdd = fmaf(ak_c, ltk, pdd);
                     pth += ltk;
                     sglV += glV;
-                    if constexpr (GI) st_f32(rGI, c.off(k, bo), c.omb * glV);
+                    if constexpr (GI != 0) st_gi<GI>(rGI, c.off(k, bo), c.omb * glV);
                     ak_c = aprev;
                 }
                 pp *= c.dd;
@@ -1387,7 +1397,8 @@ hipError_t blocks_bwd_launch(const BwdArgs &a, hipStream_t st) {
         return hipGetLastError();
     }
     const size_t sm = bwd_smem_bytes<SEG, L>(a.TR);
-    const bool gvt = a.gV || a.gTH, gi = a.gI != nullptr;
+    const bool gvt = a.gV || a.gTH;
+    const int gi = a.gI ? 1 : (a.gI16 ? 2 : 0);   // (a bfloat16 gI comes without gV / gTH)
 #define ALIF_LB3(G1, G2, SG)                                                                      \
     do {                                                                                          \
         if (a.TR == SEG * L)                                                                      \
@@ -1403,8 +1414,8 @@ hipError_t blocks_bwd_launch(const BwdArgs &a, hipStream_t st) {
         else if (a.surrogate == 2) ALIF_LB3(G1, G2, 2);                                           \
         else ALIF_LB3(G1, G2, 0);                                                                 \
     } while (0)
-    if (gvt) { if (gi) ALIF_LB(true, true); else ALIF_LB(true, false); }
-    else { if (gi) ALIF_LB(false, true); else ALIF_LB(false, false); }
+    if (gvt) { if (gi == 1) ALIF_LB(true, 1); else ALIF_LB(true, 0); }
+    else { if (gi == 1) ALIF_LB(false, 1); else if (gi == 2) ALIF_LB(false, 2); else ALIF_LB(false, 0); }
 #undef ALIF_LB
 #undef ALIF_LB3
     return hipGetLastError();

@@ -23,14 +23,17 @@ hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, 
 // rows padded to 16 bytes
 size_t gemm_wbf16_bytes(int N, int K);
 // gW[N][K] = sum_m gI[m][n] x[m][k]   (split over m, reduced in a fixed order);
-// skip_cnt / skip_le: the device-side gate of GemmArgs
-hipError_t gemm_weight_grad(size_t M, int N, int K, const float *gI, GemmIn x, float *gW, bool bf16,
+// skip_cnt / skip_le: the device-side gate of GemmArgs. gI is float, or bfloat16
+// with gi_bf16 (then bf16 must be set: the product is the BF16 one).
+hipError_t gemm_weight_grad(size_t M, int N, int K, const void *gI, GemmIn x, float *gW, bool bf16,
                             void *ws, hipStream_t st, const unsigned long long *skip_cnt = nullptr,
-                            unsigned long long skip_le = 0);
+                            unsigned long long skip_le = 0, bool gi_bf16 = false);
 // gx[M][K] = gI[M][N] . W[N][K]. With bf16, a scratch of gemm_wbf16_bytes(N, K)
-// bytes (as above) receives W transposed and rounded to bfloat16 once.
-hipError_t gemm_input_grad(size_t M, int N, int K, const float *gI, const float *W, float *gx,
-                           bool bf16, hipStream_t st, void *scratch = nullptr, size_t scratch_bytes = 0);
+// bytes (as above) receives W transposed and rounded to bfloat16 once. gI as in
+// gemm_weight_grad.
+hipError_t gemm_input_grad(size_t M, int N, int K, const void *gI, const float *W, float *gx,
+                           bool bf16, hipStream_t st, void *scratch = nullptr, size_t scratch_bytes = 0,
+                           bool gi_bf16 = false);
 // scratch bytes gemm_weight_grad needs for its split partial sums
 size_t gemm_workspace_bytes(size_t M, int N, int K);
 

@@ -522,8 +522,8 @@ static int tiled_kps(const GemmArgs &g, int bk) {
 // rows and bases aligned for its vector loads, every buffer extent within 31 bits
 static bool tiled_ok(const GemmArgs &g, bool bf16) {
     const bool fwd = g.a_kc && g.b_kc && g.b_dt == 0;
-    const bool dx = g.a_kc && g.a_dt == 0 && !g.b_kc && g.b_dt == 0;
-    const bool dw = !g.a_kc && g.a_dt == 0 && !g.b_kc;
+    const bool dx = g.a_kc && (g.a_dt == 0 || g.a_dt == 2) && !g.b_kc && g.b_dt == 0;
+    const bool dw = !g.a_kc && (g.a_dt == 0 || g.a_dt == 2) && !g.b_kc;
     if (!(fwd || dx || dw) || g.K <= 0) return false;
     if ((reinterpret_cast<uintptr_t>(g.A) & 15) || (reinterpret_cast<uintptr_t>(g.B) & 15)) return false;
     if (g.lda % 4 != 0 || g.ldb % 4 != 0) return false;
@@ -561,7 +561,12 @@ static hipError_t tiled_launch(const GemmArgs &g, hipStream_t st, int *splits_ou
         else if (g.a_dt == 1) tiled_go<1, false, 0, false, BF16>(g, mt, n_tiles, kps, tt, st);
         else tiled_go<2, false, 0, false, BF16>(g, mt, n_tiles, kps, tt, st);
     } else if (g.a_kc) {
-        tiled_go<0, false, 0, true, BF16>(g, mt, n_tiles, kps, tt, st);
+        if (g.a_dt == 2) tiled_go<2, false, 0, true, BF16>(g, mt, n_tiles, kps, tt, st);
+        else tiled_go<0, false, 0, true, BF16>(g, mt, n_tiles, kps, tt, st);
+    } else if (g.a_dt == 2) {
+        if (g.b_dt == 0) tiled_go<2, true, 0, true, BF16>(g, mt, n_tiles, kps, tt, st);
+        else if (g.b_dt == 1) tiled_go<2, true, 1, true, BF16>(g, mt, n_tiles, kps, tt, st);
+        else tiled_go<2, true, 2, true, BF16>(g, mt, n_tiles, kps, tt, st);
     } else {
         if (g.b_dt == 0) tiled_go<0, true, 0, true, BF16>(g, mt, n_tiles, kps, tt, st);
         else if (g.b_dt == 1) tiled_go<0, true, 1, true, BF16>(g, mt, n_tiles, kps, tt, st);
@@ -683,13 +688,13 @@ size_t gemm_workspace_bytes(size_t M, int N, int K) {
     return s > 1 ? (size_t)s * N * K * sizeof(float) : 0;
 }
 
-hipError_t gemm_weight_grad(size_t M, int N, int K, const float *gI, GemmIn x, float *gW, bool bf16,
+hipError_t gemm_weight_grad(size_t M, int N, int K, const void *gI, GemmIn x, float *gW, bool bf16,
                             void *ws, hipStream_t st, const unsigned long long *skip_cnt,
-                            unsigned long long skip_le) {
+                            unsigned long long skip_le, bool gi_bf16) {
     // C[n][k] = sum_m gI[m][n] x[m][k]: reduction over m (split), both operands m-major
     GemmArgs g{};
     g.M = N; g.N = K; g.K = (int)M;
-    g.A = gI; g.a_dt = 0; g.lda = N; g.a_kc = 0;
+    g.A = gI; g.a_dt = gi_bf16 ? 2 : 0; g.lda = N; g.a_kc = 0;
     g.B = x.ptr; g.b_dt = dt_of(x.kind); g.ldb = K; g.b_kc = 0;
     g.C = gW; g.ldc = K; g.bias = nullptr;
     g.splits = wgrad_splits(M, N, K);
@@ -700,12 +705,12 @@ hipError_t gemm_weight_grad(size_t M, int N, int K, const float *gI, GemmIn x, f
     return gemm_launch(g, bf16, st);
 }
 
-hipError_t gemm_input_grad(size_t M, int N, int K, const float *gI, const float *W, float *gx,
-                           bool bf16, hipStream_t st, void *scratch, size_t scratch_bytes) {
+hipError_t gemm_input_grad(size_t M, int N, int K, const void *gI, const float *W, float *gx,
+                           bool bf16, hipStream_t st, void *scratch, size_t scratch_bytes, bool gi_bf16) {
     // C[m][k] = sum_n gI[m][n] W[n][k]
     GemmArgs g{};
     g.M = (long long)M; g.N = K; g.K = N;
-    g.A = gI; g.a_dt = 0; g.lda = N; g.a_kc = 1;
+    g.A = gI; g.a_dt = gi_bf16 ? 2 : 0; g.lda = N; g.a_kc = 1;
     g.B = W; g.b_dt = 0; g.ldb = K; g.b_kc = 0;
     g.C = gx; g.ldc = K; g.bias = nullptr; g.splits = 1;
     if (bf16 && M > 0 && K > 0 && scratch_fits(scratch, scratch_bytes, N, K)) {

@@ -414,7 +414,7 @@ bool gemm_big_ok(const GemmArgs &g) {
     if (g.M < TM || g.N < TN || g.K < TK) return false;
     const bool fwd = g.a_kc && g.b_kc && (g.b_dt == 0 || g.b_dt == 2);
     const bool dx = g.a_kc && g.a_dt == 0 && !g.b_kc && g.b_dt == 0;
-    const bool dw = !g.a_kc && g.a_dt == 0 && !g.b_kc;
+    const bool dw = !g.a_kc && (g.a_dt == 0 || g.a_dt == 2) && !g.b_kc;
     if (!(fwd || dx || dw)) return false;
     if (!aligned_for(g.a_dt, g.A, g.lda) || !aligned_for(g.b_dt, g.B, g.ldb)) return false;
     if (!g.a_kc && g.lda < g.M) return false;
@@ -459,6 +459,10 @@ hipError_t gemm_big_launch(const GemmArgs &g, hipStream_t st) {
         else e = go<2, false, 2, false>(ba, st);
     } else if (g.a_kc) {
         e = go<0, false, 0, true>(ba, st);
+    } else if (g.a_dt == 2) {   // the weight gradient from a bfloat16 input-current gradient
+        if (g.b_dt == 1) e = go<2, true, 1, true>(ba, st);
+        else if (g.b_dt == 2) e = go<2, true, 2, true>(ba, st);
+        else e = go<2, true, 0, true>(ba, st);
     } else {
         if (g.b_dt == 0) e = go<0, true, 0, true>(ba, st);
         else if (g.b_dt == 1) e = go<0, true, 1, true>(ba, st);

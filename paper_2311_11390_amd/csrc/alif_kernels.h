@@ -59,6 +59,8 @@ struct BwdArgs {
     CarryView ck;
     const float *gS, *gV, *gTH;
     float *gI;
+    uint16_t *gI16;  // the same gradient as bfloat16 (round to nearest even), in place of gI
+                     // (detached policy, no gV / gTH); nullptr: none
     double *part;  // [5][B][N]
 };
 

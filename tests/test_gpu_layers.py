@@ -112,15 +112,19 @@ def test_input_grad_gemm(prec, shape):
 
 
 @pytest.mark.parametrize("kind", ["u8", "bf16"])
-@pytest.mark.parametrize("shape", [(2, 301, 300, 260), (1, 700, 1024, 512)])
+@pytest.mark.parametrize("shape", [(2, 301, 300, 260), (1, 700, 1024, 512), (2, 301, 300, 264), (2, 37, 48, 32),
+                                   (2, 37, 50, 40)])
 def test_bf16_layer_gemms_with_weight_copies(kind, shape):
     """A spike-input layer with BF16 GEMMs through alif_forward / alif_backward, at
-    shapes the large-tile kernel takes (ragged tiles and k). The forward rounds W to
-    bfloat16 once into the spike output before the block kernel fills it; the
-    backward's input gradient uses W transposed and rounded into its workspace.
-    The current and dL/dx against the oracle's FP64 products of the same rounded
-    operands, within the FP32 accumulation bound; the layer's spikes equal those of
-    the same layer fed the oracle-checked current."""
+    shapes the large-tile kernel takes (ragged tiles and k) and small ones that take
+    the tiled and the plain GEMM. The forward rounds W to bfloat16 once into the
+    spike output before the block kernel fills it; the backward's input gradient
+    uses W transposed and rounded into its workspace. The current and dL/dx against
+    the oracle's FP64 products of the same rounded operands, within the FP32
+    accumulation bound; the layer's spikes equal those of the same layer fed the
+    oracle-checked current. With a multiple of 8 neurons, the backward without a
+    float grad_current (dL/dI kept as bfloat16 in the workspace) gives the same
+    bits for every gradient."""
     import torch
     from paper_2311_11390_amd import _lib as L
     from paper_2311_11390_amd import alif
@@ -135,7 +139,8 @@ def test_bf16_layer_gemms_with_weight_copies(kind, shape):
     P = to_dev(prm)
     f = alif.forward(xt, P, 0.5, 2.0, Wt, gemm_precision=L.GEMM_BF16, save=True)
     gS = torch.as_tensor(g.standard_normal((B, T, N)).astype(np.float32), device="cuda")
-    out = alif.backward(f, xt, P, Wt, grad_spikes=gS, want_grad_input=True, want_grad_W=True)
+    out = alif.backward(f, xt, P, Wt, grad_spikes=gS, want_grad_current=True, want_grad_input=True,
+                        want_grad_W=True)
     torch.cuda.synchronize()
     Wr = _bf16_round(W)
     cur = np_(f["current"])
@@ -159,6 +164,11 @@ def test_bf16_layer_gemms_with_weight_copies(kind, shape):
     wbound = _gemm_bound(gr.reshape(-1, N).T, x.reshape(-1, n_in).astype(np.float64), B * T)
     werr = np.abs(np_(out["grad_W"]) - wref)
     assert (werr <= wbound).all(), float((werr / wbound).max())
+    out16 = alif.backward(f, xt, P, Wt, grad_spikes=gS, want_grad_input=True, want_grad_W=True)
+    torch.cuda.synchronize()
+    assert (out16["grad_current"] is None) == (N % 8 == 0)
+    for k in ("grad_W", "grad_input", "grad_tau_mem", "grad_tau_adapt", "grad_d", "grad_theta0", "grad_bias"):
+        assert np.array_equal(np_(out16[k]).view(np.uint32), np_(out[k]).view(np.uint32)), k
 
 
 @pytest.mark.parametrize("shape", [(1, 530, 96, 300), (3, 211, 256, 260), (1, 257, 72, 1024)])
