@@ -322,6 +322,47 @@ def test_three_layer_sampled_batch_weight_grads():
     log(f"[report] three-layer B=4 gradients: max rel L2 {max(e['rel_l2'] for e in errs):.1e} (bound {GRAD_TOL})")
 
 
+def test_three_layer_bf16_gradients_without_float_dI_full_size():
+    """The three-layer training step with BF16 GEMMs at its full size (B 128,
+    T 2000), each layer's backward run twice in the bench's launch configuration:
+    with a float dL/dI and without one (bfloat16 in the workspace for the two
+    1024-neuron layers; the 20-neuron layer keeps the float path). grad_W,
+    grad_input and the parameter gradients agree bit for bit."""
+    import torch
+
+    from paper_2311_11390_amd import _lib as L
+    from paper_2311_11390_amd import alif
+    from paper_2311_11390_amd.synth import three_layer
+    w = three_layer(seed=4, driven=True)
+    x, Ws, lps = w.inputs["x"], w.weights, w.layers
+    log("[full] three-layer BF16 backward with and without a float dL/dI")
+    h = torch.as_tensor(x, device="cuda")
+    fs, ins, Ps, Wts = [], [], [], []
+    for W, lp in zip(Ws, lps):
+        Wt = torch.as_tensor(W, device="cuda")
+        P = to_dev(lp)
+        f = alif.forward(h, P, w.dt, w.arp, Wt, gemm_precision=L.GEMM_BF16, spike_dtype=L.SPIKES_U8, save=True)
+        fs.append(f)
+        ins.append(h)
+        Ps.append(P)
+        Wts.append(Wt)
+        h = f["spikes"]
+    g = torch.ones(h.shape, dtype=torch.float32, device="cuda")
+    keys = ("grad_W", "grad_input", "grad_tau_mem", "grad_tau_adapt", "grad_d", "grad_theta0", "grad_bias")
+    for li in reversed(range(len(Ws))):
+        kw = dict(grad_spikes=g, want_grad_input=li > 0, want_grad_W=True)
+        a = alif.backward(fs[li], ins[li], Ps[li], Wts[li], want_grad_current=True, **kw)
+        b = alif.backward(fs[li], ins[li], Ps[li], Wts[li], **kw)
+        torch.cuda.synchronize()
+        assert (b["grad_current"] is None) == (Ws[li].shape[0] % 8 == 0)
+        for k in keys:
+            if a[k] is not None:
+                assert torch.equal(a[k].view(torch.int32), b[k].view(torch.int32)), (li, k)
+        assert a["grad_W"].abs().max().item() > 0
+        g = a["grad_input"] if li > 0 else None
+        del a, b
+
+
 def test_serving_requests_full_size():
     """The first four requests of the serving stream at their real sizes (up to
     1920 neurons x 42942 steps, DT 1 / 0.05 / 0.1 ms), served concurrently,
