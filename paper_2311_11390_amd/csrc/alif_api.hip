@@ -187,17 +187,19 @@ SeqCarryView seq_carry_view(void *base, size_t cn) {
 namespace alif {
 int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
 // Backward workspace: FP64 partial sums [5][B][N]; for spike input the weight-gradient
-// GEMM's split partials; with BF16 GEMMs, W transposed and rounded to bfloat16 once
+// GEMM's split partials and the event path's count, masks and partials (both are
+// enqueued, one runs); with BF16 GEMMs, W transposed and rounded to bfloat16 once
 // for the input gradient, then the input-current gradient as bfloat16 [B][T][N] for
 // a call that passes no grad_current.
 struct BwdWs {
-    size_t part, gemm, wt, gi16, total;
+    size_t part, gemm, wgev, wt, gi16, total;
 };
 BwdWs bwd_ws_layout(const alif_desc *desc, const Prob &p) {
     BwdWs w;
     w.part = 0;
     w.gemm = align256((size_t)5 * p.B * p.N * sizeof(double));
-    w.wt = w.gemm + (p.spikes_in ? align256(gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.n_in)) : 0);
+    w.wgev = w.gemm + (p.spikes_in ? align256(gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.n_in)) : 0);
+    w.wt = w.wgev + (p.spikes_in ? align256(wgrad_event_bytes(p.B, p.T, p.n_in, p.N)) : 0);
     const bool bf = p.spikes_in && desc->gemm_precision == ALIF_GEMM_BF16;
     w.gi16 = w.wt + (bf ? align256(gemm_wbf16_bytes(p.N, p.n_in)) : 0);
     w.total = w.gi16 + (bf ? align256((size_t)p.B * p.T * p.N * 2) : 0);
@@ -506,15 +508,23 @@ int alif_backward(const alif_desc *desc, const alif_params *prm, const void *inp
         const BwdWs lay = bwd_ws_layout(desc, p);
         void *gws = (char *)workspace + lay.gemm;
         const void *gI = gi16 ? (const void *)((char *)workspace + lay.gi16) : (const void *)grad_current;
+        const bool bf = desc->gemm_precision == ALIF_GEMM_BF16;
         if (grad_W) {
-            e = gemm_weight_grad((size_t)p.B * p.T, p.N, p.n_in, gI, in, grad_W,
-                                 desc->gemm_precision == ALIF_GEMM_BF16, gws, st, nullptr, 0, gi16);
+            // sparse input: dW summed over the active inputs (exact products, FP32 sums in a
+            // fixed order; gI rounded to bfloat16 as the BF16 GEMM rounds it); the dense GEMM
+            // behind it runs instead when the device-side count of active inputs is above
+            // one per 256 entries
+            unsigned long long *cnt = nullptr, thr = 0;
+            e = launch_wgrad_events(p.B, p.T, p.n_in, p.N, 0, desc->input_kind == ALIF_INPUT_SPIKES_U8 ? 1 : 2,
+                                    input, gI, gi16 ? 2 : (bf ? 1 : 0), grad_W, (char *)workspace + lay.wgev, &cnt,
+                                    &thr, st);
+            if (e != hipSuccess) return hip_fail(e, "weight-gradient event launch");
+            e = gemm_weight_grad((size_t)p.B * p.T, p.N, p.n_in, gI, in, grad_W, bf, gws, st, cnt, thr, gi16);
             if (e != hipSuccess) return hip_fail(e, "weight-gradient GEMM");
         }
         if (grad_input) {
-            e = gemm_input_grad((size_t)p.B * p.T, p.N, p.n_in, gI, W, grad_input,
-                                desc->gemm_precision == ALIF_GEMM_BF16, st, (char *)workspace + lay.wt,
-                                lay.gi16 - lay.wt, gi16);
+            e = gemm_input_grad((size_t)p.B * p.T, p.N, p.n_in, gI, W, grad_input, bf, st,
+                                (char *)workspace + lay.wt, lay.gi16 - lay.wt, gi16);
             if (e != hipSuccess) return hip_fail(e, "input-gradient GEMM");
         }
     }
@@ -579,7 +589,7 @@ RecLayout rec_layout(const alif_desc *d, const Prob &p) {
     // weight gradient: the event path's count, masks and partials; the dense path's
     // shifted spikes and GEMM partial sums from byte 256 on (over the masks: the
     // two never both run)
-    const size_t ev = recurrent_wgrad_event_bytes(p.B, p.T, p.N);
+    const size_t ev = wgrad_event_bytes(p.B, p.T, p.N, p.N);
     const size_t dense = 256 + align256((size_t)p.B * p.T * p.N * sb) +
                          gemm_workspace_bytes((size_t)p.B * p.T, p.N, p.N);
     const size_t wg = ev > dense ? ev : dense;
@@ -718,8 +728,8 @@ int alif_recurrent_weight_grad(const alif_desc *desc, int32_t delay, const float
     const int sb = spike_elem_bytes(desc->spike_dtype);
     // the event path, then the dense path gated on the event count it leaves
     unsigned long long *count = nullptr, thr = 0;
-    hipError_t e = launch_recurrent_wgrad_events(p.B, p.T, p.N, D, sb, spikes, grad_current, grad_W_rec, workspace,
-                                                 &count, &thr, st);
+    hipError_t e = launch_wgrad_events(p.B, p.T, p.N, p.N, D, sb, spikes, grad_current, 0, grad_W_rec, workspace,
+                                       &count, &thr, st);
     if (e != hipSuccess) return hip_fail(e, "recurrent weight-gradient event launch");
     const size_t shb = align256((size_t)p.B * p.T * p.N * sb);
     char *shifted = (char *)workspace + 256;

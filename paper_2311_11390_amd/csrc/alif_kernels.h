@@ -139,17 +139,19 @@ hipError_t launch_recurrent_events(int B, int TR, int rows, int N, long long bst
 bool recurrent_fused_ok(int N, int TR, int D);
 int recurrent_ring_slots(int TR, int D);
 hipError_t launch_recurrent_fused(const RecArgs &a, hipStream_t st);
-// The recurrent weight gradient from the spike events (dW[i][j] = sum over b and
-// u < T - D of S[b][u][j] gI[b][u + D][i]) into the workspace ws (256-byte
-// aligned, recurrent_wgrad_event_bytes(B, T, N) bytes, which bound every D >= 0).
-// It counts the events into a device word first and computes dW only when they
-// are few; *count and *thr (nullptr when the event path cannot take the shape)
-// give the gate of the dense path enqueued behind it: dense runs when
-// *count > *thr.
-size_t recurrent_wgrad_event_bytes(int B, int T, int N);
-hipError_t launch_recurrent_wgrad_events(int B, int T, int N, int D, int elem, const void *spikes, const float *gI,
-                                         float *dW, void *ws, unsigned long long **count,
-                                         unsigned long long *thr, hipStream_t st);
+// The weight gradient of a spike-driven projection from the spike events
+// (dW[i][j] = sum over b and u < T - D of S[b][u][j] gI[b][u + D][i], Nj spike
+// columns j, Ni gradient columns i; D = 0 for a feed-forward projection) into the
+// workspace ws (256-byte aligned, wgrad_event_bytes(B, T, Nj, Ni) bytes, which
+// bound every D >= 0). gI [B][T][Ni] is float (gi_mode 0), float rounded to
+// bfloat16 as it is read (1) or bfloat16 (2). It counts the events into a device
+// word first and computes dW only when they are few; *count and *thr (nullptr
+// when the event path cannot take the shape) give the gate of the dense path
+// enqueued behind it: dense runs when *count > *thr.
+size_t wgrad_event_bytes(int B, int T, int Nj, int Ni);
+hipError_t launch_wgrad_events(int B, int T, int Nj, int Ni, int D, int elem, const void *spikes, const void *gI,
+                               int gi_mode, float *dW, void *ws, unsigned long long **count, unsigned long long *thr,
+                               hipStream_t st);
 // out[j][i] = in[i][j], N x N float
 hipError_t launch_transpose(int N, const float *in, float *out, hipStream_t st);
 // out[b][t][i] = in[b][t - D][i] for t >= D, else 0 (elements of `elem` bytes); with

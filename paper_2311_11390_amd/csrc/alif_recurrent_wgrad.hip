@@ -1,9 +1,11 @@
-// Recurrent weight gradient from the spike events: the backward of the recurrent
-// current W_rec S[t - D] of Eq. 3 under the detached policy,
-//   dW_rec[i][j] = sum over b and u < T - D of S[b][u][j] gI[b][u + D][i].
-// A neuron fires at most once per T_R steps (Prop. 3), and at the rates of a fitted
-// network almost every spike row is zero: a dense GEMM spends N^2 multiply-adds on
-// each of the R = B (T - D) source rows for a handful of events. Three kernels:
+// Weight gradient of a spike-driven projection from the spike events: for the
+// recurrent current W_rec S[t - D] of Eq. 3 under the detached policy
+//   dW_rec[i][j] = sum over b and u < T - D of S[b][u][j] gI[b][u + D][i],
+// and with D = 0 for the feed-forward projection W x of spike input (Nj inputs j,
+// Ni neurons i). A neuron fires at most once per T_R steps (Prop. 3), and at the
+// rates of a fitted network almost every spike row is zero: a dense GEMM spends
+// Ni Nj multiply-adds on each of the R = B (T - D) source rows for a handful of
+// events. Three kernels:
 //   mask    reads S once: for chunk q = b NC + k (64 steps of one sequence, NC
 //           chunks a sequence) and column j, the bit mask of its nonzero steps
 //           (u64, bit r for step 64 k + r), stored only when nonzero, and one
@@ -14,11 +16,13 @@
 //           times gI row u + D into FP32 accumulators: a partial per segment.
 //   sum     dW_rec[i][j] = the segments' partials added in segment order.
 // Every sum runs in a fixed order, so the result does not depend on scheduling.
-// The event path reads E N gI values (one row per event) where the dense product
-// does 2 R N^2 flops over R N of them; above one event per 256 spike entries of
-// the source steps (E > R N / 256) the dense GEMM is the faster one, so reduce and
-// sum return at entry and the dense time shift + GEMM, enqueued behind them with
-// the same device-side test on E, run instead.
+// The event path reads E Ni gI values (one row per event) where the dense product
+// does 2 R Ni Nj flops over R Ni of them; above one event per 256 spike entries of
+// the source steps (E > R Nj / 256) the dense GEMM is the faster one, so reduce and
+// sum return at entry and the dense GEMM (after the time shift for D > 0),
+// enqueued behind them with the same device-side test on E, runs instead.
+// gI is float, float rounded to bfloat16 as it is loaded (the operand of a BF16
+// GEMM), or bfloat16.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -40,7 +44,7 @@ constexpr int ELIST = GQ * CH;    // the events of 64 listed chunks at most (u16
 constexpr int BATCH = 8;          // events whose gI rows are loaded together
 
 struct WgArgs {
-    int B, T, TD, N, D;
+    int B, T, TD, Nj, Ni, D;  // Nj spike columns j, Ni gradient columns i
     int NC;        // chunks a sequence, ceil(TD / CH)
     int Q;         // chunks, B NC
     int Q16;       // quarters, ceil(Q / QC)
@@ -48,16 +52,79 @@ struct WgArgs {
     long long QP;  // mask row length in chunks, QG GQ
     int SG, S;     // groups a segment, segments
     const void *spikes;
-    const float *gI;
+    const void *gI;          // [B][T][Ni] float or bfloat16
     unsigned long long *E;   // event count
     unsigned long long thr;  // this path runs when E <= thr
-    uint16_t *sum16;         // [Q16][N]: bit c set when chunk 16 k + c of column j has an event
-    uint64_t *mask;          // [N][QP]: written (and read) only where the summary bit is set
-    float *part;             // [S][N (j)][N (i)]
-    float *dW;               // [N (i)][N (j)]
+    uint16_t *sum16;         // [Q16][Nj]: bit c set when chunk 16 k + c of column j has an event
+    uint64_t *mask;          // [Nj][QP]: written (and read) only where the summary bit is set
+    float *part;             // [S][Nj][Ni]
+    float *dW;               // [Ni][Nj]
 };
 
+// The counting pass reads every spike byte, which a dense input would spend for
+// nothing. On inputs of more than DIRECT entries one workgroup first counts the
+// nonzero entries of whole source rows spaced evenly over the B (T - D) of them,
+// at least SROWS rows and at least SAMPLE entries: when the sample puts the
+// density above 1.1 / 256 (past the event path's one per 256; at the threshold
+// the cut is 1.6 standard deviations of the sampled count away, at 0.8 of it
+// 5.4) E is set to
+// SKIP, which turns the counting pass off and the dense path on; otherwise E
+// starts at 0 and the counting pass decides exactly. Smaller inputs are counted
+// exactly right away. Either way the result is the same product; only the time
+// differs.
+constexpr int SROWS = 64;
+constexpr long long SAMPLE = 65536;
+constexpr long long DIRECT = 1LL << 24;
+constexpr unsigned long long SKIP = ~0ull;
+
 __global__ void k_wg_zero(unsigned long long *E) { *E = 0; }
+
+// nonzero elements in a dword of ELEM-byte elements (the sign bit of a
+// floating-point element ignored: -0 is no event)
+template <int ELEM>
+__device__ __forceinline__ int nz_elems(uint32_t v) {
+    if constexpr (ELEM == 1) return __popc((((v | 0x80808080u) - 0x01010101u) | v) & 0x80808080u);
+    else if constexpr (ELEM == 2) return __popc(((v & 0x7fff7fffu) + 0x7fff7fffu) & 0x80008000u);
+    else return (v & 0x7fffffffu) != 0u;
+}
+
+template <int ELEM, bool VEC>
+__global__ __launch_bounds__(1024) void k_wg_sample(WgArgs a) {
+    __shared__ int part[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long R = (long long)a.B * a.TD;   // source rows
+    const long long want = SROWS > (SAMPLE + a.Nj - 1) / a.Nj ? SROWS : (SAMPLE + a.Nj - 1) / a.Nj;
+    const long long taken = R < want ? R : want;
+    int c = 0;
+#pragma unroll 4
+    for (long long k = wave; k < taken; k += 16) {   // (uniform per wave)
+        const long long r = k * R / taken;
+        const long long b = r / a.TD, u = r - b * a.TD;
+        const char *row = static_cast<const char *>(a.spikes) + ((size_t)b * a.T + (size_t)u) * a.Nj * ELEM;
+        if constexpr (VEC) {
+            const int words = a.Nj * ELEM / 4;
+#pragma unroll 4
+            for (int w = lane; w < words; w += 64) c += nz_elems<ELEM>(reinterpret_cast<const uint32_t *>(row)[w]);
+        } else {
+#pragma unroll 4
+            for (int j = lane; j < a.Nj; j += 64) {
+                uint32_t v;
+                if constexpr (ELEM == 1) v = reinterpret_cast<const uint8_t *>(row)[j];
+                else v = (uint32_t)reinterpret_cast<const uint16_t *>(row)[j];   // (unaligned float rows take VEC)
+                c += nz_elems<ELEM>(v);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane == 0) part[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long tot = 0;
+        for (int w = 0; w < 16; w++) tot += part[w];
+        *a.E = tot * 256 * 10 <= 11LL * taken * a.Nj ? 0ull : SKIP;
+    }
+}
 
 // Bit r of half[c] = (element c of v[r] != 0), for 32 rows. VEC: v holds a dword of
 // a row (4 bytes, 2 bfloat16 or 1 float); else one element in the low bits. The sign
@@ -113,10 +180,11 @@ template <int ELEM, bool VEC>
 __global__ __launch_bounds__(64 * MASK_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void k_wg_mask(WgArgs a) {
     constexpr int CPL = VEC ? 4 / ELEM : 1;
     __shared__ uint32_t other[64 * CPL];   // the second wave's summary bits
+    if (*a.E == SKIP) return;   // the sample found a dense input
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j0 = (blockIdx.y * 64 + lane) * CPL;
-    const uint32_t rowb = (uint32_t)a.N * ELEM;
-    const bool col_ok = j0 < a.N;
+    const uint32_t rowb = (uint32_t)a.Nj * ELEM;
+    const bool col_ok = j0 < a.Nj;
     unsigned long long cnt = 0;
     uint32_t sb[CPL];
 #pragma unroll
@@ -160,8 +228,8 @@ __global__ __launch_bounds__(64 * MASK_WAVES) __attribute__((amdgpu_waves_per_eu
     if (wave == 0)
 #pragma unroll
         for (int c = 0; c < CPL; c++)
-            if (j0 + c < a.N)
-                a.sum16[(size_t)blockIdx.x * a.N + j0 + c] = (uint16_t)(sb[c] | other[lane * CPL + c]);
+            if (j0 + c < a.Nj)
+                a.sum16[(size_t)blockIdx.x * a.Nj + j0 + c] = (uint16_t)(sb[c] | other[lane * CPL + c]);
     // event count: wave sum, one atomic a wave (integer: the total is exact)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
@@ -186,32 +254,52 @@ __device__ __forceinline__ float spike_value(const void *S, size_t idx) {
     else return static_cast<const float *>(S)[idx];
 }
 
+// Four consecutive gI values of a row at byte offset off (one 16-byte load of
+// floats, one 8-byte load of bfloat16): GI 0 float, 1 float rounded to bfloat16
+// (round to nearest even, as a BF16 GEMM rounds its operand), 2 bfloat16. The
+// range check drops whole dwords past the row's end, which read as zeros.
+template <int GI>
+__device__ __forceinline__ void ld_gi4(rsrc_t r, uint32_t off, float (&g)[4]) {
+    if constexpr (GI == 2) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            g[2 * c] = __uint_as_float((uint32_t)w[c] << 16);
+            g[2 * c + 1] = __uint_as_float((uint32_t)w[c] & 0xffff0000u);
+        }
+    } else {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            g[c] = __uint_as_float((uint32_t)w[c]);
+            if constexpr (GI == 1) g[c] = (float)(__bf16)g[c];
+        }
+    }
+}
+
 // One wave: column j = blockIdx.x, segment s = blockIdx.y (at most WIN groups = 64
-// quarters), rows i = 256 blockIdx.z + lane + 64 p (p < 4). The segment's summary
+// quarters), rows i = 256 blockIdx.z + 4 lane + c (c < 4). The segment's summary
 // words (lane = quarter) give the chunks with events, listed in order in LDS; their
 // masks are loaded 64 at a time (lane = listed chunk) and their set bits listed in
 // (chunk, step) order, which is step order; the event list is consumed BATCH events
 // at a time (first when 64 more chunks could overflow it, then at the end).
-template <int ELEM>
+template <int ELEM, int GI>
 __global__ __launch_bounds__(64) void k_wg_reduce(WgArgs a) {
     if (*a.E > a.thr) return;   // the dense path runs
+    constexpr uint32_t GB = GI == 2 ? 2u : 4u;   // bytes of a gI element
     __shared__ uint16_t clist[CLIST];   // chunk offsets from the segment's first chunk
     __shared__ uint16_t elist[ELIST];   // (chunk offset << 6) | step
     const int lane = threadIdx.x;
     const int j = blockIdx.x, s = blockIdx.y, i0 = blockIdx.z * 256;
-    uint32_t ioff[4];
-#pragma unroll
-    for (int p = 0; p < 4; p++) {
-        const int i = i0 + lane + 64 * p;
-        ioff[p] = i < a.N ? (uint32_t)i * 4u : ALIF_OOB;
-    }
+    const int ib = i0 + 4 * lane;
+    const uint32_t ioff = ib < a.Ni ? (uint32_t)ib * GB : ALIF_OOB;
     float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     const int g0 = s * a.SG;
     const int k0 = g0 * (GQ / QC), nq = min(a.SG * (GQ / QC), a.Q16 - k0);   // quarters (<= 64)
     const int qbase = g0 * GQ;                                                // first chunk
     const uint64_t *mrow = a.mask + (size_t)j * a.QP + qbase;
 
-    const uint32_t sm = lane < nq ? (uint32_t)a.sum16[(size_t)(k0 + lane) * a.N + j] : 0u;
+    const uint32_t sm = lane < nq ? (uint32_t)a.sum16[(size_t)(k0 + lane) * a.Nj + j] : 0u;
     if (__ballot(sm != 0u) != 0ull) {   // uniform
         const int c = __popc(sm);
         const int pre = wave_incl_scan(c, lane);
@@ -227,6 +315,7 @@ __global__ __launch_bounds__(64) void k_wg_reduce(WgArgs a) {
         }
         __syncthreads();
 
+        const char *gbase = static_cast<const char *>(a.gI);
         auto consume = [&](int count) {
             __syncthreads();   // the list entries are written
             for (int e0 = 0; e0 < count; e0 += BATCH) {
@@ -238,11 +327,10 @@ __global__ __launch_bounds__(64) void k_wg_reduce(WgArgs a) {
                     const int q = qbase + (int)(ent >> 6);
                     const int b = q / a.NC, k = q - b * a.NC;
                     const size_t srow = (size_t)b * a.T + (size_t)k * CH + (ent & 63u);
-                    const float sv = spike_value<ELEM>(a.spikes, srow * a.N + j);   // a valid entry's address
+                    const float sv = spike_value<ELEM>(a.spikes, srow * a.Nj + j);   // a valid entry's address
                     v[u] = ok ? sv : 0.0f;
-                    const rsrc_t rr = make_rsrc(a.gI + (srow + a.D) * a.N, ok ? (uint32_t)a.N * 4u : 0u);
-#pragma unroll
-                    for (int p = 0; p < 4; p++) g[u][p] = ld_f32(rr, ioff[p]);
+                    const rsrc_t rr = make_rsrc(gbase + (srow + a.D) * a.Ni * GB, ok ? (uint32_t)a.Ni * GB : 0u);
+                    ld_gi4<GI>(rr, ioff, g[u]);
                 }
 #pragma unroll
                 for (int u = 0; u < BATCH; u++)
@@ -276,12 +364,10 @@ __global__ __launch_bounds__(64) void k_wg_reduce(WgArgs a) {
         }
         consume(count);
     }
-    float *out = a.part + ((size_t)s * a.N + j) * a.N;
+    float *out = a.part + ((size_t)s * a.Nj + j) * a.Ni;
 #pragma unroll
-    for (int p = 0; p < 4; p++) {
-        const int i = i0 + lane + 64 * p;
-        if (i < a.N) out[i] = acc[p];
-    }
+    for (int c = 0; c < 4; c++)
+        if (ib + c < a.Ni) out[ib + c] = acc[c];
 }
 
 // dW[i][j] = sum over segments in order of part[s][j][i], through a 16 x 16 LDS tile
@@ -293,9 +379,9 @@ __global__ __launch_bounds__(256) void k_wg_sum(WgArgs a) {
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int j = j0 + ty, i = i0 + tx;
     float sum = 0.0f;
-    if (j < a.N && i < a.N) {
-        const size_t NN = (size_t)a.N * a.N;
-        const float *p = a.part + (size_t)j * a.N + i;
+    if (j < a.Nj && i < a.Ni) {
+        const size_t NN = (size_t)a.Nj * a.Ni;
+        const float *p = a.part + (size_t)j * a.Ni + i;
         int s = 0;
         for (; s + 8 <= a.S; s += 8) {
             float v[8];
@@ -309,7 +395,7 @@ __global__ __launch_bounds__(256) void k_wg_sum(WgArgs a) {
     t[ty][tx] = sum;
     __syncthreads();
     const int io = i0 + ty, jo = j0 + tx;
-    if (io < a.N && jo < a.N) a.dW[(size_t)io * a.N + jo] = t[tx][ty];
+    if (io < a.Ni && jo < a.Nj) a.dW[(size_t)io * a.Nj + jo] = t[tx][ty];
 }
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -322,65 +408,77 @@ struct Plan {
     size_t sum_bytes, mask_bytes, part_bytes;
 };
 
-Plan plan(int B, int T, int N, int D) {
+Plan plan(int B, int T, int Nj, int Ni, int D) {
     Plan p{};
     const long long TD = T > D ? T - D : 0;
     const long long NC = (TD + CH - 1) / CH;
     const long long Q = (long long)B * NC;
     const long long QG = (Q + GQ - 1) / GQ;
-    const long long NIS = (N + 255) / 256;
+    const long long NIS = (Ni + 255) / 256;
     // segments: about 8192 reduce waves, at most WIN groups each, gridDim.y <= 65535
-    long long S = (8192 + (long long)N * NIS - 1) / ((long long)N * NIS);
+    long long S = (8192 + (long long)Nj * NIS - 1) / ((long long)Nj * NIS);
     if (S > QG) S = QG;
     if (S < (QG + WIN - 1) / WIN) S = (QG + WIN - 1) / WIN;
-    // (grid limits: NIS and S as reduce's y and z, N / 64 as mask's y, N / 16 as sum's)
-    p.ok = N > 0 && Q < (1LL << 30) && NIS <= 65535 && S <= 65535 && 64LL * N * 4 < (1LL << 31) &&
-           (N + 15) / 16 <= 65535;
+    // (grid limits: S and NIS as reduce's y and z, Nj / 64 as mask's y, Nj / 16 as sum's y)
+    p.ok = Nj > 0 && Ni > 0 && Q < (1LL << 30) && NIS <= 65535 && S <= 65535 && 64LL * Nj * 4 < (1LL << 31) &&
+           (Nj + 15) / 16 <= 65535;
     if (!p.ok) return p;
     p.NC = (int)NC; p.Q = (int)Q; p.Q16 = (int)((Q + QC - 1) / QC); p.QG = (int)QG;
     p.QP = QG * GQ;
     p.SG = S > 0 ? (int)((QG + S - 1) / S) : 1;
     p.S = S > 0 ? (int)((QG + p.SG - 1) / p.SG) : 0;
-    p.sum_bytes = a256((size_t)p.Q16 * N * 2);
-    p.mask_bytes = a256((size_t)N * (size_t)p.QP * 8);
-    p.part_bytes = a256((size_t)p.S * N * N * 4);
+    p.sum_bytes = a256((size_t)p.Q16 * Nj * 2);
+    p.mask_bytes = a256((size_t)Nj * (size_t)p.QP * 8);
+    p.part_bytes = a256((size_t)p.S * Nj * Ni * 4);
     return p;
 }
 
 }  // namespace
 
-size_t recurrent_wgrad_event_bytes(int B, int T, int N) {
-    const Plan p = plan(B, T, N, 0);   // D = 0 bounds every D >= 0
+size_t wgrad_event_bytes(int B, int T, int Nj, int Ni) {
+    const Plan p = plan(B, T, Nj, Ni, 0);   // D = 0 bounds every D >= 0
     return p.ok ? 256 + p.sum_bytes + p.mask_bytes + p.part_bytes : 256;
 }
 
-hipError_t launch_recurrent_wgrad_events(int B, int T, int N, int D, int elem, const void *spikes, const float *gI,
-                                         float *dW, void *ws, unsigned long long **count,
-                                         unsigned long long *thr, hipStream_t st) {
+hipError_t launch_wgrad_events(int B, int T, int Nj, int Ni, int D, int elem, const void *spikes, const void *gI,
+                               int gi_mode, float *dW, void *ws, unsigned long long **count, unsigned long long *thr,
+                               hipStream_t st) {
     *count = nullptr;
     *thr = 0;
-    const Plan p = plan(B, T, N, D);
+    const Plan p = plan(B, T, Nj, Ni, D);
     // (naturally aligned elements, and the shape within the index ranges for every D,
     // as the workspace size assumes; otherwise the dense path runs ungated)
-    if (!p.ok || !plan(B, T, N, 0).ok || (reinterpret_cast<uintptr_t>(spikes) & (uintptr_t)(elem - 1)) != 0)
+    // (bfloat16 gI rows are read four values at a time: whole 8-byte groups)
+    if (!p.ok || !plan(B, T, Nj, Ni, 0).ok || (reinterpret_cast<uintptr_t>(spikes) & (uintptr_t)(elem - 1)) != 0 ||
+        (gi_mode == 2 && Ni % 4 != 0))
         return hipSuccess;
     WgArgs a{};
-    a.B = B; a.T = T; a.TD = T > D ? T - D : 0; a.N = N; a.D = D;
+    a.B = B; a.T = T; a.TD = T > D ? T - D : 0; a.Nj = Nj; a.Ni = Ni; a.D = D;
     a.NC = p.NC; a.Q = p.Q; a.Q16 = p.Q16; a.QG = p.QG; a.QP = p.QP; a.SG = p.SG; a.S = p.S;
     a.spikes = spikes;
     a.gI = gI;
     char *w = static_cast<char *>(ws);
     a.E = reinterpret_cast<unsigned long long *>(w);
-    a.thr = (unsigned long long)B * a.TD * (unsigned long long)N / 256;
+    a.thr = (unsigned long long)B * a.TD * (unsigned long long)Nj / 256;
     a.sum16 = reinterpret_cast<uint16_t *>(w + 256);
     a.mask = reinterpret_cast<uint64_t *>(w + 256 + p.sum_bytes);
     a.part = reinterpret_cast<float *>(w + 256 + p.sum_bytes + p.mask_bytes);
     a.dW = dW;
-    hipLaunchKernelGGL(k_wg_zero, dim3(1), dim3(1), 0, st, a.E);
+    const bool vec = (reinterpret_cast<uintptr_t>(spikes) & 3) == 0 && ((size_t)Nj * elem) % 4 == 0;
+    if ((long long)B * a.TD * Nj <= DIRECT) {
+        hipLaunchKernelGGL(k_wg_zero, dim3(1), dim3(1), 0, st, a.E);
+    } else if (elem == 1) {
+        if (vec) hipLaunchKernelGGL((k_wg_sample<1, true>), dim3(1), dim3(1024), 0, st, a);
+        else hipLaunchKernelGGL((k_wg_sample<1, false>), dim3(1), dim3(1024), 0, st, a);
+    } else if (elem == 2) {
+        if (vec) hipLaunchKernelGGL((k_wg_sample<2, true>), dim3(1), dim3(1024), 0, st, a);
+        else hipLaunchKernelGGL((k_wg_sample<2, false>), dim3(1), dim3(1024), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_wg_sample<4, true>), dim3(1), dim3(1024), 0, st, a);
+    }
     if (p.Q > 0) {
-        const bool vec = (reinterpret_cast<uintptr_t>(spikes) & 3) == 0 && ((size_t)N * elem) % 4 == 0;
         const int cpl = vec ? 4 / elem : 1;
-        const dim3 grid((unsigned)p.Q16, (unsigned)((N + 64 * cpl - 1) / (64 * cpl)));
+        const dim3 grid((unsigned)p.Q16, (unsigned)((Nj + 64 * cpl - 1) / (64 * cpl)));
         const dim3 blk(64 * MASK_WAVES);
         if (elem == 1) {
             if (vec) hipLaunchKernelGGL((k_wg_mask<1, true>), grid, blk, 0, st, a);
@@ -391,12 +489,19 @@ hipError_t launch_recurrent_wgrad_events(int B, int T, int N, int D, int elem, c
         } else {
             hipLaunchKernelGGL((k_wg_mask<4, true>), grid, blk, 0, st, a);
         }
-        const dim3 rg((unsigned)N, (unsigned)p.S, (unsigned)((N + 255) / 256));
-        if (elem == 1) hipLaunchKernelGGL(k_wg_reduce<1>, rg, dim3(64), 0, st, a);
-        else if (elem == 2) hipLaunchKernelGGL(k_wg_reduce<2>, rg, dim3(64), 0, st, a);
-        else hipLaunchKernelGGL(k_wg_reduce<4>, rg, dim3(64), 0, st, a);
+        const dim3 rg((unsigned)Nj, (unsigned)p.S, (unsigned)((Ni + 255) / 256));
+#define ALIF_WGR(E)                                                                          \
+    do {                                                                                     \
+        if (gi_mode == 2) hipLaunchKernelGGL((k_wg_reduce<E, 2>), rg, dim3(64), 0, st, a);  \
+        else if (gi_mode == 1) hipLaunchKernelGGL((k_wg_reduce<E, 1>), rg, dim3(64), 0, st, a); \
+        else hipLaunchKernelGGL((k_wg_reduce<E, 0>), rg, dim3(64), 0, st, a);              \
+    } while (0)
+        if (elem == 1) ALIF_WGR(1);
+        else if (elem == 2) ALIF_WGR(2);
+        else ALIF_WGR(4);
+#undef ALIF_WGR
     }
-    hipLaunchKernelGGL(k_wg_sum, dim3((unsigned)((N + 15) / 16), (unsigned)((N + 15) / 16)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_wg_sum, dim3((unsigned)((Ni + 15) / 16), (unsigned)((Nj + 15) / 16)), dim3(256), 0, st, a);
     *count = a.E;
     *thr = a.thr;
     return hipGetLastError();

@@ -171,6 +171,56 @@ def test_bf16_layer_gemms_with_weight_copies(kind, shape):
         assert np.array_equal(np_(out16[k]).view(np.uint32), np_(out[k]).view(np.uint32)), k
 
 
+# (input kind, GEMM precision, B, T, n_in, N): sparse spike input for the event-driven
+# weight gradient: odd input widths (element loads), a 20-neuron layer, several
+# gradient slices of 256 neurons, several segments of chunks
+_SPARSE_W = [("u8", 0, 2, 1501, 301, 67), ("u8", 1, 2, 1501, 256, 264), ("bf16", 1, 3, 900, 130, 20),
+             ("bf16", 0, 2, 700, 64, 600), ("u8", 1, 4, 6000, 1024, 96)]
+
+
+@pytest.mark.parametrize("kind,prec,B,T,n_in,N", _SPARSE_W)
+def test_sparse_input_weight_grad_from_events(kind, prec, B, T, n_in, N):
+    """Spike input with at most one active input per 256 entries: alif_backward's
+    grad_W is summed over the active inputs (the device-side count gates the dense
+    GEMM off). Against the oracle's product of the same operands (gI rounded to
+    bfloat16 under BF16 GEMMs) within the element-wise FP32 bound of a fixed-order
+    sum, (2 n_j + 4) 2^-24 sum |gI| |x| (n_j active entries of input j); the same
+    bits again on a second call, and (a multiple of 8 neurons, BF16) without a float
+    grad_current."""
+    import torch
+    from paper_2311_11390_amd import alif
+    g = rng(9100 + n_in + N + T)
+    x = np.where(g.random((B, T, n_in)) < 0.002, g.choice(np.array([1, 1, 1, 2], np.uint8), size=(B, T, n_in)), 0)
+    x = x.astype(np.uint8)
+    assert 0 < np.count_nonzero(x) <= B * T * n_in // 256
+    W = normal_weights(g, N, n_in) * 8.0
+    prm = random_params(n_in + N, N, bias=(1.0, 2.0))
+    log(f"[sparse dW] {kind} prec={prec} B={B} T={T} n_in={n_in} N={N}: {np.count_nonzero(x)} active")
+    xt = _as_torch_spikes(x, kind)
+    Wt = torch.as_tensor(W, device="cuda")
+    P = to_dev(prm)
+    f = alif.forward(xt, P, 0.5, 2.0, Wt, gemm_precision=prec, save=True)
+    gS = torch.as_tensor(g.standard_normal((B, T, N)).astype(np.float32), device="cuda")
+    out = alif.backward(f, xt, P, Wt, grad_spikes=gS, want_grad_current=True, want_grad_W=True)
+    again = alif.backward(f, xt, P, Wt, grad_spikes=gS, want_grad_current=True, want_grad_W=True)
+    torch.cuda.synchronize()
+    gI = np_(out["grad_current"])
+    gr = _bf16_round(gI) if prec == 1 else gI.astype(np.float64)
+    xf = x.reshape(-1, n_in).astype(np.float64)
+    ref = oracle.weight_grad(gr, x)
+    n_j = np.count_nonzero(xf, axis=0).astype(np.float64)
+    bound = (2.0 * n_j[None, :] + 4.0) * 2.0 ** -24 * (np.abs(gr.reshape(-1, N)).T @ np.abs(xf)) + 1e-30
+    err = np.abs(np_(out["grad_W"]).astype(np.float64) - ref)
+    log(f"    grad_W: max |err| {err.max():.2e}, worst err / bound {float((err / bound).max()):.3f}")
+    assert (err <= bound).all(), float((err / bound).max())
+    assert np.array_equal(np_(out["grad_W"]).view(np.uint32), np_(again["grad_W"]).view(np.uint32))
+    if prec == 1 and N % 8 == 0:
+        b16 = alif.backward(f, xt, P, Wt, grad_spikes=gS, want_grad_W=True)
+        torch.cuda.synchronize()
+        assert b16["grad_current"] is None
+        assert np.array_equal(np_(out["grad_W"]).view(np.uint32), np_(b16["grad_W"]).view(np.uint32))
+
+
 @pytest.mark.parametrize("shape", [(1, 530, 96, 300), (3, 211, 256, 260), (1, 257, 72, 1024)])
 def test_bf16_gemm_ragged_tiles_write_only_their_output(shape):
     """A BF16 input-current GEMM whose last row and column tiles are ragged, into an

@@ -10,7 +10,9 @@ tensors, through the C ABI, against the oracle's FP64 product:
 * many nonzero spikes: the dense GEMM path, to the GEMM tolerance.
 
 The device-side event count (the first word of the workspace) must equal the
-number of nonzero spikes in the source steps t < T - D, which pins the masks.
+number of nonzero spikes in the source steps t < T - D, which pins the masks;
+on dense input a sampling pass may skip the count (the word is then all ones)
+and the dense path runs either way.
 Spike values other than 0/1 (u8 2 and 3, signed floats, -0.0 as no event), u8,
 bfloat16 and float spikes, odd widths (element loads) and widths whose rows are
 whole dwords, two 256-row slices of i, several segments and groups, a group
@@ -29,6 +31,7 @@ from paper_2311_11390_amd.synth import rng
 pytestmark = pytest.mark.gpu
 
 _DT = {"u8": 0, "bf16": 1, "f32": 2}
+_SKIPPED = 2 ** 64 - 1   # the count word when the sampling pass found a dense input
 
 
 def _spikes(g, B, T, N, p, kind):
@@ -167,7 +170,7 @@ def test_dense_path_matches_oracle(kind, B, T, N, D, p, prec):
     assert E > B * (T - D) * N // 256   # the case is meant for the dense path
     log(f"[wgrad] dense {kind} B={B} T={T} N={N} D={D} prec={prec}: {E} events")
     got, count, _ = _run(S, gI, D, kind, prec=prec)
-    assert count == E
+    assert count in (E, _SKIPPED)
     check_grad("grad_W_rec", got, _reference(gI, S, D), tol=1e-4 if prec == 0 else 1e-2)
 
 
@@ -180,7 +183,7 @@ def test_no_source_steps():
         gI = g.standard_normal((B, T, N)).astype(np.float32)
         log(f"[wgrad] short B={B} T={T} N={N} D={D}")
         got, count, _ = _run(S, gI, D, "u8")
-        assert count == _events(S, D)
+        assert count in (_events(S, D), _SKIPPED)
         if T <= D:
             assert not got.any()
         else:
