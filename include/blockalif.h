@@ -288,7 +288,12 @@ int alif_forward(const alif_desc *desc, const alif_params *prm,
  *            GEMMs
  *   grad_input    spike input only: device float [B][T][n_in] = grad_current W;
  *            nullable. (For current input the gradient is grad_current.)
- *   grad_W        device float [N][n_in] = sum_{b,t} grad_current^T x; nullable
+ *   grad_W        device float [N][n_in] = sum_{b,t} grad_current^T x; nullable.
+ *            With at most one nonzero per 256 entries of x (counted on the
+ *            device, after a sampled estimate on inputs above 2^24 entries) it is
+ *            summed over the nonzero entries (FP32, fixed order; grad_current
+ *            rounded to bfloat16 under BF16 GEMMs), else it is the GEMM of
+ *            desc->gemm_precision; deterministic either way
  *   grad_bias, grad_tau_mem, grad_tau_adapt, grad_d, grad_theta0
  *            device float [N], summed over the batch; each nullable
  *   workspace device scratch of alif_backward_workspace_bytes() bytes (with
