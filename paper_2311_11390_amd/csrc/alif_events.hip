@@ -23,6 +23,7 @@
 #include <cstdint>
 
 #include "../../include/blockalif.h"
+#include "alif_gemm.h"
 #include "alif_kernels.h"
 
 namespace alif {
@@ -62,7 +63,9 @@ template <int KIND, int CT, bool WORDS>
 __global__ __launch_bounds__(64 * EV_WAVES) void k_events_current(long long M, int n_in, int N, const void *x,
                                                                    const float *__restrict__ WT,
                                                                    const float *__restrict__ bias,
-                                                                   float *__restrict__ C) {
+                                                                   float *__restrict__ C,
+                                                                   const unsigned long long *gate) {
+    if (gate && *gate != 0ull) return;   // the caller's dense product runs instead
     constexpr int ES = ev_elem_bytes<KIND>();
     constexpr int EPW = WORDS ? 4 / ES : 1;          // elements per unit
     const int lane = threadIdx.x & 63;
@@ -140,32 +143,40 @@ __global__ __launch_bounds__(64 * EV_WAVES) void k_events_current(long long M, i
 
 template <int KIND, int CT>
 void launch_events_ct(bool words, long long M, hipStream_t st, int n_in, int N, const void *x, const float *WT,
-                      const float *bias, float *C) {
+                      const float *bias, float *C, const unsigned long long *gate) {
     const long long groups = (M + EV_WAVES - 1) / EV_WAVES;
     const dim3 grid((unsigned)(groups < EV_MAX_GROUPS ? groups : EV_MAX_GROUPS)), blk(64 * EV_WAVES);
     if (words)
-        hipLaunchKernelGGL((k_events_current<KIND, CT, true>), grid, blk, 0, st, M, n_in, N, x, WT, bias, C);
+        hipLaunchKernelGGL((k_events_current<KIND, CT, true>), grid, blk, 0, st, M, n_in, N, x, WT, bias, C, gate);
     else
-        hipLaunchKernelGGL((k_events_current<KIND, CT, false>), grid, blk, 0, st, M, n_in, N, x, WT, bias, C);
+        hipLaunchKernelGGL((k_events_current<KIND, CT, false>), grid, blk, 0, st, M, n_in, N, x, WT, bias, C, gate);
 }
 
 template <int KIND>
 void launch_events(int ct, long long M, hipStream_t st, int n_in, int N, const void *x, const float *WT,
-                   const float *bias, float *C) {
+                   const float *bias, float *C, const unsigned long long *gate = nullptr) {
     // word loads need every row to start on a 4-byte boundary
     const bool words = ((size_t)n_in * ev_elem_bytes<KIND>()) % 4 == 0 && ((uintptr_t)x & 3u) == 0;
     switch (ct) {
-        case 1: launch_events_ct<KIND, 1>(words, M, st, n_in, N, x, WT, bias, C); break;
-        case 2: launch_events_ct<KIND, 2>(words, M, st, n_in, N, x, WT, bias, C); break;
-        case 4: launch_events_ct<KIND, 4>(words, M, st, n_in, N, x, WT, bias, C); break;
-        case 8: launch_events_ct<KIND, 8>(words, M, st, n_in, N, x, WT, bias, C); break;
-        default: launch_events_ct<KIND, 16>(words, M, st, n_in, N, x, WT, bias, C);
+        case 1: launch_events_ct<KIND, 1>(words, M, st, n_in, N, x, WT, bias, C, gate); break;
+        case 2: launch_events_ct<KIND, 2>(words, M, st, n_in, N, x, WT, bias, C, gate); break;
+        case 4: launch_events_ct<KIND, 4>(words, M, st, n_in, N, x, WT, bias, C, gate); break;
+        case 8: launch_events_ct<KIND, 8>(words, M, st, n_in, N, x, WT, bias, C, gate); break;
+        default: launch_events_ct<KIND, 16>(words, M, st, n_in, N, x, WT, bias, C, gate);
     }
 }
 
-// out[c][r] = in[r][c] for a rows x cols matrix, through 32 x 32 LDS tiles
+// column tile: the smallest 64 CT (CT = 1, 2, 4, 8, 16) that covers N, else 1024 columns per pass
+int column_tile(int N) {
+    for (int c = 1; c < 16; c *= 2)
+        if (64 * c >= N) return c;
+    return 16;
+}
+
+// out[c][r] = in[r][c] for a rows x cols matrix, through 32 x 32 LDS tiles (with
+// round_bf16, each value rounded to the nearest bfloat16, kept as float)
 __global__ __launch_bounds__(256) void k_transpose_rect(int rows, int cols, const float *__restrict__ in,
-                                                        float *__restrict__ out) {
+                                                        float *__restrict__ out, int round_bf16) {
     __shared__ float tile[32][33];
     const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
@@ -176,11 +187,32 @@ __global__ __launch_bounds__(256) void k_transpose_rect(int rows, int cols, cons
     __syncthreads();
     for (int k = ty; k < 32; k += 8) {
         const int c = c0 + k, r = r0 + tx;
-        if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][k];
+        if (r < rows && c < cols) {
+            const float v = tile[tx][k];
+            out[(size_t)c * rows + r] = round_bf16 ? (float)(__bf16)v : v;
+        }
     }
 }
 
 }  // namespace
+
+bool events_current_launch(int kind, long long M, int n_in, int N, const void *x, const float *W, float *WT,
+                           bool round_bf16, const float *bias, float *C, const unsigned long long *gate,
+                           hipStream_t st) {
+    const unsigned esz = kind == ALIF_INPUT_SPIKES_U8 ? 1u : 2u;
+    if ((kind != ALIF_INPUT_SPIKES_U8 && kind != ALIF_INPUT_SPIKES_BF16) || M <= 0 || n_in <= 0 || N <= 0 ||
+        ((uintptr_t)x % esz) != 0 || ((uintptr_t)WT % 4u) != 0 || ((uintptr_t)C % 4u) != 0 ||
+        (bias && ((uintptr_t)bias % 4u) != 0) || (N + 31) / 32 > 65535)
+        return false;
+    const dim3 tg((unsigned)((n_in + 31) / 32), (unsigned)((N + 31) / 32));
+    hipLaunchKernelGGL(k_transpose_rect, tg, dim3(256), 0, st, N, n_in, W, WT, round_bf16 ? 1 : 0);
+    if (kind == ALIF_INPUT_SPIKES_U8)
+        launch_events<ALIF_INPUT_SPIKES_U8>(column_tile(N), M, st, n_in, N, x, WT, bias, C, gate);
+    else
+        launch_events<ALIF_INPUT_SPIKES_BF16>(column_tile(N), M, st, n_in, N, x, WT, bias, C, gate);
+    return true;
+}
+
 }  // namespace alif
 
 using namespace alif;
@@ -194,7 +226,7 @@ int alif_transpose(int32_t rows, int32_t cols, const float *in, float *out, void
     if (in == out) return alif::set_error(ALIF_EINVAL, "transpose: in and out must not alias");
     const dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)), blk(256);
     if (grid.y > 65535u) return alif::set_error(ALIF_EUNSUPPORTED, "transpose: too many rows");
-    hipLaunchKernelGGL(k_transpose_rect, grid, blk, 0, (hipStream_t)stream, rows, cols, in, out);
+    hipLaunchKernelGGL(k_transpose_rect, grid, blk, 0, (hipStream_t)stream, rows, cols, in, out, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return alif::set_error(ALIF_EHIP, hipGetErrorString(e));
     return ALIF_OK;
@@ -216,13 +248,7 @@ int alif_input_current_events(const alif_desc *desc, const void *input, const fl
     if (((uintptr_t)input % esz) != 0 || ((uintptr_t)WT % 4u) != 0 || ((uintptr_t)current % 4u) != 0 ||
         (bias && ((uintptr_t)bias % 4u) != 0))
         return alif::set_error(ALIF_EINVAL, "event current: buffer not aligned to its element type");
-    // column tile: the smallest 64 CT (CT = 1, 2, 4, 8, 16) that covers N, else 1024 columns per pass
-    int ct = 16;
-    for (int c = 1; c < 16; c *= 2)
-        if (64 * c >= N) {
-            ct = c;
-            break;
-        }
+    const int ct = column_tile(N);
     hipStream_t st = (hipStream_t)stream;
     if (kind == ALIF_INPUT_SPIKES_U8)
         launch_events<ALIF_INPUT_SPIKES_U8>(ct, M, st, n_in, N, input, WT, bias, current);

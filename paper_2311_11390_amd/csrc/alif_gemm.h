@@ -37,6 +37,20 @@ hipError_t gemm_input_grad(size_t M, int N, int K, const void *gI, const float *
 // scratch bytes gemm_weight_grad needs for its split partial sums
 size_t gemm_workspace_bytes(size_t M, int N, int K);
 
+// Sparse spike input (alif_events.hip, alif_recurrent_wgrad.hip):
+// density_flag_launch writes *flag = 0 when a fixed sample of whole rows of x
+// ([rows][cols] of elem-byte elements) has at most cut_num / cut_den nonzero
+// entries, else ~0 (one workgroup). events_current_launch writes W [N][n_in]
+// transposed into WT (n_in x N floats; values rounded to bfloat16 with
+// round_bf16) and then C = bias + x W^T from the active inputs only, its kernel
+// returning at entry unless *gate == 0; false (nothing launched) for shapes or
+// alignments it does not take.
+hipError_t density_flag_launch(long long rows, int cols, int elem, const void *x, unsigned long long *flag,
+                               int cut_num, int cut_den, hipStream_t st);
+bool events_current_launch(int kind, long long M, int n_in, int N, const void *x, const float *W, float *WT,
+                           bool round_bf16, const float *bias, float *C, const unsigned long long *gate,
+                           hipStream_t st);
+
 // general C[M][N] = sum_k A(m, k) B(n, k) (+ bias[n]) for tests and readout
 struct GemmArgs {
     long long M;

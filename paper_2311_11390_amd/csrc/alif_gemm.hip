@@ -651,6 +651,14 @@ static bool scratch_fits(const void *scratch, size_t bytes, int N, int K) {
     return scratch && bytes >= gemm_wbf16_bytes(N, K) && (reinterpret_cast<uintptr_t>(scratch) & 15) == 0;
 }
 
+// Sparse spike input: at most one nonzero per EV_CUT entries (estimated on the device
+// from a sample of rows) takes the current from the active inputs alone (FP32 sums of
+// exact products; under BF16 GEMMs of W rounded to bfloat16, the GEMM's rounding of
+// it); the GEMM is enqueued behind it with the opposite gate. Only for inputs of more
+// than EV_MIN entries, where the sample (10 us) is small against either product.
+constexpr int EV_CUT = 64;
+constexpr double EV_MIN = 16777216.0;
+
 hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, const float *bias,
                               float *out, bool bf16, hipStream_t st, void *scratch, size_t scratch_bytes) {
     GemmArgs g{};
@@ -658,6 +666,24 @@ hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, 
     g.A = x.ptr; g.a_dt = dt_of(x.kind); g.lda = K; g.a_kc = 1;
     g.B = W; g.b_dt = 0; g.ldb = K; g.b_kc = 1;
     g.C = out; g.ldc = N; g.bias = bias; g.splits = 1;
+    const bool spk = x.kind == ALIF_INPUT_SPIKES_U8 || x.kind == ALIF_INPUT_SPIKES_BF16;
+    const size_t wt_bytes = ((size_t)K * N * 4 + 255) & ~(size_t)255;
+    if (spk && M > 0 && N > 0 && K > 0 && M < ((size_t)1 << 31) && (double)M * K > EV_MIN && scratch &&
+        (reinterpret_cast<uintptr_t>(scratch) & 255) == 0 && scratch_bytes >= 256 + wt_bytes + gemm_wbf16_bytes(N, K)) {
+        // scratch: the gate word, W transposed, then the GEMM's bfloat16 copy of W
+        unsigned long long *flag = static_cast<unsigned long long *>(scratch);
+        float *WT = reinterpret_cast<float *>(static_cast<char *>(scratch) + 256);
+        const int elem = x.kind == ALIF_INPUT_SPIKES_U8 ? 1 : 2;
+        if (density_flag_launch((long long)M, K, elem, x.ptr, flag, 1, EV_CUT, st) == hipSuccess &&
+            events_current_launch(x.kind, (long long)M, K, N, x.ptr, W, WT, bf16, bias, out, flag, st)) {
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            g.skip_cnt = flag;   // the GEMM returns at entry when *flag == 0 (the event path ran)
+            g.skip_le = 0;
+            scratch = static_cast<char *>(scratch) + 256 + wt_bytes;
+            scratch_bytes -= 256 + wt_bytes;
+        }
+    }
     if (bf16 && M > 0 && N > 0 && scratch_fits(scratch, scratch_bytes, N, K)) {
         GemmArgs h = g;
         h.B = scratch; h.b_dt = 2; h.ldb = ld16(K);

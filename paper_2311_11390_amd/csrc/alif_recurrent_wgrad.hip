@@ -28,6 +28,7 @@
 #include <cstdint>
 
 #include "alif_common.h"
+#include "alif_gemm.h"
 #include "alif_kernels.h"
 
 namespace alif {
@@ -51,6 +52,7 @@ struct WgArgs {
     int QG;        // groups, ceil(Q / GQ)
     long long QP;  // mask row length in chunks, QG GQ
     int SG, S;     // groups a segment, segments
+    int cut_num, cut_den;   // the sampling pass turns the count off above this density
     const void *spikes;
     const void *gI;          // [B][T][Ni] float or bfloat16
     unsigned long long *E;   // event count
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(1024) void k_wg_sample(WgArgs a) {
     if (threadIdx.x == 0) {
         long long tot = 0;
         for (int w = 0; w < 16; w++) tot += part[w];
-        *a.E = tot * 256 * 10 <= 11LL * taken * a.Nj ? 0ull : SKIP;
+        *a.E = tot * a.cut_den <= (long long)a.cut_num * taken * a.Nj ? 0ull : SKIP;
     }
 }
 
@@ -460,6 +462,8 @@ hipError_t launch_wgrad_events(int B, int T, int Nj, int Ni, int D, int elem, co
     char *w = static_cast<char *>(ws);
     a.E = reinterpret_cast<unsigned long long *>(w);
     a.thr = (unsigned long long)B * a.TD * (unsigned long long)Nj / 256;
+    a.cut_num = 11;
+    a.cut_den = 2560;
     a.sum16 = reinterpret_cast<uint16_t *>(w + 256);
     a.mask = reinterpret_cast<uint64_t *>(w + 256 + p.sum_bytes);
     a.part = reinterpret_cast<float *>(w + 256 + p.sum_bytes + p.mask_bytes);
@@ -504,6 +508,30 @@ hipError_t launch_wgrad_events(int B, int T, int Nj, int Ni, int D, int elem, co
     hipLaunchKernelGGL(k_wg_sum, dim3((unsigned)((Ni + 15) / 16), (unsigned)((Nj + 15) / 16)), dim3(256), 0, st, a);
     *count = a.E;
     *thr = a.thr;
+    return hipGetLastError();
+}
+
+hipError_t density_flag_launch(long long rows, int cols, int elem, const void *x, unsigned long long *flag,
+                               int cut_num, int cut_den, hipStream_t st) {
+    if (rows <= 0 || rows >= (1LL << 31) || cols <= 0 || (elem != 1 && elem != 2 && elem != 4) ||
+        (reinterpret_cast<uintptr_t>(x) & (uintptr_t)(elem - 1)) != 0)
+        return hipErrorInvalidValue;
+    WgArgs a{};
+    a.B = 1; a.T = (int)rows; a.TD = (int)rows; a.Nj = cols;
+    a.spikes = x;
+    a.E = flag;
+    a.cut_num = cut_num;
+    a.cut_den = cut_den;
+    const bool vec = (reinterpret_cast<uintptr_t>(x) & 3) == 0 && ((size_t)cols * elem) % 4 == 0;
+    if (elem == 1) {
+        if (vec) hipLaunchKernelGGL((k_wg_sample<1, true>), dim3(1), dim3(1024), 0, st, a);
+        else hipLaunchKernelGGL((k_wg_sample<1, false>), dim3(1), dim3(1024), 0, st, a);
+    } else if (elem == 2) {
+        if (vec) hipLaunchKernelGGL((k_wg_sample<2, true>), dim3(1), dim3(1024), 0, st, a);
+        else hipLaunchKernelGGL((k_wg_sample<2, false>), dim3(1), dim3(1024), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_wg_sample<4, true>), dim3(1), dim3(1024), 0, st, a);
+    }
     return hipGetLastError();
 }
 

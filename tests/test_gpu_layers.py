@@ -171,6 +171,42 @@ def test_bf16_layer_gemms_with_weight_copies(kind, shape):
         assert np.array_equal(np_(out16[k]).view(np.uint32), np_(out[k]).view(np.uint32)), k
 
 
+# (input kind, GEMM precision, spike probability): inputs of more than 2^24 entries,
+# where alif_forward estimates the density from a sample of rows and takes the current
+# from the active inputs at most one in 64 active, else from the GEMM
+_BIG_CUR = [("u8", 1, 0.002), ("bf16", 0, 0.002), ("u8", 1, 0.05), ("u8", 0, 0.05), ("bf16", 1, 0.01)]
+
+
+@pytest.mark.parametrize("kind,prec,p", _BIG_CUR)
+def test_big_spike_input_current_both_paths(kind, prec, p):
+    """alif_forward's input current for 2 x 9000 x 1024 spike inputs (18.9 M entries)
+    at densities on both sides of the event path's cut: against the oracle's FP64
+    projection of the same operands (W rounded to bfloat16 under BF16 GEMMs) within
+    the FP32 accumulation bound, and the layer's spikes equal those of the same layer
+    fed the checked current."""
+    import torch
+    from paper_2311_11390_amd import alif
+    B, T, n_in, N = 2, 9000, 1024, 64
+    g = rng(int(9300 + 1000 * p) + prec)
+    x = bernoulli_spikes(g, (B, T, n_in), p)
+    W = normal_weights(g, N, n_in) * 4.0
+    prm = random_params(9301, N, bias=(0.5, 1.5))
+    log(f"[big current] {kind} prec={prec} p={p}")
+    xt = _as_torch_spikes(x, kind)
+    P = to_dev(prm)
+    f = alif.forward(xt, P, 0.5, 2.0, torch.as_tensor(W, device="cuda"), gemm_precision=prec, save=True)
+    torch.cuda.synchronize()
+    Wr = _bf16_round(W) if prec == 1 else W.astype(np.float64)
+    ref = oracle.input_current(x, Wr, prm.bias)
+    bound = _gemm_bound(x.reshape(-1, n_in).astype(np.float64), np.abs(Wr).T, n_in).reshape(ref.shape) \
+        + 2.0 ** -24 * np.abs(ref)
+    err = np.abs(np_(f["current"]) - ref)
+    assert (err <= bound).all(), float((err / bound).max())
+    f2 = alif.forward(f["current"].contiguous(), alif.Params(P.tau_mem, P.tau_adapt, P.d, P.theta0), 0.5, 2.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(np_(f2["spikes"]), np_(f["spikes"]))
+
+
 # (input kind, GEMM precision, B, T, n_in, N): sparse spike input for the event-driven
 # weight gradient: odd input widths (element loads), a 20-neuron layer, several
 # gradient slices of 256 neurons, several segments of chunks
