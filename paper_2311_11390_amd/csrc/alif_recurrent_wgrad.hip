@@ -5,7 +5,9 @@
 // Ni neurons i). A neuron fires at most once per T_R steps (Prop. 3), and at the
 // rates of a fitted network almost every spike row is zero: a dense GEMM spends
 // Ni Nj multiply-adds on each of the R = B (T - D) source rows for a handful of
-// events. Three kernels:
+// events. Four kernels:
+//   sample  (inputs above 2^24 entries) estimates the density from whole rows and
+//           turns the rest off when the input is dense, else E starts at 0.
 //   mask    reads S once: for chunk q = b NC + k (64 steps of one sequence, NC
 //           chunks a sequence) and column j, the bit mask of its nonzero steps
 //           (u64, bit r for step 64 k + r), stored only when nonzero, and one
@@ -22,7 +24,8 @@
 // sum return at entry and the dense GEMM (after the time shift for D > 0),
 // enqueued behind them with the same device-side test on E, runs instead.
 // gI is float, float rounded to bfloat16 as it is loaded (the operand of a BF16
-// GEMM), or bfloat16.
+// GEMM), or bfloat16. The sample kernel also gives the forward's choice between
+// the event-driven input current and the GEMM (density_flag_launch).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
