@@ -174,23 +174,26 @@ def test_bf16_layer_gemms_with_weight_copies(kind, shape):
 # (input kind, GEMM precision, spike probability): inputs of more than 2^24 entries,
 # where alif_forward estimates the density from a sample of rows and takes the current
 # from the active inputs at most one in 64 active, else from the GEMM
-_BIG_CUR = [("u8", 1, 0.002), ("bf16", 0, 0.002), ("u8", 1, 0.05), ("u8", 0, 0.05), ("bf16", 1, 0.01)]
+# (input kind, GEMM precision, spike probability, neurons, bias)
+_BIG_CUR = [("u8", 1, 0.002, 64, True), ("bf16", 0, 0.002, 64, True), ("u8", 1, 0.05, 64, True),
+            ("u8", 0, 0.05, 64, True), ("bf16", 1, 0.01, 64, True), ("u8", 1, 0.003, 100, False)]
 
 
-@pytest.mark.parametrize("kind,prec,p", _BIG_CUR)
-def test_big_spike_input_current_both_paths(kind, prec, p):
+@pytest.mark.parametrize("kind,prec,p,N,bias", _BIG_CUR)
+def test_big_spike_input_current_both_paths(kind, prec, p, N, bias):
     """alif_forward's input current for 2 x 9000 x 1024 spike inputs (18.9 M entries)
-    at densities on both sides of the event path's cut: against the oracle's FP64
-    projection of the same operands (W rounded to bfloat16 under BF16 GEMMs) within
-    the FP32 accumulation bound, and the layer's spikes equal those of the same layer
-    fed the checked current."""
+    at densities on both sides of the event path's cut (and a ragged column tile of
+    100 neurons without bias): against the oracle's FP64 projection of the same
+    operands (W rounded to bfloat16 under BF16 GEMMs) within the FP32 accumulation
+    bound, and the layer's spikes equal those of the same layer fed the checked
+    current."""
     import torch
     from paper_2311_11390_amd import alif
-    B, T, n_in, N = 2, 9000, 1024, 64
-    g = rng(int(9300 + 1000 * p) + prec)
+    B, T, n_in = 2, 9000, 1024
+    g = rng(int(9300 + 1000 * p) + prec + N)
     x = bernoulli_spikes(g, (B, T, n_in), p)
     W = normal_weights(g, N, n_in) * 4.0
-    prm = random_params(9301, N, bias=(0.5, 1.5))
+    prm = random_params(9301, N, bias=(0.5, 1.5) if bias else None)
     log(f"[big current] {kind} prec={prec} p={p}")
     xt = _as_torch_spikes(x, kind)
     P = to_dev(prm)
