@@ -251,8 +251,9 @@ int alif_input_grad(const alif_desc *desc, const float *grad_current, const floa
  *   current  device float [B][T][N] workspace receiving b + W x for spike input
  *            (keep it for alif_backward); must be NULL for current input. It is
  *            the GEMM of desc->gemm_precision, or, for inputs of more than 2^24
- *            entries that a device-side sample of rows puts at most one in 64
- *            nonzero, the sum over the nonzero inputs in FP32 (W rounded to
+ *            entries that a device-side sample of rows puts at most one in 16
+ *            (FP32 GEMMs), one in 64 (BF16, N >= 256) or one in 256 (BF16, smaller
+ *            N) nonzero, the sum over the nonzero inputs in FP32 (W rounded to
  *            bfloat16 under BF16 GEMMs, as the GEMM rounds it), computed in
  *            `spikes` as scratch before the block kernel writes it
  *   init     initial state or NULL (= zeros, no earlier spike)

@@ -651,13 +651,17 @@ static bool scratch_fits(const void *scratch, size_t bytes, int N, int K) {
     return scratch && bytes >= gemm_wbf16_bytes(N, K) && (reinterpret_cast<uintptr_t>(scratch) & 15) == 0;
 }
 
-// Sparse spike input: at most one nonzero per EV_CUT entries (estimated on the device
-// from a sample of rows) takes the current from the active inputs alone (FP32 sums of
-// exact products; under BF16 GEMMs of W rounded to bfloat16, the GEMM's rounding of
-// it); the GEMM is enqueued behind it with the opposite gate. Only for inputs of more
-// than EV_MIN entries, where the sample (10 us) is small against either product.
-constexpr int EV_CUT = 64;
+// Sparse spike input: a density (estimated on the device from a sample of rows) of at
+// most one nonzero per ev_cut entries takes the current from the active inputs alone
+// (FP32 sums of exact products; under BF16 GEMMs of W rounded to bfloat16, the GEMM's
+// rounding of it); the GEMM is enqueued behind it with the opposite gate. Only for
+// inputs of more than EV_MIN entries, where the sample (10 us) is small against either
+// product. The cuts come from timing both on MI355X with a cold MALL: against the FP32
+// GEMM the event kernel was 2-8x faster up to 5% active (K 700, N 512 and 1024);
+// against the BF16 GEMM it won up to 1% at N = 1024 (0.50 against 0.61 ms) and lost at
+// 2% (0.73 ms), and with N = 20 it won at 0.19% and lost at 2%.
 constexpr double EV_MIN = 16777216.0;
+static int ev_cut(bool bf16, int N) { return bf16 ? (N >= 256 ? 64 : 256) : 16; }
 
 hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, const float *bias,
                               float *out, bool bf16, hipStream_t st, void *scratch, size_t scratch_bytes) {
@@ -674,7 +678,7 @@ hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, 
         unsigned long long *flag = static_cast<unsigned long long *>(scratch);
         float *WT = reinterpret_cast<float *>(static_cast<char *>(scratch) + 256);
         const int elem = x.kind == ALIF_INPUT_SPIKES_U8 ? 1 : 2;
-        if (density_flag_launch((long long)M, K, elem, x.ptr, flag, 1, EV_CUT, st) == hipSuccess &&
+        if (density_flag_launch((long long)M, K, elem, x.ptr, flag, 1, ev_cut(bf16, N), st) == hipSuccess &&
             events_current_launch(x.kind, (long long)M, K, N, x.ptr, W, WT, bf16, bias, out, flag, st)) {
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;

@@ -174,15 +174,17 @@ def test_bf16_layer_gemms_with_weight_copies(kind, shape):
 # (input kind, GEMM precision, spike probability): inputs of more than 2^24 entries,
 # where alif_forward estimates the density from a sample of rows and takes the current
 # from the active inputs at most one in 64 active, else from the GEMM
-# (input kind, GEMM precision, spike probability, neurons, bias)
+# (input kind, GEMM precision, spike probability, neurons, bias); the cut is one active
+# input in 16 for FP32 GEMMs, in 64 for BF16 GEMMs of 256 or more neurons, else in 256
 _BIG_CUR = [("u8", 1, 0.002, 64, True), ("bf16", 0, 0.002, 64, True), ("u8", 1, 0.05, 64, True),
-            ("u8", 0, 0.05, 64, True), ("bf16", 1, 0.01, 64, True), ("u8", 1, 0.003, 100, False)]
+            ("u8", 0, 0.05, 64, True), ("u8", 0, 0.15, 64, True), ("bf16", 1, 0.01, 64, True),
+            ("u8", 1, 0.003, 100, False), ("u8", 1, 0.01, 256, True)]
 
 
 @pytest.mark.parametrize("kind,prec,p,N,bias", _BIG_CUR)
 def test_big_spike_input_current_both_paths(kind, prec, p, N, bias):
     """alif_forward's input current for 2 x 9000 x 1024 spike inputs (18.9 M entries)
-    at densities on both sides of the event path's cut (and a ragged column tile of
+    at densities on both sides of the event path's cuts (and a ragged column tile of
     100 neurons without bias): against the oracle's FP64 projection of the same
     operands (W rounded to bfloat16 under BF16 GEMMs) within the FP32 accumulation
     bound, and the layer's spikes equal those of the same layer fed the checked
