@@ -673,7 +673,8 @@ hipError_t gemm_input_current(size_t M, int N, int K, GemmIn x, const float *W, 
     const bool spk = x.kind == ALIF_INPUT_SPIKES_U8 || x.kind == ALIF_INPUT_SPIKES_BF16;
     const size_t wt_bytes = ((size_t)K * N * 4 + 255) & ~(size_t)255;
     if (spk && M > 0 && N > 0 && K > 0 && M < ((size_t)1 << 31) && (double)M * K > EV_MIN && scratch &&
-        (reinterpret_cast<uintptr_t>(scratch) & 255) == 0 && scratch_bytes >= 256 + wt_bytes + gemm_wbf16_bytes(N, K)) {
+        (reinterpret_cast<uintptr_t>(scratch) & 255) == 0 &&
+        scratch_bytes >= 256 + wt_bytes + gemm_wbf16_bytes(N, K)) {
         // scratch: the gate word, W transposed, then the GEMM's bfloat16 copy of W
         unsigned long long *flag = static_cast<unsigned long long *>(scratch);
         float *WT = reinterpret_cast<float *>(static_cast<char *>(scratch) + 256);
